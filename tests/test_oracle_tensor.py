@@ -1,0 +1,223 @@
+"""Pins of the oracle's analytical cuboid tensor against what physics and
+mathematics fix independently of its formula (paper Sec. 3: the field of each
+uniformly magnetised tile at the other tiles' centres; Sec. 3.2: the tensor is
+symmetric).
+
+* surface-charge quadrature of a uniformly magnetised box (independent
+  derivation of the same field: H = (1/4pi) sum_faces sigma int (r-r')/|r-r'|^3);
+* closed form at the centre of a cuboid (textbook demagnetising factors);
+* trace 1 inside the tile and 0 outside (Poisson/Laplace for psi);
+* far field of a point dipole;
+* scale invariance, pair symmetry on identical tiles, positive
+  semi-definiteness of the demag energy, superposition of sub-tiles;
+* the cancellation-free logarithms against a 50-digit evaluation of the
+  plain eight-corner sum.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+def quad_tensor(r, c, s, eps=1e-13):
+    """N(r) of the box (centre c, edges s) from the field of its surface
+    charges: for M = e_j the faces normal to j carry sigma = +-1 and
+    H(r) = (1/4pi) sum sigma int (r - r') / |r - r'|^3 dS'; N_ij = -H_i."""
+    r = np.asarray(r, float)
+    c = np.asarray(c, float)
+    h = 0.5 * np.asarray(s, float)
+    N = np.zeros((3, 3))
+    for j in range(3):
+        e1, e2 = (j + 1) % 3, (j + 2) % 3
+        for sign in (+1, -1):
+            xj = c[j] + sign * h[j]
+            for i in range(3):
+                def f(v, u):
+                    rp = np.empty(3)
+                    rp[j], rp[e1], rp[e2] = xj, u, v
+                    d = r - rp
+                    return d[i] / np.dot(d, d) ** 1.5
+
+                val, _ = integrate.dblquad(f, c[e1] - h[e1], c[e1] + h[e1], c[e2] - h[e2],
+                                           c[e2] + h[e2], epsabs=eps, epsrel=1e-12)
+                N[i, j] -= sign * val / (4 * math.pi)
+    return N
+
+
+@pytest.mark.parametrize("r", [
+    [2.3, 0.9, -1.7],      # exterior, generic
+    [0.1, 0.2, -0.15],     # interior, off-centre
+    [0.6, 0.3, 0.2],       # exterior, close to a face
+    [0.5, 3.0, 0.2],       # in the plane of the x face, outside it (U = 0)
+    [0.5, 1.0, 2.0],       # on the line of an x-y edge (U = V = 0)
+    [-0.9, -1.4, 0.75],    # in the plane of the upper z face, outside it
+])
+def test_tensor_matches_surface_charge_quadrature(orc, r):
+    c, s = [0.0, 0.0, 0.0], [1.0, 2.0, 1.5]
+    Nq = quad_tensor(r, c, s)
+    No = orc.prism_tensor(r, c, s)
+    assert np.abs(Nq - No).max() < 1e-12, (Nq, No)
+
+
+def test_tensor_quadrature_shifted_box(orc):
+    # the box does not sit at the origin and the point is off every axis
+    c, s = [3.0, -2.0, 1.0], [0.7, 1.3, 0.4]
+    r = [4.1, -1.2, 0.35]
+    assert np.abs(quad_tensor(r, c, s) - orc.prism_tensor(r, c, s)).max() < 1e-12
+
+
+def test_cube_centre_is_one_third(orc):
+    N = orc.prism_tensor([0, 0, 0], [0, 0, 0], [5e-9, 5e-9, 5e-9])
+    assert np.abs(N - np.eye(3) / 3).max() < 1e-15
+
+
+def _centre_factor(a, b, c):
+    # demagnetising factor along the edge of half-length c at the centre of
+    # a cuboid with half-edges (a, b, c): (2/pi) atan(ab / (c sqrt(a^2+b^2+c^2)))
+    return 2.0 / math.pi * math.atan(a * b / (c * math.sqrt(a * a + b * b + c * c)))
+
+
+@pytest.mark.parametrize("edges", [[1, 1, 1], [5, 5, 3], [10, 2, 1], [1, 7, 30], [3, 3, 0.1]])
+def test_cuboid_centre_closed_form(orc, edges):
+    a, b, c = (0.5 * np.asarray(edges, float)).tolist()
+    N = orc.prism_tensor([0, 0, 0], [0, 0, 0], edges)
+    want = [_centre_factor(b, c, a), _centre_factor(c, a, b), _centre_factor(a, b, c)]
+    np.testing.assert_allclose(np.diag(N), want, rtol=1e-14, atol=1e-16)
+    assert abs(np.trace(N) - 1.0) < 1e-14
+
+
+def test_trace_inside_and_outside(orc):
+    rng = np.random.default_rng(7)
+    s = np.array([1.0, 2.5, 0.6])
+    for _ in range(50):
+        inside = (rng.random(3) - 0.5) * s * 0.98
+        assert abs(np.trace(orc.prism_tensor(inside, [0, 0, 0], s)) - 1.0) < 1e-14
+        out = (rng.random(3) - 0.5) * 12.0
+        if np.all(np.abs(out) <= 0.5 * s + 1e-3):
+            continue
+        assert abs(np.trace(orc.prism_tensor(out, [0, 0, 0], s))) < 1e-14
+
+
+def _dipole(d, vol):
+    r = np.linalg.norm(d)
+    u = d / r
+    return vol / (4 * math.pi) * (np.eye(3) - 3.0 * np.outer(u, u)) / r**3
+
+
+@pytest.mark.parametrize("ratio,bound", [(5, 6e-3), (20, 2e-5), (100, 3e-8)])
+def test_cube_far_field_is_dipole(orc, ratio, bound):
+    # cube of half-edge 1; the quadrupole vanishes by symmetry, so the
+    # relative deviation falls like (h/d)^4
+    d = np.array([0.8, 0.5, 0.33])
+    d = d / np.linalg.norm(d) * ratio
+    N = orc.prism_tensor(d, [0, 0, 0], [2, 2, 2])
+    D = _dipole(d, 8.0)
+    rel = np.abs(N - D).max() / np.abs(D).max()
+    assert rel < bound
+
+
+def test_cube_far_field_order_four(orc):
+    d0 = np.array([0.8, 0.5, 0.33])
+    d0 /= np.linalg.norm(d0)
+    errs = []
+    for ratio in (10, 20, 40):
+        N = orc.prism_tensor(d0 * ratio, [0, 0, 0], [2, 2, 2])
+        D = _dipole(d0 * ratio, 8.0)
+        errs.append(np.abs(N - D).max() / np.abs(D).max())
+    assert 13.0 < errs[0] / errs[1] < 19.0 and 13.0 < errs[1] / errs[2] < 19.0
+
+
+def test_cuboid_far_field_converges(orc):
+    # non-cubic cuboid: the deviation from the dipole falls like (h/d)^2
+    s = np.array([2.0, 1.0, 0.5])
+    d0 = np.array([0.3, 0.9, 0.4])
+    d0 /= np.linalg.norm(d0)
+    errs = []
+    for ratio in (50, 100, 200):
+        N = orc.prism_tensor(d0 * ratio, [0, 0, 0], s)
+        D = _dipole(d0 * ratio, float(np.prod(s)))
+        errs.append(np.abs(N - D).max() / np.abs(D).max())
+    assert errs[0] < 1e-3
+    assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0
+
+
+def test_scale_invariance(orc):
+    r, c, s = np.array([3.3, -1.2, 0.4]), np.array([0.1, 0.2, 0.3]), np.array([1.0, 0.5, 2.0])
+    N1 = orc.prism_tensor(r, c, s)
+    for lam in (1e-9, 2.5e-9, 1e3):
+        np.testing.assert_allclose(orc.prism_tensor(r * lam, c * lam, s * lam), N1, rtol=1e-12,
+                                   atol=1e-16)
+
+
+def test_pair_symmetry_identical_tiles(orc):
+    from paper_2107_05364_amd.workloads import grid
+
+    c, s = grid(4, 3, 2, 5e-9, 4e-9, 3e-9)
+    T = orc.assemble(c, s)
+    assert np.abs(T - T.T).max() < 1e-15
+
+
+def test_demag_energy_positive_semidefinite(orc):
+    from paper_2107_05364_amd.workloads import grid
+
+    c, s = grid(3, 3, 2, 1.0, 1.0, 1.0)
+    T = orc.assemble(c, s)
+    w = np.linalg.eigvalsh(0.5 * (T + T.T))
+    assert w.min() > 0.0 and w.max() < 1.0
+    # self blocks of a cube: 1/3 on the diagonal, trace of off blocks 0
+    n = c.shape[0]
+    for a in range(n):
+        for b in range(n):
+            blk = T[3 * a:3 * a + 3, 3 * b:3 * b + 3]
+            assert abs(np.trace(blk) - (1.0 if a == b else 0.0)) < 1e-14
+
+
+def test_superposition_of_subtiles(orc):
+    # tiles that exactly fill a box reproduce the box's tensor at any point
+    from paper_2107_05364_amd.workloads import grid
+
+    c, s = grid(3, 2, 2, 1.0, 1.5, 0.5)
+    big_c, big_s = np.array([1.5, 1.5, 0.5]), np.array([3.0, 3.0, 1.0])
+    for r in ([0.5, 0.75, 0.25], [5.0, -2.0, 1.3], [2.2, 3.1, -0.4]):
+        tot = sum(orc.prism_tensor(r, c[b], s[b]) for b in range(c.shape[0]))
+        np.testing.assert_allclose(tot, orc.prism_tensor(r, big_c, big_s), rtol=0, atol=2e-15)
+
+
+def test_logs_against_50_digit_plain_sum(orc):
+    """The oracle writes the ln(W + R) sums as cancellation-free ratios; the
+    plain eight-corner sum evaluated with 50 significant digits must agree to
+    FP64 accuracy, including column-aligned far pairs where W + R cancels."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+
+    def plain(r, c, s):
+        h = [mp.mpf(x) / 2 for x in s]
+        d = [mp.mpf(r[i]) - mp.mpf(c[i]) for i in range(3)]
+        X = [d[0] + h[0], d[0] - h[0]]
+        Y = [d[1] + h[1], d[1] - h[1]]
+        Z = [d[2] + h[2], d[2] - h[2]]
+        out = {}
+        for name, (P, Q, Wv) in {"xy": (X, Y, Z), "xz": (X, Z, Y), "yz": (Y, Z, X)}.items():
+            acc = mp.mpf(0)
+            for i in range(2):
+                for j in range(2):
+                    for k in range(2):
+                        R = mp.sqrt(P[i] ** 2 + Q[j] ** 2 + Wv[k] ** 2)
+                        acc += (-1) ** (i + j + k) * mp.log(Wv[k] + R)
+            # 0-based corner indices: the sign of corner (i, j, k) is -(-1)^(i+j+k)
+            out[name] = -acc / (4 * mp.pi)
+        return out
+
+    cases = [
+        ([0.3, 0.2, -400.0], [0, 0, 0], [1, 1, 1]),     # column-aligned, W + R cancels
+        ([0.25, -0.4, -1600.0], [0, 0, 0], [1, 1, 1]),
+        ([-800.0, 0.3, 0.1], [0, 0, 0], [1, 1, 1]),
+        ([40.0, 13.0, 7.0], [0, 0, 0], [2, 1, 1]),
+        ([0.9, 1.1, 0.2], [0, 0, 0], [1, 1, 1]),
+    ]
+    for r, c, s in cases:
+        N = orc.prism_tensor(r, c, s)
+        ref = plain(r, c, s)
+        for name, (i, j) in {"xy": (0, 1), "xz": (0, 2), "yz": (1, 2)}.items():
+            assert abs(N[i, j] - float(ref[name])) < 1e-16 + 1e-12 * abs(float(ref[name])), \
+                (r, name, N[i, j], float(ref[name]))
