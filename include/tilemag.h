@@ -1,0 +1,284 @@
+/*
+ * tilemag.h -- C ABI of the tile micromagnetics library for AMD MI355X (gfx950).
+ *
+ * The library evaluates the hot path of the analytical-demagnetisation-tensor
+ * method of Bjork, Poulsen, Nielsen & Insinga, "MagTense: a micromagnetic
+ * framework using the analytical demagnetization tensor", J. Magn. Magn.
+ * Mater. 535, 168057 (2021):
+ *   - the domain is split into N uniformly magnetised cuboid tiles and the
+ *     state is the 3N vector m (Sec. 3);
+ *   - the demag field at each tile centre is the superposition of the
+ *     analytical fields of all tiles, H_d = -N (Ms m), with a dense 3N x 3N
+ *     operator computed once (Sec. 3, Sec. 3.1, Sec. 3.2);
+ *   - the effective field adds exchange (finite differences, Neumann
+ *     boundary), uniaxial anisotropy and the applied field (Sec. 2.1, 2.3);
+ *   - the Landau-Lifshitz equation is integrated with an explicit Runge-Kutta
+ *     (4,5) pair (Sec. 2.1 eq. LL, Sec. 3.1).
+ *
+ * Conventions (apply to every entry point):
+ *   - Every call returns tm_status: TM_OK (0) or a negative code.  The text of
+ *     the last error on the calling thread is returned by tm_last_error().
+ *   - SI units: lengths in m, Ms and fields in A/m, A in J/m, K in J/m^3,
+ *     time in s, energies in J.
+ *   - Host arrays are owned by the caller and copied during the call.
+ *   - Device pointers are owned by the caller, borrowed for the call and used
+ *     in stream order on the given stream; calls return after enqueueing
+ *     unless stated otherwise.  Device pointers must be 16-byte aligned.
+ *   - State arrays are float32 [B][N][3] (state-major, tile, component),
+ *     applied fields float32 [B][3].
+ *   - Opaque handles are created and destroyed only by the library.  A
+ *     handle may be used from one thread at a time.
+ *   - HIP runtime errors are reported as TM_EDEVICE with the HIP message.
+ */
+#ifndef TILEMAG_H
+#define TILEMAG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tm_status;
+#define TM_OK 0
+#define TM_EINVAL (-1)      /* invalid argument (shape, null pointer, non-finite input) */
+#define TM_ENOMEM (-2)      /* device allocation failed or admission budget exceeded */
+#define TM_EDEVICE (-3)     /* HIP runtime error */
+#define TM_ENONFINITE (-4)  /* a state produced a non-finite value */
+#define TM_ESTEP (-5)       /* step size underflow or attempt limit reached */
+#define TM_EBUSY (-6)       /* resource still in use */
+#define TM_ENOTFOUND (-7)   /* unknown ticket or handle */
+
+/* Storage precision of the demag operator. */
+typedef enum {
+    TM_PREC_FP32 = 0,    /* float32 entries, float32 products */
+    TM_PREC_BF16X3 = 1,  /* bf16 hi + lo entries; MFMA hi*hi + hi*lo + lo*hi, fp32 accumulate */
+    TM_PREC_FP16X3 = 2,  /* fp16 hi + lo entries with a power-of-two scale per row */
+    TM_PREC_FP64 = 3     /* float64 entries (verification and debugging only) */
+} tm_prec;
+
+/* Layout of the stored operator. */
+typedef enum {
+    TM_LAYOUT_SYM6 = 0,   /* 6 planes [6][N][ldN] of (xx,xy,xz,yy,yz,zz), each 3x3 block symmetric */
+    TM_LAYOUT_DENSE9 = 1  /* row-major [3N][ld3N] dense operator (MFMA GEMM operand) */
+} tm_layout;
+
+typedef enum { TM_RK4 = 0, TM_DP45 = 1 } tm_integrator;
+
+typedef struct tm_ctx tm_ctx;
+typedef struct tm_geom tm_geom;
+typedef struct tm_tensor tm_tensor;
+typedef struct tm_problem tm_problem;
+typedef struct tm_server tm_server;
+
+/* Text of the last error raised on the calling thread ("" if none).  The
+ * pointer stays valid until the next call on that thread. */
+const char* tm_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t tm_version(void);
+
+/* Opens device `device` (HIP ordinal) and creates a context that owns the
+ * tensor cache and the admission budget (default: free device memory at
+ * creation minus 4 GiB).  TM_EDEVICE if the device cannot be opened. */
+tm_status tm_init(int32_t device, tm_ctx** out);
+
+/* Destroys the context and every tensor it owns.  TM_EBUSY if problems or
+ * servers created from it still exist. */
+tm_status tm_finalize(tm_ctx* ctx);
+
+/* Sets the admission budget in bytes for library-owned device memory
+ * (tensors, integrator workspaces, server slots). */
+tm_status tm_set_memory_budget(tm_ctx* ctx, int64_t bytes);
+
+/* Geometry of N axis-aligned cuboid tiles (paper Sec. 3).  Host-side only:
+ * ctx may be NULL (the geometry touches no device).
+ *   centers: host [n][3] tile centres [m]
+ *   sizes  : host [n][3] full edge lengths [m], all > 0
+ * The tiles must not overlap.  Also finds the face-sharing neighbour pairs
+ * used by the exchange operator.  TM_EINVAL on n < 1, a null pointer, a
+ * non-finite value or a non-positive edge. */
+tm_status tm_geometry_create(tm_ctx* ctx, int64_t n, const double* centers, const double* sizes,
+                             tm_geom** out);
+
+/* 64-bit hash of the canonical geometry bytes (n, centres, edges); equal
+ * geometries hash equal.  The tensor cache keys on it and confirms hits by
+ * comparing the bytes. */
+tm_status tm_geometry_hash(const tm_geom* g, uint64_t* out);
+
+/* Number of tiles and number of ordered face-neighbour pairs. */
+tm_status tm_geometry_info(const tm_geom* g, int64_t* n, int64_t* nfaces);
+
+tm_status tm_geometry_destroy(tm_geom* g);
+
+/* Assembles (or finds in the context's cache) the dense demag operator of g:
+ * block (a, b) is the analytical tensor of tile b at the centre of tile a
+ * (paper Sec. 3), evaluated in float64 on the device and stored in
+ * `store` precision and `layout`.  FP32 and FP64 support both layouts;
+ * BF16X3 and FP16X3 require DENSE9.  The returned handle holds a reference;
+ * release it with tm_tensor_release.  The call blocks until the operator is
+ * ready.  TM_ENOMEM if it does not fit the admission budget after evicting
+ * unreferenced cached tensors. */
+tm_status tm_tensor_assemble(tm_ctx* ctx, const tm_geom* g, tm_prec store, tm_layout layout,
+                             hipStream_t stream, tm_tensor** out);
+
+/* Reads back block (a, b) as stored (converted to double), row-major 3x3.
+ * Blocking.  For split precisions returns (hi + lo) / scale. */
+tm_status tm_tensor_get(const tm_tensor* t, int64_t a, int64_t b, double out9[9]);
+
+/* Reads back the blocks of target tiles [a0, a0 + count) against every
+ * source tile, as stored (converted to double; split precisions as
+ * (hi + lo) / scale), into host out[count][n][9] (row-major 3x3 blocks).
+ * Blocking. */
+tm_status tm_tensor_rows(const tm_tensor* t, int64_t a0, int64_t count, double* out);
+
+/* Device bytes held by the stored operator. */
+tm_status tm_tensor_bytes(const tm_tensor* t, int64_t* bytes);
+
+/* Drops the caller's reference; the tensor stays cached until evicted. */
+tm_status tm_tensor_release(tm_tensor* t);
+
+/* Material data (paper Sec. 2.1-2.3).
+ *   Ms     : host [n] saturation magnetisation [A/m], > 0 (required)
+ *   A_exch : exchange constant [J/m], >= 0
+ *   Ku     : host [n] uniaxial anisotropy constant [J/m^3] or NULL (none)
+ *   easy   : host [n][3] easy axes (normalised by the library) or NULL
+ *   alpha, gamma0, ll_form: Landau-Lifshitz coefficients of
+ *            dm/dt = -c1 m x H - c2 m x (m x H):
+ *            ll_form 0: alpha is the Gilbert damping,
+ *                       c1 = gamma0/(1+alpha^2), c2 = gamma0 alpha/(1+alpha^2);
+ *            ll_form 1: c1 = gamma0, c2 = alpha (the paper's LL parameters). */
+typedef struct {
+    const double* Ms;
+    double A_exch;
+    const double* Ku;
+    const double* easy;
+    double alpha;
+    double gamma0;
+    int32_t ll_form;
+} tm_material;
+
+/* Binds geometry, operator and material into a problem.  The problem keeps a
+ * reference to the tensor.  `g` must be the geometry the tensor was built
+ * from (checked by hash). */
+tm_status tm_problem_create(tm_ctx* ctx, const tm_geom* g, tm_tensor* t, const tm_material* mat,
+                            tm_problem** out);
+tm_status tm_problem_destroy(tm_problem* p);
+
+/* H_d = -N (Ms m) for B states (paper Sec. 2.3 demag term, Sec. 3.1).
+ *   m : device [B][n][3] float32,  Hd : device [B][n][3] float32 [A/m]. */
+tm_status tm_demag(tm_problem* p, int64_t B, const float* m, float* Hd, hipStream_t stream);
+
+/* H_eff = H_d + H_ex + H_anis + H_a (paper Sec. 2.3, affine form of Sec. 3.1).
+ *   Ha : device [B][3] applied field [A/m] (NULL: zero). */
+tm_status tm_heff(tm_problem* p, int64_t B, const float* m, const float* Ha, float* H,
+                  hipStream_t stream);
+
+/* dm/dt = -c1 m x H_eff - c2 m x (m x H_eff) (paper Sec. 2.1) [1/s]. */
+tm_status tm_dmdt(tm_problem* p, int64_t B, const float* m, const float* Ha, float* dmdt,
+                  hipStream_t stream);
+
+/* Free energy terms per state [J] (paper Sec. 2.2-2.3), accumulated in
+ * float64: E[b][0] demag, [1] exchange, [2] anisotropy, [3] Zeeman.
+ *   E : device [B][4] float64. */
+tm_status tm_energy(tm_problem* p, int64_t B, const float* m, const float* Ha, double* E,
+                    hipStream_t stream);
+
+/* Integration controls. */
+typedef struct {
+    int64_t max_steps;     /* accepted steps per state (RK4: steps) */
+    int64_t max_attempts;  /* > 0: replay exactly this many attempted steps; 0: until done */
+    double t_end;          /* > 0: stop each state at t = t_end */
+    double atol, rtol;     /* DP45 error tolerances (max norm) */
+    double dt_min;         /* DP45: a state whose step falls below this fails with TM_ESTEP */
+    double dmdt_stop;      /* > 0: a state is done once max_a |dm/dt|_a < dmdt_stop [1/s] */
+    int32_t renorm;        /* 1: |m_a| := 1 after each accepted step */
+    int32_t use_graph;     /* 1: capture one attempted step in a hipGraph and replay it */
+    int32_t poll_every;    /* attempts between host checks of the done flags (0: 64) */
+} tm_run_cfg;
+
+typedef struct {
+    int64_t attempts;      /* attempted steps replayed (all states together) */
+    int64_t accepted_min;  /* fewest accepted steps over the states */
+    int64_t accepted_max;
+    int64_t rejected;      /* rejected attempts summed over states */
+    int32_t states_done;   /* states that reached max_steps, t_end or dmdt_stop */
+    int32_t states_failed; /* states stopped by a non-finite value or step underflow */
+    double elapsed_ms;     /* host wall time of the call */
+} tm_run_stats;
+
+/* Integrates B independent states that share the problem's operator
+ * (paper Sec. 3.1: explicit Runge-Kutta (4,5); RK4 with fixed dt).
+ *   m  : device [B][n][3] float32, initial state in, final state out
+ *   Ha : device [B][3] applied field per state (NULL: zero)
+ *   t  : device [B] float64 time, in/out
+ *   dt : device [B] float64 step size (RK4: fixed step; DP45: initial and
+ *        final proposal), in/out
+ *   steps_out : device [B] int64 accepted steps per state, or NULL
+ * Blocks until finished.  Returns TM_ENONFINITE / TM_ESTEP if any state
+ * failed (the other states are still integrated). */
+tm_status tm_run(tm_problem* p, tm_integrator integ, int64_t B, float* m, const float* Ha,
+                 double* t, double* dt, int64_t* steps_out, const tm_run_cfg* cfg,
+                 tm_run_stats* stats, hipStream_t stream);
+
+/* ---- Profiling ---------------------------------------------------------- */
+
+/* Times the fused demag + effective-field + LL + stage-update kernel that
+ * every Runge-Kutta stage of tm_run launches (the same kernel and launch
+ * shape, on the problem's integration workspace for B states): `iters`
+ * back-to-back launches between two HIP events recorded on `stream`.
+ * Blocking.  avg_ms receives the mean duration of one launch; bytes_out
+ * (may be NULL) the algorithmic bytes one launch moves (stored operator +
+ * 24 bytes per tile and state).  The workspace contents are overwritten. */
+tm_status tm_profile_field(tm_problem* p, int64_t B, int32_t iters, hipStream_t stream,
+                           double* avg_ms, int64_t* bytes_out);
+
+/* ---- Serving: continuous batching of relaxation requests -------------- */
+
+typedef struct {
+    int64_t memory_budget;   /* bytes for tensors + slots (0: the context budget) */
+    int32_t max_slots;       /* states per geometry group (batch width), >= 1 */
+    int32_t max_groups;      /* geometry groups resident at once, >= 1 */
+    int32_t steps_per_round; /* attempted steps per group between scheduler checks */
+    tm_prec prec;            /* operator precision (FP32 only at present) */
+} tm_server_cfg;
+
+typedef struct {
+    int64_t n;
+    const double* centers;   /* host [n][3] */
+    const double* sizes;     /* host [n][3] */
+    tm_material mat;
+    double Ha[3];            /* applied field [A/m] */
+    const float* m0;         /* host [n][3] initial state */
+    double dt0;              /* initial step [s] */
+    double atol, rtol;
+    double dmdt_stop;        /* equilibrium threshold on max_a |dm/dt|_a [1/s] */
+    int64_t max_steps;       /* accepted-step cap */
+} tm_request;
+
+typedef struct {
+    int32_t status;          /* TM_OK, TM_EBUSY (still running), TM_ESTEP, TM_ENONFINITE */
+    int64_t steps;           /* accepted steps */
+    double t;                /* simulated time [s] */
+    double latency_ms;       /* submit -> completion wall time */
+    int32_t cache_hit;       /* 1 if the tensor came from the cache */
+} tm_result;
+
+/* Creates a server with its own scheduler thread on the context's device. */
+tm_status tm_server_create(tm_ctx* ctx, const tm_server_cfg* cfg, tm_server** out);
+
+/* Queues a request (host data copied).  Returns a ticket. */
+tm_status tm_server_submit(tm_server* s, const tm_request* req, uint64_t* ticket);
+
+/* Result of a ticket.  wait = 1 blocks until it completes.  If m_out is not
+ * NULL (host [n][3]) the final state is copied there once complete. */
+tm_status tm_server_poll(tm_server* s, uint64_t ticket, int32_t wait, tm_result* res, float* m_out);
+
+/* Stops the scheduler after draining the queue, frees its memory. */
+tm_status tm_server_destroy(tm_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TILEMAG_H */

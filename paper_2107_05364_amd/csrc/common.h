@@ -1,0 +1,221 @@
+// Internal declarations of the tilemag library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <list>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/tilemag.h"
+
+namespace tmag {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kMu0 = 4.0e-7 * kPi;  // vacuum permeability [H/m]
+
+void set_error(const char* fmt, ...);
+
+#define TM_TRY_HIP(call)                                                                  \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            ::tmag::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                            __LINE__);                                                    \
+            return TM_EDEVICE;                                                            \
+        }                                                                                 \
+    } while (0)
+
+#define TM_REQUIRE(cond, code, ...)        \
+    do {                                   \
+        if (!(cond)) {                     \
+            ::tmag::set_error(__VA_ARGS__);  \
+            return (code);                 \
+        }                                  \
+    } while (0)
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct Tensor;
+
+// One device; owns the tensor cache and the admission ledger.
+struct Ctx {
+    int device = 0;
+    int64_t budget = 0;        // bytes the library may hold on the device
+    int64_t used = 0;          // bytes currently held (tensors, workspaces, slots)
+    std::mutex mu;
+    std::list<Tensor*> cache;  // most recently used first
+    int live_problems = 0;
+    int live_servers = 0;
+    int64_t cache_hits = 0, cache_misses = 0;
+};
+
+// Reserve / return bytes against the context budget, evicting unreferenced
+// cached tensors (least recently used first) when needed.
+tm_status admit_bytes(Ctx* c, int64_t bytes);
+void release_bytes(Ctx* c, int64_t bytes);
+
+struct Geom {
+    Ctx* ctx = nullptr;
+    int64_t n = 0;
+    std::vector<double> centers, sizes;  // [n][3]
+    uint64_t hash = 0;
+    // ordered face-neighbour pairs in CSR form by the first tile
+    std::vector<int32_t> nbr_ptr;        // [n+1]
+    std::vector<int32_t> nbr_idx;
+    std::vector<double> nbr_area;        // shared face area [m^2]
+    std::vector<double> nbr_dist;        // centre distance along the face normal [m]
+};
+
+uint64_t geometry_hash(int64_t n, const double* centers, const double* sizes);
+void find_faces(Geom& g);
+
+struct Tensor {
+    Ctx* ctx = nullptr;
+    uint64_t hash = 0;
+    int64_t n = 0;
+    std::vector<double> centers, sizes;
+    tm_prec prec = TM_PREC_FP32;
+    tm_layout layout = TM_LAYOUT_SYM6;
+    int64_t ld = 0;       // row stride in elements
+    int64_t plane = 0;    // SYM6: stride between component planes in elements
+    int64_t rows = 0;     // DENSE9: allocated rows (>= 3n)
+    void* data = nullptr; // fp32 / fp64 entries, or the hi part
+    void* lo = nullptr;   // lo part of split precisions
+    float* rscale = nullptr; // FP16X3: per-row 1/scale (power of two)
+    int64_t bytes = 0;
+    int refs = 0;
+};
+
+// Device-side description of the pieces of a problem the kernels read.
+struct DevProblem {
+    int32_t n;          // tiles
+    int32_t np;         // padded tile count (multiple of 4); state stride = 3*np floats
+    const float* Ms;    // [np] saturation magnetisation, 0 in the padding
+    const int32_t* nbr_ptr;
+    const int32_t* nbr_idx;
+    const float* nbr_w; // 2A S_ab / (mu0 Ms_a V_a d_ab)  [A/m per unit of m]
+    const float* ku;    // [n] 2K/(mu0 Ms) or nullptr
+    const float* easy;  // [n][3] unit axes or nullptr
+    float c1, c2;       // LL coefficients
+};
+
+struct Workspace;
+
+struct Problem {
+    Ctx* ctx = nullptr;
+    Tensor* T = nullptr;
+    int64_t n = 0, np = 0;
+    double c1 = 0, c2 = 0;
+    double ms_ref = 0;          // max Ms (scale of the GEMM right operand)
+    bool uniform_ms = true;
+    // device arrays
+    float* Ms = nullptr;
+    int32_t* nbr_ptr = nullptr;
+    int32_t* nbr_idx = nullptr;
+    float* nbr_w = nullptr;
+    float* ku = nullptr;
+    float* easy = nullptr;
+    double* e_w = nullptr;      // [n] V_a Ms_a (float64, energy weights)
+    double* e_vk = nullptr;     // [n] V_a K_a
+    double* x_w = nullptr;      // per face A S/d (exchange energy), same CSR
+    int64_t nnz = 0;
+    int64_t bytes = 0;          // device bytes owned by the problem
+    std::unique_ptr<Workspace> ws;
+    DevProblem dev() const;
+};
+
+// Integrator / field workspace sized for a batch of B states.
+struct Workspace {
+    int64_t B = 0;
+    int64_t bytes = 0;
+    float* y = nullptr;       // [B][np][3] current state
+    float* ya = nullptr;      // stage input buffers
+    float* yb = nullptr;
+    float* y5 = nullptr;      // fifth-order solution (DP45) / scratch
+    float* k[7] = {};         // stage derivatives
+    float* Ha = nullptr;      // [B][3]
+    float* hd = nullptr;      // [B][np][3] demag / field scratch
+    // GEMM operands and partial sums (batched path)
+    void* xh = nullptr;       // right operand hi  [B][ld3]
+    void* xl = nullptr;       // right operand lo
+    float* part = nullptr;    // split-K partials [S][B][3np]
+    int64_t part_splits = 0;
+    // per-state control
+    double* t = nullptr;
+    double* h = nullptr;      // step used by the current attempt (0: frozen)
+    double* dt = nullptr;     // proposal
+    unsigned long long* err = nullptr;  // float64 bits, atomic max
+    unsigned long long* dmx = nullptr;
+    int64_t* steps = nullptr;
+    int64_t* rejected = nullptr;
+    int32_t* flags = nullptr;
+    int32_t* acc = nullptr;
+    double* params = nullptr; // RunParams on device
+    double* esum = nullptr;   // energy partial sums
+    int64_t esum_blocks = 0;
+    // pinned host mirrors (run parameters, polling)
+    double* host_params = nullptr;
+    int32_t* host_flags = nullptr;
+    int64_t* host_steps = nullptr;
+    // captured step graphs: one attempt, and kGraphSteps attempts
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph1 = nullptr;
+    hipGraphExec_t graphK = nullptr;
+    int graph_integ = -1;       // scheme, batch and renormalisation the graphs were captured for
+    int64_t graph_B = -1;
+    int graph_renorm = -1;
+    ~Workspace();
+};
+
+tm_status ensure_workspace(Problem* p, int64_t B);
+constexpr int kGraphSteps = 16;
+
+// Kernel launchers (fieldstep.hip).
+enum class Epi : int { HD = 0, HEFF = 1, DMDT = 2, STAGE = 3, RK4_FINAL = 4, DP_LAST = 5 };
+
+struct EpiArgs {
+    float* out;            // HD/HEFF/DMDT: output; STAGE/DP_LAST: k of this stage
+    int64_t out_stride;    // floats between states of `out`
+    const float* Ha;       // [B][3] or nullptr
+    const float* y;        // base state (STAGE, RK4_FINAL, DP_LAST)
+    float* y_mut;          // RK4_FINAL: state updated in place
+    const float* kprev[6]; // previous stage derivatives
+    float coef[7];         // STAGE: next-input weights of kprev[0..nprev-1] and of this k
+    int32_t nprev;
+    float* ynext;          // STAGE: next stage input
+    const double* h;       // [B] step of this attempt
+    const double* params;  // RunParams (atol, rtol, ...)
+    unsigned long long* err;
+    unsigned long long* dmx;
+    int32_t renorm;
+};
+
+// H (or a stage) for B states whose inputs X are padded internal buffers.
+tm_status launch_field(const Problem* p, Epi mode, int64_t B, const float* X, const EpiArgs& e,
+                       hipStream_t s);
+tm_status launch_pack(const float* src, int64_t B, int64_t n, int64_t np, float* dst, hipStream_t s);
+tm_status launch_control(Workspace* w, int64_t B, int integ, hipStream_t s);
+tm_status launch_commit(const Problem* p, Workspace* w, int64_t B, hipStream_t s);
+tm_status launch_energy(const Problem* p, int64_t B, const float* X, const float* Ha,
+                        const float* Hd, double* E, hipStream_t s);
+
+// Integrator pieces shared with the server (integrate.hip).
+tm_status enqueue_attempts(const Problem* p, Workspace* w, int integ, int64_t B, int renorm,
+                           int count, hipStream_t s);
+tm_status capture(const Problem* p, Workspace* w, int integ, int64_t B, int renorm, int count,
+                  hipGraphExec_t* out);
+tm_status start_slot(const Problem* p, Workspace* w, int64_t i, double dt0, hipStream_t s);
+tm_status free_slot(Workspace* w, int64_t i, hipStream_t s);
+
+// Run-parameter slots stored in Workspace::params (doubles).
+enum RunParam { RP_ATOL = 0, RP_RTOL, RP_TEND, RP_DTMIN, RP_DMDT_STOP, RP_MAX_STEPS, RP_RENORM,
+                RP_COUNT };
+
+// Per-state flag bits.
+constexpr int32_t FLAG_DONE = 1, FLAG_NONFINITE = 2, FLAG_STEP = 4;
+
+}  // namespace tmag

@@ -1,0 +1,492 @@
+// Demag product fused with the local effective-field terms, the
+// Landau-Lifshitz right-hand side and the Runge-Kutta stage update, plus the
+// per-state step control, the accept/commit pass and the energy reduction.
+//
+// One workgroup owns TT target tiles of one state.  It streams their rows of
+// the stored operator (SYM6: six planes xx, xy, xz, yy, yz, zz, each row
+// contiguous over source tiles) once from memory with 16-byte loads, 4 source
+// tiles per lane per step; the source state is read in the same step and
+// reused by the TT rows.  After a fixed-order wave + LDS reduction the
+// workgroup holds H_d = -N (Ms m) of its tiles (paper Sec. 2.3, Sec. 3.1) and
+// finishes them in the same launch:
+//   exchange  : sum_b w_ab (m_b - m_a), w_ab = 2A S_ab/(mu0 Ms_a V_a d_ab), a
+//               missing neighbour contributes nothing (Neumann, Sec. 2.1);
+//   anisotropy: (2K/(mu0 Ms)) (m . e) e;   applied field H_a  (Sec. 2.3);
+//   LL        : dm/dt = -c1 m x H - c2 m x (m x H)             (Sec. 2.1);
+//   stage     : next stage input y + h sum_j a_j k_j, or the RK4 update, or
+//               the Dormand-Prince error estimate in float64 (Sec. 3.1).
+// The reduction order depends only on the tile count, never on the batch,
+// so a state's result does not depend on what it is batched with.
+#include <cmath>
+
+#include "common.h"
+
+namespace tmag {
+namespace {
+
+struct MvArgs {
+    int32_t n;
+    int64_t ld;     // SYM6 row stride (multiple of 4) = number of streamed columns
+    int64_t plane;  // SYM6 plane stride
+    const float* T;
+    const float* Ms;  // [np]
+    const float* X;   // [B][np][3]
+    int64_t sx;       // 3 * np
+};
+
+__device__ inline float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+
+// Dormand-Prince 5(4): fifth-order weights b and embedded fourth-order b*;
+// the error weights are b - b*.
+__device__ constexpr double kDpB[7] = {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192,
+                                       -2187.0 / 6784, 11.0 / 84, 0.0};
+__device__ constexpr double kDpBs[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640,
+                                        -92097.0 / 339200, 187.0 / 2100, 1.0 / 40};
+
+template <Epi MODE>
+__device__ void finish_tile(const DevProblem& P, const MvArgs& M, const EpiArgs& E, int s, int a,
+                            float hd0, float hd1, float hd2, double* rmax, double* dmax) {
+    const int64_t o = s * M.sx + 3 * static_cast<int64_t>(a);
+    if constexpr (MODE == Epi::HD) {
+        float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
+        out[0] = hd0; out[1] = hd1; out[2] = hd2;
+        return;
+    } else {
+        const float* x = M.X + s * M.sx;
+        const float m0 = x[3 * a], m1 = x[3 * a + 1], m2 = x[3 * a + 2];
+        float H0 = hd0, H1 = hd1, H2 = hd2;
+        const int32_t j0 = P.nbr_ptr[a], j1 = P.nbr_ptr[a + 1];
+        for (int32_t j = j0; j < j1; ++j) {
+            const int32_t b = P.nbr_idx[j];
+            const float w = P.nbr_w[j];
+            H0 += w * (x[3 * b] - m0);
+            H1 += w * (x[3 * b + 1] - m1);
+            H2 += w * (x[3 * b + 2] - m2);
+        }
+        if (P.ku) {
+            const float e0 = P.easy[3 * a], e1 = P.easy[3 * a + 1], e2 = P.easy[3 * a + 2];
+            const float g = P.ku[a] * (m0 * e0 + m1 * e1 + m2 * e2);
+            H0 += g * e0; H1 += g * e1; H2 += g * e2;
+        }
+        if (E.Ha) {
+            H0 += E.Ha[3 * s]; H1 += E.Ha[3 * s + 1]; H2 += E.Ha[3 * s + 2];
+        }
+        if constexpr (MODE == Epi::HEFF) {
+            float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
+            out[0] = H0; out[1] = H1; out[2] = H2;
+            return;
+        } else {
+            // m x H and m x (m x H)
+            const float p0 = m1 * H2 - m2 * H1, p1 = m2 * H0 - m0 * H2, p2 = m0 * H1 - m1 * H0;
+            const float q0 = m1 * p2 - m2 * p1, q1 = m2 * p0 - m0 * p2, q2 = m0 * p1 - m1 * p0;
+            const float k0 = -P.c1 * p0 - P.c2 * q0;
+            const float k1 = -P.c1 * p1 - P.c2 * q1;
+            const float k2 = -P.c1 * p2 - P.c2 * q2;
+            if constexpr (MODE == Epi::DMDT) {
+                float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
+                out[0] = k0; out[1] = k1; out[2] = k2;
+                return;
+            } else if constexpr (MODE == Epi::STAGE) {
+                float* out = E.out + o;
+                out[0] = k0; out[1] = k1; out[2] = k2;
+                const float h = static_cast<float>(E.h[s]);
+                float c0 = E.coef[E.nprev] * k0, c1 = E.coef[E.nprev] * k1,
+                      c2 = E.coef[E.nprev] * k2;
+                for (int j = 0; j < E.nprev; ++j) {
+                    const float* kj = E.kprev[j] + o;
+                    c0 += E.coef[j] * kj[0]; c1 += E.coef[j] * kj[1]; c2 += E.coef[j] * kj[2];
+                }
+                const float* y = E.y + o;
+                float* yn = E.ynext + o;
+                yn[0] = y[0] + h * c0; yn[1] = y[1] + h * c1; yn[2] = y[2] + h * c2;
+                return;
+            } else if constexpr (MODE == Epi::RK4_FINAL) {
+                const double hd = E.h[s];
+                if (hd == 0.0) return;
+                const float h = static_cast<float>(hd);
+                float c0 = E.coef[E.nprev] * k0, c1 = E.coef[E.nprev] * k1,
+                      c2 = E.coef[E.nprev] * k2;
+                for (int j = 0; j < E.nprev; ++j) {
+                    const float* kj = E.kprev[j] + o;
+                    c0 += E.coef[j] * kj[0]; c1 += E.coef[j] * kj[1]; c2 += E.coef[j] * kj[2];
+                }
+                float* y = E.y_mut + o;
+                float v0 = y[0] + h * c0, v1 = y[1] + h * c1, v2 = y[2] + h * c2;
+                if (E.renorm) {
+                    const float r = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+                    v0 *= r; v1 *= r; v2 *= r;
+                }
+                y[0] = v0; y[1] = v1; y[2] = v2;
+                return;
+            } else {  // DP_LAST: k7 at the fifth-order solution, float64 error estimate
+                float* out = E.out + o;
+                out[0] = k0; out[1] = k1; out[2] = k2;
+                const double h = E.h[s];
+                double e0 = (kDpB[6] - kDpBs[6]) * k0, e1 = (kDpB[6] - kDpBs[6]) * k1,
+                       e2 = (kDpB[6] - kDpBs[6]) * k2;
+#pragma unroll
+                for (int j = 0; j < 6; ++j) {
+                    const double w = kDpB[j] - kDpBs[j];
+                    const float* kj = E.kprev[j] + o;
+                    e0 += w * kj[0]; e1 += w * kj[1]; e2 += w * kj[2];
+                }
+                const double atol = E.params[RP_ATOL], rtol = E.params[RP_RTOL];
+                const float* y = E.y + o;
+                const double s0 = atol + rtol * fmax(fabs((double)y[0]), fabs((double)m0));
+                const double s1 = atol + rtol * fmax(fabs((double)y[1]), fabs((double)m1));
+                const double s2 = atol + rtol * fmax(fabs((double)y[2]), fabs((double)m2));
+                const double r0 = fabs(h * e0) / s0, r1 = fabs(h * e1) / s1, r2 = fabs(h * e2) / s2;
+                // a NaN anywhere must win the max: map it to +inf (fmax drops NaN)
+                const bool bad = !(r0 == r0) || !(r1 == r1) || !(r2 == r2);
+                *rmax = bad ? INFINITY : fmax(r0, fmax(r1, r2));
+                const double d = sqrt((double)k0 * k0 + (double)k1 * k1 + (double)k2 * k2);
+                *dmax = (d == d) ? d : INFINITY;
+                return;
+            }
+        }
+    }
+}
+
+template <int BLOCK, int TT, Epi MODE>
+__global__ __launch_bounds__(BLOCK) void k_field(DevProblem P, MvArgs M, EpiArgs E) {
+    constexpr int NW = BLOCK / 64;
+    const int s = blockIdx.y;
+    const int a0 = blockIdx.x * TT;
+    const float* x = M.X + s * M.sx;
+    float acc[TT][3];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) acc[t][0] = acc[t][1] = acc[t][2] = 0.0f;
+    int64_t rowoff[TT];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) rowoff[t] = static_cast<int64_t>(min(a0 + t, M.n - 1)) * M.ld;
+
+    for (int64_t b = 4 * static_cast<int64_t>(threadIdx.x); b < M.ld; b += 4 * BLOCK) {
+        const float4 q0 = ld4(x + 3 * b), q1 = ld4(x + 3 * b + 4), q2 = ld4(x + 3 * b + 8);
+        const float4 ms = ld4(M.Ms + b);
+        const float mx0 = q0.x * ms.x, mx1 = q0.w * ms.y, mx2 = q1.z * ms.z, mx3 = q2.y * ms.w;
+        const float my0 = q0.y * ms.x, my1 = q1.x * ms.y, my2 = q1.w * ms.z, my3 = q2.z * ms.w;
+        const float mz0 = q0.z * ms.x, mz1 = q1.y * ms.y, mz2 = q2.x * ms.z, mz3 = q2.w * ms.w;
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+            const float* tp = M.T + rowoff[t] + b;
+            const float4 xx = ld4(tp), xy = ld4(tp + M.plane), xz = ld4(tp + 2 * M.plane);
+            const float4 yy = ld4(tp + 3 * M.plane), yz = ld4(tp + 4 * M.plane),
+                         zz = ld4(tp + 5 * M.plane);
+            float hx = acc[t][0], hy = acc[t][1], hz = acc[t][2];
+            hx += xx.x * mx0 + xy.x * my0 + xz.x * mz0;
+            hy += xy.x * mx0 + yy.x * my0 + yz.x * mz0;
+            hz += xz.x * mx0 + yz.x * my0 + zz.x * mz0;
+            hx += xx.y * mx1 + xy.y * my1 + xz.y * mz1;
+            hy += xy.y * mx1 + yy.y * my1 + yz.y * mz1;
+            hz += xz.y * mx1 + yz.y * my1 + zz.y * mz1;
+            hx += xx.z * mx2 + xy.z * my2 + xz.z * mz2;
+            hy += xy.z * mx2 + yy.z * my2 + yz.z * mz2;
+            hz += xz.z * mx2 + yz.z * my2 + zz.z * mz2;
+            hx += xx.w * mx3 + xy.w * my3 + xz.w * mz3;
+            hy += xy.w * mx3 + yy.w * my3 + yz.w * mz3;
+            hz += xz.w * mx3 + yz.w * my3 + zz.w * mz3;
+            acc[t][0] = hx; acc[t][1] = hy; acc[t][2] = hz;
+        }
+    }
+    // fixed-order reduction: butterfly inside each wave, then across waves
+#pragma unroll
+    for (int t = 0; t < TT; ++t)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float v = acc[t][c];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            acc[t][c] = v;
+        }
+    __shared__ float red[NW][TT * 3];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int t = 0; t < TT; ++t)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) red[wave][3 * t + c] = acc[t][c];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    double rmax = 0.0, dmax = 0.0;
+    if (lane < TT && a0 + lane < M.n) {
+        float h[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float v = 0.0f;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) v += red[w][3 * lane + c];
+            h[c] = -v;
+        }
+        finish_tile<MODE>(P, M, E, s, a0 + lane, h[0], h[1], h[2], &rmax, &dmax);
+    }
+    if constexpr (MODE == Epi::DP_LAST) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
+            dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
+        }
+        if (lane == 0) {
+            atomicMax(E.err + s, static_cast<unsigned long long>(__double_as_longlong(rmax)));
+            atomicMax(E.dmx + s, static_cast<unsigned long long>(__double_as_longlong(dmax)));
+        }
+    }
+}
+
+template <int BLOCK, int TT>
+tm_status launch_tt(const DevProblem& P, const MvArgs& M, Epi mode, int64_t B, const EpiArgs& e,
+                    hipStream_t st) {
+    const dim3 grid(static_cast<unsigned>((M.n + TT - 1) / TT), static_cast<unsigned>(B));
+    const dim3 block(BLOCK);
+    switch (mode) {
+        case Epi::HD: k_field<BLOCK, TT, Epi::HD><<<grid, block, 0, st>>>(P, M, e); break;
+        case Epi::HEFF: k_field<BLOCK, TT, Epi::HEFF><<<grid, block, 0, st>>>(P, M, e); break;
+        case Epi::DMDT: k_field<BLOCK, TT, Epi::DMDT><<<grid, block, 0, st>>>(P, M, e); break;
+        case Epi::STAGE: k_field<BLOCK, TT, Epi::STAGE><<<grid, block, 0, st>>>(P, M, e); break;
+        case Epi::RK4_FINAL:
+            k_field<BLOCK, TT, Epi::RK4_FINAL><<<grid, block, 0, st>>>(P, M, e);
+            break;
+        case Epi::DP_LAST: k_field<BLOCK, TT, Epi::DP_LAST><<<grid, block, 0, st>>>(P, M, e); break;
+    }
+    TM_TRY_HIP(hipGetLastError());
+    return TM_OK;
+}
+
+// ---------------------------------------------------------------- elementwise
+
+__global__ void k_pack(const float* __restrict__ src, int64_t n, int64_t np, int64_t B,
+                       float* __restrict__ dst) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= B * np * 3) return;
+    const int64_t s = i / (3 * np), r = i % (3 * np);
+    dst[i] = (r < 3 * n) ? src[s * 3 * n + r] : 0.0f;
+}
+
+// Per-state step control after the last stage (one thread per state).
+__global__ void k_control(int64_t B, int integ, const double* __restrict__ prm,
+                          double* __restrict__ t, double* __restrict__ h, double* __restrict__ dt,
+                          unsigned long long* __restrict__ err, unsigned long long* __restrict__ dmx,
+                          int64_t* __restrict__ steps, int64_t* __restrict__ rejected,
+                          int32_t* __restrict__ flags, int32_t* __restrict__ acc) {
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= B) return;
+    const double t_end = prm[RP_TEND];
+    const double max_steps = prm[RP_MAX_STEPS];
+    const double e = __longlong_as_double(static_cast<long long>(err[s]));
+    const double dm = __longlong_as_double(static_cast<long long>(dmx[s]));
+    err[s] = 0ull;
+    dmx[s] = 0ull;
+    int32_t f = flags[s];
+    if (f & (FLAG_DONE | FLAG_NONFINITE | FLAG_STEP)) {
+        acc[s] = 0;
+        h[s] = 0.0;
+        return;
+    }
+    const double hh = h[s];
+    double tn = t[s];
+    bool done = false;
+    if (integ == TM_RK4) {
+        tn += hh;
+        steps[s] += 1;
+        acc[s] = 1;
+        done = static_cast<double>(steps[s]) >= max_steps || (t_end > 0.0 && tn >= t_end);
+        t[s] = tn;
+        if (done) f |= FLAG_DONE;
+        flags[s] = f;
+        const double dn = dt[s];
+        h[s] = done ? 0.0 : (t_end > 0.0 ? fmin(dn, t_end - tn) : dn);
+        return;
+    }
+    if (!(e == e) || e == INFINITY || !(dm == dm)) {
+        flags[s] = f | FLAG_NONFINITE;
+        acc[s] = 0;
+        h[s] = 0.0;
+        return;
+    }
+    const bool ok = e <= 1.0;
+    if (ok) {
+        tn += hh;
+        steps[s] += 1;
+    } else {
+        rejected[s] += 1;
+    }
+    acc[s] = ok ? 1 : 0;
+    const double fac = (e == 0.0) ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(e, -0.2)));
+    double dn = hh * fac;
+    t[s] = tn;
+    done = static_cast<double>(steps[s]) >= max_steps || (t_end > 0.0 && tn >= t_end) ||
+           (ok && prm[RP_DMDT_STOP] > 0.0 && dm < prm[RP_DMDT_STOP]);
+    if (t_end > 0.0 && tn + dn > t_end) dn = t_end - tn;
+    dt[s] = done ? hh * fac : dn;
+    if (done) {
+        f |= FLAG_DONE;
+    } else if (dn < prm[RP_DTMIN]) {
+        f |= FLAG_STEP;
+    }
+    flags[s] = f;
+    h[s] = (f & (FLAG_DONE | FLAG_STEP)) ? 0.0 : dn;
+}
+
+// Accept / reject (DP45): on acceptance y <- y5 (renormalised), k1 <- k7;
+// then the next attempt's stage-2 input y + h a21 k1.
+__global__ void k_commit(int32_t n, int64_t np, int64_t B, float* __restrict__ y,
+                         float* __restrict__ k1, const float* __restrict__ y5,
+                         const float* __restrict__ k7, float* __restrict__ ya,
+                         const double* __restrict__ h, const int32_t* __restrict__ acc,
+                         const double* __restrict__ prm) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= B * np) return;
+    const int64_t s = i / np, a = i % np;
+    if (a >= n) return;
+    const int64_t o = s * 3 * np + 3 * a;
+    float v0 = y[o], v1 = y[o + 1], v2 = y[o + 2];
+    float g0 = k1[o], g1 = k1[o + 1], g2 = k1[o + 2];
+    if (acc[s]) {
+        v0 = y5[o]; v1 = y5[o + 1]; v2 = y5[o + 2];
+        if (prm[RP_RENORM] != 0.0) {
+            const float r = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+            v0 *= r; v1 *= r; v2 *= r;
+        }
+        g0 = k7[o]; g1 = k7[o + 1]; g2 = k7[o + 2];
+        y[o] = v0; y[o + 1] = v1; y[o + 2] = v2;
+        k1[o] = g0; k1[o + 1] = g1; k1[o + 2] = g2;
+    }
+    const float hh = static_cast<float>(h[s]) * (1.0f / 5.0f);
+    ya[o] = v0 + hh * g0;
+    ya[o + 1] = v1 + hh * g1;
+    ya[o + 2] = v2 + hh * g2;
+}
+
+// Energy terms per state in float64: block partial sums, then a fixed-order
+// final pass (paper Sec. 2.2-2.3 energy densities, integrated tile-wise).
+__global__ __launch_bounds__(256) void k_energy_part(int32_t n, int64_t np, const float* __restrict__ X,
+                                                     const float* __restrict__ Ha,
+                                                     const float* __restrict__ Hd,
+                                                     const double* __restrict__ vms,
+                                                     const double* __restrict__ vk,
+                                                     const float* __restrict__ easy,
+                                                     const int32_t* __restrict__ nptr,
+                                                     const int32_t* __restrict__ nidx,
+                                                     const double* __restrict__ xw,
+                                                     double* __restrict__ part) {
+    const int s = blockIdx.y;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    double ed = 0.0, ex = 0.0, ea = 0.0, ez = 0.0;
+    if (a < n) {
+        const float* x = X + static_cast<int64_t>(s) * 3 * np;
+        const double m0 = x[3 * a], m1 = x[3 * a + 1], m2 = x[3 * a + 2];
+        const float* hd = Hd + static_cast<int64_t>(s) * 3 * np + 3 * a;
+        ed = -0.5 * kMu0 * vms[a] * (m0 * hd[0] + m1 * hd[1] + m2 * hd[2]);
+        if (Ha) ez = -kMu0 * vms[a] * (m0 * Ha[3 * s] + m1 * Ha[3 * s + 1] + m2 * Ha[3 * s + 2]);
+        if (easy) {
+            const double me = m0 * easy[3 * a] + m1 * easy[3 * a + 1] + m2 * easy[3 * a + 2];
+            ea = -vk[a] * me * me;
+        }
+        for (int32_t j = nptr[a]; j < nptr[a + 1]; ++j) {
+            const int32_t b = nidx[j];
+            if (b < a) continue;  // each face once
+            const double d0 = x[3 * b] - m0, d1 = x[3 * b + 1] - m1, d2 = x[3 * b + 2] - m2;
+            ex += xw[j] * (d0 * d0 + d1 * d1 + d2 * d2);
+        }
+    }
+    __shared__ double red[4][256];
+    red[0][threadIdx.x] = ed; red[1][threadIdx.x] = ex;
+    red[2][threadIdx.x] = ea; red[3][threadIdx.x] = ez;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[(static_cast<int64_t>(s) * gridDim.x + blockIdx.x) * 4 + threadIdx.x] =
+        red[threadIdx.x][0];
+}
+
+__global__ void k_energy_final(int64_t B, int64_t nblk, const double* __restrict__ part,
+                               double* __restrict__ E) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= B * 4) return;
+    const int64_t s = i / 4, c = i % 4;
+    double v = 0.0;
+    for (int64_t b = 0; b < nblk; ++b) v += part[(s * nblk + b) * 4 + c];
+    E[i] = v;
+}
+
+}  // namespace
+
+DevProblem Problem::dev() const {
+    DevProblem d;
+    d.n = static_cast<int32_t>(n);
+    d.np = static_cast<int32_t>(np);
+    d.Ms = Ms;
+    d.nbr_ptr = nbr_ptr;
+    d.nbr_idx = nbr_idx;
+    d.nbr_w = nbr_w;
+    d.ku = ku;
+    d.easy = easy;
+    d.c1 = static_cast<float>(c1);
+    d.c2 = static_cast<float>(c2);
+    return d;
+}
+
+tm_status launch_field(const Problem* p, Epi mode, int64_t B, const float* X, const EpiArgs& e,
+                       hipStream_t s) {
+    const Tensor* T = p->T;
+    TM_REQUIRE(T->layout == TM_LAYOUT_SYM6 && T->prec == TM_PREC_FP32, TM_EINVAL,
+               "the single-state field path needs an FP32 SYM6 operator");
+    MvArgs M;
+    M.n = static_cast<int32_t>(p->n);
+    M.ld = T->ld;
+    M.plane = T->plane;
+    M.T = static_cast<const float*>(T->data);
+    M.Ms = p->Ms;
+    M.X = X;
+    M.sx = 3 * p->np;
+    const DevProblem P = p->dev();
+    // narrow workgroups for short rows so that every lane streams data
+    if (M.ld <= 256) return launch_tt<64, 2>(P, M, mode, B, e, s);
+    if (M.ld <= 1024) return launch_tt<128, 2>(P, M, mode, B, e, s);
+    if (p->n <= 4096) return launch_tt<256, 4>(P, M, mode, B, e, s);
+    return launch_tt<256, 8>(P, M, mode, B, e, s);
+}
+
+tm_status launch_pack(const float* src, int64_t B, int64_t n, int64_t np, float* dst,
+                      hipStream_t s) {
+    const int64_t cnt = B * np * 3;
+    k_pack<<<static_cast<unsigned>((cnt + 255) / 256), 256, 0, s>>>(src, n, np, B, dst);
+    TM_TRY_HIP(hipGetLastError());
+    return TM_OK;
+}
+
+tm_status launch_control(Workspace* w, int64_t B, int integ, hipStream_t s) {
+    k_control<<<static_cast<unsigned>((B + 255) / 256), 256, 0, s>>>(
+        B, integ, w->params, w->t, w->h, w->dt, w->err, w->dmx, w->steps, w->rejected, w->flags,
+        w->acc);
+    TM_TRY_HIP(hipGetLastError());
+    return TM_OK;
+}
+
+tm_status launch_commit(const Problem* p, Workspace* w, int64_t B, hipStream_t s) {
+    const int64_t cnt = B * p->np;
+    k_commit<<<static_cast<unsigned>((cnt + 255) / 256), 256, 0, s>>>(
+        static_cast<int32_t>(p->n), p->np, B, w->y, w->k[0], w->y5, w->k[6], w->ya, w->h, w->acc,
+        w->params);
+    TM_TRY_HIP(hipGetLastError());
+    return TM_OK;
+}
+
+tm_status launch_energy(const Problem* p, int64_t B, const float* X, const float* Ha,
+                        const float* Hd, double* E, hipStream_t s) {
+    Workspace* w = p->ws.get();
+    const int64_t nblk = (p->n + 255) / 256;
+    TM_REQUIRE(w && w->esum && w->esum_blocks >= nblk * B, TM_EINVAL, "energy workspace missing");
+    k_energy_part<<<dim3(static_cast<unsigned>(nblk), static_cast<unsigned>(B)), 256, 0, s>>>(
+        static_cast<int32_t>(p->n), p->np, X, Ha, Hd, p->e_w, p->e_vk, p->ku ? p->easy : nullptr,
+        p->nbr_ptr, p->nbr_idx, p->x_w, w->esum);
+    TM_TRY_HIP(hipGetLastError());
+    k_energy_final<<<static_cast<unsigned>((B * 4 + 255) / 256), 256, 0, s>>>(B, nblk, w->esum, E);
+    TM_TRY_HIP(hipGetLastError());
+    return TM_OK;
+}
+
+}  // namespace tmag

@@ -1,0 +1,374 @@
+// Time integration of the Landau-Lifshitz equation (paper Sec. 2.1) with an
+// explicit Runge-Kutta (4,5) pair, adaptive per state (Sec. 3.1), or with
+// the classical fourth-order scheme at a fixed step.
+//
+// Every stage is one launch of the fused field kernel: it evaluates the
+// right-hand side at the stage input and writes the next stage input (or the
+// RK4 update, or the float64 Dormand-Prince error estimate).  A small
+// control kernel then decides acceptance and the next step per state, and
+// (DP45) a commit pass applies the accepted step, restores |m| = 1 and forms
+// the next attempt's first stage input.  Nothing returns to the host between
+// attempts; one attempt (or kGraphSteps of them) is captured in a hipGraph
+// and replayed.  States of a batch never couple: each has its own field,
+// time, step size and flags, and finished or failed states are frozen.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "common.h"
+
+namespace tmag {
+namespace {
+
+// Dormand-Prince 5(4) stage weights a_sj (first-same-as-last: the last row
+// is the fifth-order solution).
+constexpr double kDpA[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+
+__global__ void k_init_run(int64_t B, const double* __restrict__ t_in, const double* __restrict__ dt_in,
+                           const double* __restrict__ prm, double* __restrict__ t,
+                           double* __restrict__ h, double* __restrict__ dt,
+                           unsigned long long* __restrict__ err, unsigned long long* __restrict__ dmx,
+                           int64_t* __restrict__ steps, int64_t* __restrict__ rejected,
+                           int32_t* __restrict__ flags, int32_t* __restrict__ acc) {
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= B) return;
+    const double t0 = t_in[s], d0 = dt_in[s], t_end = prm[RP_TEND];
+    t[s] = t0;
+    dt[s] = d0;
+    double hh = d0;
+    int32_t f = 0;
+    if (t_end > 0.0 && t0 + hh > t_end) hh = t_end - t0;
+    if (prm[RP_MAX_STEPS] <= 0.0 || (t_end > 0.0 && t0 >= t_end)) f = FLAG_DONE;
+    h[s] = f ? 0.0 : hh;
+    flags[s] = f;
+    err[s] = 0ull;
+    dmx[s] = 0ull;
+    steps[s] = 0;
+    rejected[s] = 0;
+    acc[s] = 0;
+}
+
+__global__ void k_unpack(const float* __restrict__ src, int64_t n, int64_t np, int64_t B,
+                         float* __restrict__ dst) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= B * n * 3) return;
+    const int64_t s = i / (3 * n), r = i % (3 * n);
+    dst[i] = src[s * 3 * np + r];
+}
+
+EpiArgs stage_args(Workspace* w, float* kout, const float* const* kprev, int nprev,
+                   const double* coef, float* ynext) {
+    EpiArgs e{};
+    e.out = kout;
+    e.out_stride = 0;
+    e.Ha = w->Ha;
+    e.y = w->y;
+    for (int j = 0; j < nprev; ++j) e.kprev[j] = kprev[j];
+    for (int j = 0; j <= nprev; ++j) e.coef[j] = static_cast<float>(coef[j]);
+    e.nprev = nprev;
+    e.ynext = ynext;
+    e.h = w->h;
+    e.params = w->params;
+    e.err = w->err;
+    e.dmx = w->dmx;
+    return e;
+}
+
+// DP45 first stage: k1 = f(y), stage-2 input y + h a21 k1.
+tm_status dp_first(const Problem* p, Workspace* w, int64_t B, hipStream_t s) {
+    const double c[1] = {kDpA[1][0]};
+    EpiArgs e = stage_args(w, w->k[0], nullptr, 0, c, w->ya);
+    return launch_field(p, Epi::STAGE, B, w->y, e, s);
+}
+
+// One attempted DP45 step: stages 2..7, control, commit.
+tm_status dp_attempt(const Problem* p, Workspace* w, int64_t B, hipStream_t s) {
+    float* in[7] = {nullptr, w->ya, w->yb, w->ya, w->yb, w->ya, w->y5};
+    float* nxt[7] = {nullptr, w->yb, w->ya, w->yb, w->ya, w->y5, nullptr};
+    const float* kp[6] = {w->k[0], w->k[1], w->k[2], w->k[3], w->k[4], w->k[5]};
+    for (int st = 1; st < 6; ++st) {  // stages 2..6 (0-based st)
+        double c[7];
+        for (int j = 0; j <= st; ++j) c[j] = kDpA[st + 1][j];
+        EpiArgs e = stage_args(w, w->k[st], kp, st, c, nxt[st]);
+        tm_status r = launch_field(p, Epi::STAGE, B, in[st], e, s);
+        if (r != TM_OK) return r;
+    }
+    const double none[7] = {0, 0, 0, 0, 0, 0, 0};
+    EpiArgs e = stage_args(w, w->k[6], kp, 6, none, nullptr);
+    tm_status r = launch_field(p, Epi::DP_LAST, B, w->y5, e, s);
+    if (r != TM_OK) return r;
+    r = launch_control(w, B, TM_DP45, s);
+    if (r != TM_OK) return r;
+    return launch_commit(p, w, B, s);
+}
+
+// One classical RK4 step.
+tm_status rk4_attempt(const Problem* p, Workspace* w, int64_t B, int renorm, hipStream_t s) {
+    const float* kp[3] = {w->k[0], w->k[1], w->k[2]};
+    const double half[1] = {0.5}, one[1] = {1.0};
+    tm_status r;
+    EpiArgs e1 = stage_args(w, w->k[0], nullptr, 0, half, w->ya);
+    if ((r = launch_field(p, Epi::STAGE, B, w->y, e1, s)) != TM_OK) return r;
+    EpiArgs e2 = stage_args(w, w->k[1], nullptr, 0, half, w->yb);
+    if ((r = launch_field(p, Epi::STAGE, B, w->ya, e2, s)) != TM_OK) return r;
+    EpiArgs e3 = stage_args(w, w->k[2], nullptr, 0, one, w->ya);
+    if ((r = launch_field(p, Epi::STAGE, B, w->yb, e3, s)) != TM_OK) return r;
+    const double fin[4] = {1.0 / 6, 2.0 / 6, 2.0 / 6, 1.0 / 6};
+    EpiArgs e4 = stage_args(w, nullptr, kp, 3, fin, nullptr);
+    e4.y_mut = w->y;
+    e4.renorm = renorm;
+    if ((r = launch_field(p, Epi::RK4_FINAL, B, w->ya, e4, s)) != TM_OK) return r;
+    return launch_control(w, B, TM_RK4, s);
+}
+
+}  // namespace
+
+tm_status enqueue_attempts(const Problem* p, Workspace* w, int integ, int64_t B, int renorm,
+                           int count, hipStream_t s) {
+    for (int i = 0; i < count; ++i) {
+        tm_status r = integ == TM_RK4 ? rk4_attempt(p, w, B, renorm, s) : dp_attempt(p, w, B, s);
+        if (r != TM_OK) return r;
+    }
+    return TM_OK;
+}
+
+tm_status capture(const Problem* p, Workspace* w, int integ, int64_t B, int renorm, int count,
+                  hipGraphExec_t* out) {
+    if (!w->cap_stream) TM_TRY_HIP(hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking));
+    TM_TRY_HIP(hipStreamBeginCapture(w->cap_stream, hipStreamCaptureModeThreadLocal));
+    tm_status r = enqueue_attempts(p, w, integ, B, renorm, count, w->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(w->cap_stream, &g);
+    if (r != TM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    TM_TRY_HIP(e);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    TM_TRY_HIP(e);
+    return TM_OK;
+}
+
+namespace {
+__global__ void k_init_slot(int64_t i, double dt0, double* __restrict__ t, double* __restrict__ h,
+                            double* __restrict__ dt, unsigned long long* __restrict__ err,
+                            unsigned long long* __restrict__ dmx, int64_t* __restrict__ steps,
+                            int64_t* __restrict__ rejected, int32_t* __restrict__ flags,
+                            int32_t* __restrict__ acc) {
+    if (threadIdx.x != 0) return;
+    t[i] = 0.0;
+    dt[i] = dt0;
+    h[i] = dt0;
+    err[i] = 0ull;
+    dmx[i] = 0ull;
+    steps[i] = 0;
+    rejected[i] = 0;
+    flags[i] = 0;
+    acc[i] = 0;
+}
+
+__global__ void k_free_slot(int64_t i, double* __restrict__ h, int32_t* __restrict__ flags) {
+    if (threadIdx.x != 0) return;
+    h[i] = 0.0;
+    flags[i] = FLAG_DONE;
+}
+}  // namespace
+
+// Starts state `i` of a batch: control reset, k1 = f(y_i) and the first
+// stage input, touching no other state.
+tm_status start_slot(const Problem* p, Workspace* w, int64_t i, double dt0, hipStream_t s) {
+    k_init_slot<<<1, 64, 0, s>>>(i, dt0, w->t, w->h, w->dt, w->err, w->dmx, w->steps, w->rejected,
+                                 w->flags, w->acc);
+    TM_TRY_HIP(hipGetLastError());
+    const int64_t o = i * 3 * p->np;
+    const double c[1] = {kDpA[1][0]};
+    EpiArgs e = stage_args(w, w->k[0] + o, nullptr, 0, c, w->ya + o);
+    e.Ha = w->Ha + 3 * i;
+    e.y = w->y + o;
+    e.h = w->h + i;
+    e.params = w->params;
+    return launch_field(p, Epi::STAGE, 1, w->y + o, e, s);
+}
+
+tm_status free_slot(Workspace* w, int64_t i, hipStream_t s) {
+    k_free_slot<<<1, 64, 0, s>>>(i, w->h, w->flags);
+    TM_TRY_HIP(hipGetLastError());
+    return TM_OK;
+}
+
+}  // namespace tmag
+
+using namespace tmag;
+
+extern "C" tm_status tm_run(tm_problem* pp, tm_integrator integ, int64_t B, float* m, const float* Ha,
+                            double* t, double* dt, int64_t* steps_out, const tm_run_cfg* cfg,
+                            tm_run_stats* stats, hipStream_t s) {
+    Problem* p = reinterpret_cast<Problem*>(pp);
+    auto t0 = std::chrono::steady_clock::now();
+    TM_REQUIRE(p && m && t && dt && cfg && B >= 1, TM_EINVAL, "tm_run: null argument or B < 1");
+    TM_REQUIRE(integ == TM_RK4 || integ == TM_DP45, TM_EINVAL, "tm_run: unknown integrator");
+    TM_REQUIRE(cfg->max_steps >= 0 && cfg->max_attempts >= 0, TM_EINVAL, "tm_run: negative limits");
+    TM_REQUIRE(integ == TM_RK4 || (cfg->atol > 0.0 || cfg->rtol > 0.0), TM_EINVAL,
+               "tm_run: DP45 needs atol > 0 or rtol > 0");
+    TM_REQUIRE((reinterpret_cast<uintptr_t>(m) & 15) == 0, TM_EINVAL, "tm_run: m must be 16-byte aligned");
+    TM_REQUIRE(B <= (int64_t(1) << 16), TM_EINVAL, "tm_run: batch too large");
+    TM_TRY_HIP(hipSetDevice(p->ctx->device));
+    tm_status st = ensure_workspace(p, B);
+    if (st != TM_OK) return st;
+    Workspace* w = p->ws.get();
+    // a graph holds B in its launch shapes: re-capture when B or the scheme changes
+    const int renorm = cfg->renorm ? 1 : 0;
+    if (w->graph1 && (w->graph_integ != static_cast<int>(integ) || w->graph_B != B ||
+                      w->graph_renorm != renorm)) {
+        (void)hipGraphExecDestroy(w->graph1);
+        w->graph1 = nullptr;
+        if (w->graphK) (void)hipGraphExecDestroy(w->graphK);
+        w->graphK = nullptr;
+    }
+    TM_TRY_HIP(hipStreamSynchronize(s));  // pinned parameter buffer is about to be rewritten
+    double* hp = w->host_params;
+    hp[RP_ATOL] = cfg->atol;
+    hp[RP_RTOL] = cfg->rtol;
+    hp[RP_TEND] = cfg->t_end;
+    hp[RP_DTMIN] = cfg->dt_min;
+    hp[RP_DMDT_STOP] = cfg->dmdt_stop;
+    hp[RP_MAX_STEPS] = static_cast<double>(cfg->max_steps);
+    hp[RP_RENORM] = cfg->renorm ? 1.0 : 0.0;
+    TM_TRY_HIP(hipMemcpyAsync(w->params, hp, RP_COUNT * sizeof(double), hipMemcpyHostToDevice, s));
+    st = launch_pack(m, B, p->n, p->np, w->y, s);
+    if (st != TM_OK) return st;
+    if (Ha)
+        TM_TRY_HIP(hipMemcpyAsync(w->Ha, Ha, B * 12, hipMemcpyDeviceToDevice, s));
+    else
+        TM_TRY_HIP(hipMemsetAsync(w->Ha, 0, B * 12, s));
+    k_init_run<<<static_cast<unsigned>((B + 255) / 256), 256, 0, s>>>(
+        B, t, dt, w->params, w->t, w->h, w->dt, w->err, w->dmx, w->steps, w->rejected, w->flags,
+        w->acc);
+    TM_TRY_HIP(hipGetLastError());
+    if (integ == TM_DP45) {
+        st = dp_first(p, w, B, s);
+        if (st != TM_OK) return st;
+    }
+    if (cfg->use_graph && !w->graph1) {
+        st = capture(p, w, integ, B, renorm, 1, &w->graph1);
+        if (st != TM_OK) return st;
+        st = capture(p, w, integ, B, renorm, kGraphSteps, &w->graphK);
+        if (st != TM_OK) return st;
+        w->graph_integ = static_cast<int>(integ);
+        w->graph_B = B;
+        w->graph_renorm = renorm;
+    }
+    auto run_chunk = [&](int64_t cnt) -> tm_status {
+        if (!cfg->use_graph) return enqueue_attempts(p, w, integ, B, renorm, static_cast<int>(cnt), s);
+        int64_t q = cnt / kGraphSteps, r = cnt % kGraphSteps;
+        for (int64_t i = 0; i < q; ++i) TM_TRY_HIP(hipGraphLaunch(w->graphK, s));
+        for (int64_t i = 0; i < r; ++i) TM_TRY_HIP(hipGraphLaunch(w->graph1, s));
+        return TM_OK;
+    };
+    int64_t attempts = 0;
+    if (cfg->max_attempts > 0) {
+        st = run_chunk(cfg->max_attempts);
+        if (st != TM_OK) return st;
+        attempts = cfg->max_attempts;
+    } else {
+        const int64_t poll = cfg->poll_every > 0 ? cfg->poll_every : 64;
+        const int64_t cap = integ == TM_RK4 ? cfg->max_steps : 64 * cfg->max_steps + 4096;
+        while (attempts < cap) {
+            int64_t cnt = integ == TM_RK4 ? std::min(cap - attempts, cap) : std::min(poll, cap - attempts);
+            st = run_chunk(cnt);
+            if (st != TM_OK) return st;
+            attempts += cnt;
+            if (integ == TM_RK4) break;
+            TM_TRY_HIP(hipMemcpyAsync(w->host_flags, w->flags, B * 4, hipMemcpyDeviceToHost, s));
+            TM_TRY_HIP(hipStreamSynchronize(s));
+            bool all = true;
+            for (int64_t i = 0; i < B && all; ++i) all = w->host_flags[i] != 0;
+            if (all) break;
+        }
+    }
+    // results back to the caller's buffers
+    k_unpack<<<static_cast<unsigned>((B * p->n * 3 + 255) / 256), 256, 0, s>>>(w->y, p->n, p->np, B, m);
+    TM_TRY_HIP(hipGetLastError());
+    TM_TRY_HIP(hipMemcpyAsync(t, w->t, B * 8, hipMemcpyDeviceToDevice, s));
+    TM_TRY_HIP(hipMemcpyAsync(dt, w->dt, B * 8, hipMemcpyDeviceToDevice, s));
+    if (steps_out) TM_TRY_HIP(hipMemcpyAsync(steps_out, w->steps, B * 8, hipMemcpyDeviceToDevice, s));
+    TM_TRY_HIP(hipMemcpyAsync(w->host_flags, w->flags, B * 4, hipMemcpyDeviceToHost, s));
+    TM_TRY_HIP(hipMemcpyAsync(w->host_steps, w->steps, B * 8, hipMemcpyDeviceToHost, s));
+    TM_TRY_HIP(hipMemcpyAsync(w->host_steps + B, w->rejected, B * 8, hipMemcpyDeviceToHost, s));
+    TM_TRY_HIP(hipStreamSynchronize(s));
+    int64_t amin = INT64_MAX, amax = 0, rej = 0;
+    int32_t done = 0, failed = 0, nonfinite = 0;
+    for (int64_t i = 0; i < B; ++i) {
+        amin = std::min(amin, w->host_steps[i]);
+        amax = std::max(amax, w->host_steps[i]);
+        rej += w->host_steps[B + i];
+        const int32_t f = w->host_flags[i];
+        if (f & FLAG_DONE) ++done;
+        if (f & (FLAG_NONFINITE | FLAG_STEP)) ++failed;
+        if (f & FLAG_NONFINITE) ++nonfinite;
+    }
+    if (stats) {
+        stats->attempts = attempts;
+        stats->accepted_min = amin;
+        stats->accepted_max = amax;
+        stats->rejected = rej;
+        stats->states_done = done;
+        stats->states_failed = failed;
+        stats->elapsed_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (nonfinite) {
+        set_error("tm_run: %d state(s) produced non-finite values", nonfinite);
+        return TM_ENONFINITE;
+    }
+    if (failed) {
+        set_error("tm_run: %d state(s) stopped by step-size underflow", failed);
+        return TM_ESTEP;
+    }
+    if (cfg->max_attempts == 0 && done < B) {
+        set_error("tm_run: %lld state(s) not finished after %lld attempts",
+                  static_cast<long long>(B - done), static_cast<long long>(attempts));
+        return TM_ESTEP;
+    }
+    return TM_OK;
+}
+
+extern "C" tm_status tm_profile_field(tm_problem* pp, int64_t B, int32_t iters, hipStream_t s,
+                                      double* avg_ms, int64_t* bytes_out) {
+    Problem* p = reinterpret_cast<Problem*>(pp);
+    TM_REQUIRE(p && avg_ms && B >= 1 && iters >= 1, TM_EINVAL, "tm_profile_field: bad arguments");
+    TM_TRY_HIP(hipSetDevice(p->ctx->device));
+    tm_status st = ensure_workspace(p, B);
+    if (st != TM_OK) return st;
+    Workspace* w = p->ws.get();
+    // the stage-2 launch of a Dormand-Prince attempt: reads ya, k1, y; writes k2, yb
+    const float* kp[6] = {w->k[0], w->k[1], w->k[2], w->k[3], w->k[4], w->k[5]};
+    double c[7] = {kDpA[2][0], kDpA[2][1]};
+    EpiArgs e = stage_args(w, w->k[1], kp, 1, c, w->yb);
+    hipEvent_t e0, e1;
+    TM_TRY_HIP(hipEventCreate(&e0));
+    TM_TRY_HIP(hipEventCreate(&e1));
+    st = launch_field(p, Epi::STAGE, B, w->ya, e, s);  // untimed first launch
+    if (st == TM_OK && hipEventRecord(e0, s) != hipSuccess) st = TM_EDEVICE;
+    for (int32_t i = 0; i < iters && st == TM_OK; ++i) st = launch_field(p, Epi::STAGE, B, w->ya, e, s);
+    float ms = 0.0f;
+    if (st == TM_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)) {
+        set_error("tm_profile_field: event timing failed");
+        st = TM_EDEVICE;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != TM_OK) return st;
+    *avg_ms = static_cast<double>(ms) / iters;
+    if (bytes_out) *bytes_out = 24 * p->n * p->n + 24 * p->n * B;
+    return TM_OK;
+}
