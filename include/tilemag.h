@@ -234,6 +234,27 @@ tm_status tm_run(tm_problem* p, tm_integrator integ, int64_t B, float* m, const 
 tm_status tm_profile_field(tm_problem* p, int64_t B, int32_t iters, hipStream_t stream,
                            double* avg_ms, int64_t* bytes_out);
 
+/* Same timing for one epilogue variant: mode 0 the stage update (as
+ * tm_profile_field), 1 the demag field only, 2 the last Dormand-Prince stage
+ * with its float64 error estimate. */
+tm_status tm_profile_field_mode(tm_problem* p, int64_t B, int32_t mode, int32_t iters,
+                                hipStream_t stream, double* avg_ms, int64_t* bytes_out);
+
+/* Number of launch shapes (workgroup width x target tiles per workgroup x
+ * load kind) the fused field kernel is compiled for. */
+int32_t tm_num_shapes(void);
+
+/* Fixes the launch shape of p's field kernel (0 <= shape < tm_num_shapes(),
+ * or -1 for the default chosen from the tile count).  The shape sets the
+ * summation order of the demag product, so results are bitwise reproducible
+ * for a fixed shape and independent of the batch size. */
+tm_status tm_problem_set_shape(tm_problem* p, int32_t shape);
+
+/* Autotuner: times every shape (iters launches each, B states) and keeps the
+ * fastest for p.  Blocking.  chosen / best_ms may be NULL. */
+tm_status tm_problem_tune(tm_problem* p, int64_t B, int32_t iters, hipStream_t stream,
+                          int32_t* chosen, double* best_ms);
+
 /* ---- Serving: continuous batching of relaxation requests -------------- */
 
 typedef struct {

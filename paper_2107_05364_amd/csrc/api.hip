@@ -216,7 +216,7 @@ tm_status tm_tensor_assemble(tm_ctx* c, const tm_geom* g, tm_prec store, tm_layo
         main_bytes = 6 * T->plane * static_cast<int64_t>(esz);
     } else {
         T->ld = 3 * np;
-        T->rows = 3 * np;
+        T->rows = round_up(3 * np, 128);
         main_bytes = T->rows * T->ld * static_cast<int64_t>(esz);
         if (store == TM_PREC_BF16X3 || store == TM_PREC_FP16X3) lo_bytes = main_bytes;
         if (store == TM_PREC_FP16X3) sc_bytes = T->rows * 4;
@@ -557,11 +557,28 @@ tm_status tm_problem_destroy(tm_problem* p) {
 namespace tmag {
 
 tm_status ensure_workspace(Problem* p, int64_t B) {
-    if (p->ws && p->ws->B >= B) return TM_OK;
+    const Tensor* T = p->T;
+    const bool dense = T->layout == TM_LAYOUT_DENSE9 && T->prec != TM_PREC_FP64;
+    if (dense)
+        TM_REQUIRE(B <= kMaxGemmStates, TM_EINVAL,
+                   "batched (DENSE9) path: at most %lld states per call",
+                   static_cast<long long>(kMaxGemmStates));
+    // the GEMM operand is read in tiles of 16 states: pad the batch
+    const int64_t bcap = dense ? 16 * gemm_state_tiles(B) : B;
+    if (p->ws && p->ws->B >= bcap) return TM_OK;
     const int64_t np = p->np, n = p->n;
-    const int64_t sb = B * 3 * np * 4;  // one state buffer
+    const int64_t sb = bcap * 3 * np * 4;  // one state buffer
     const int64_t nblk = (n + 255) / 256;
-    int64_t bytes = 12 * sb + B * 12 + B * (8 * 5 + 8 * 2 + 4 * 2) + RP_COUNT * 8 + nblk * B * 32;
+    int64_t xbytes = 0, pbytes = 0, splits = 0;
+    if (dense) {
+        const int64_t esz = T->prec == TM_PREC_FP32 ? 4 : 2;
+        const bool need_x = T->prec != TM_PREC_FP32 || !p->uniform_ms;
+        xbytes = need_x ? bcap * T->ld * esz * (T->prec == TM_PREC_FP32 ? 1 : 2) : 0;
+        splits = gemm_splits(p);
+        pbytes = splits * bcap * T->rows * 4;
+    }
+    int64_t bytes = 12 * sb + bcap * 12 + bcap * (8 * 5 + 8 * 2 + 4 * 2) + RP_COUNT * 8 +
+                    nblk * bcap * 32 + xbytes + pbytes;
     {
         std::lock_guard<std::mutex> lk(p->ctx->mu);
         const int64_t old = p->ws ? p->ws->bytes : 0;
@@ -577,7 +594,8 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
         p->ws.reset();
     }
     auto w = std::make_unique<Workspace>();
-    w->B = B;
+    w->B = bcap;
+    w->bpad = dense ? bcap : 0;
     w->bytes = bytes;
     auto alloc = [](void** d, size_t sz) -> hipError_t {
         hipError_t e = hipMalloc(d, sz);
@@ -589,22 +607,31 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
                       &w->k[3], &w->k[4], &w->k[5], &w->k[6]};
     for (float** b : bufs)
         if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(b), sb);
-    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->Ha), B * 12);
-    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->t), B * 8);
-    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->h), B * 8);
-    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->dt), B * 8);
-    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->err), B * 8);
-    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->dmx), B * 8);
-    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->steps), B * 8);
-    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->rejected), B * 8);
-    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->flags), B * 4);
-    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->acc), B * 4);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->Ha), bcap * 12);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->t), bcap * 8);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->h), bcap * 8);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->dt), bcap * 8);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->err), bcap * 8);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->dmx), bcap * 8);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->steps), bcap * 8);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->rejected), bcap * 8);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->flags), bcap * 4);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->acc), bcap * 4);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->params), RP_COUNT * 8);
-    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->esum), nblk * B * 32);
-    w->esum_blocks = nblk * B;
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->esum), nblk * bcap * 32);
+    w->esum_blocks = nblk * bcap;
+    if (dense && xbytes && e == hipSuccess) {
+        const int64_t half = T->prec == TM_PREC_FP32 ? xbytes : xbytes / 2;
+        e = alloc(&w->xh, half);
+        if (e == hipSuccess && T->prec != TM_PREC_FP32) e = alloc(&w->xl, half);
+    }
+    if (dense && e == hipSuccess) {
+        e = alloc(reinterpret_cast<void**>(&w->part), pbytes);
+        w->part_splits = splits;
+    }
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&w->host_params), RP_COUNT * 8);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&w->host_flags), B * 4);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&w->host_steps), B * 8 * 2);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&w->host_flags), bcap * 4);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&w->host_steps), bcap * 8 * 2);
     if (e != hipSuccess) {
         set_error("workspace allocation (%lld bytes): %s", static_cast<long long>(bytes),
                   hipGetErrorString(e));

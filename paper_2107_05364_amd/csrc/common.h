@@ -123,6 +123,7 @@ struct Problem {
     double* e_vk = nullptr;     // [n] V_a K_a
     double* x_w = nullptr;      // per face A S/d (exchange energy), same CSR
     int64_t nnz = 0;
+    int shape = -1;             // field-kernel launch shape (-1: default for n)
     int64_t bytes = 0;          // device bytes owned by the problem
     std::unique_ptr<Workspace> ws;
     DevProblem dev() const;
@@ -142,8 +143,9 @@ struct Workspace {
     // GEMM operands and partial sums (batched path)
     void* xh = nullptr;       // right operand hi  [B][ld3]
     void* xl = nullptr;       // right operand lo
-    float* part = nullptr;    // split-K partials [S][B][3np]
+    float* part = nullptr;    // split-K partials [S][bpad][rows]
     int64_t part_splits = 0;
+    int64_t bpad = 0;         // states in the GEMM operand buffers (multiple of 16)
     // per-state control
     double* t = nullptr;
     double* h = nullptr;      // step used by the current attempt (0: frozen)
@@ -197,6 +199,15 @@ struct EpiArgs {
 // H (or a stage) for B states whose inputs X are padded internal buffers.
 tm_status launch_field(const Problem* p, Epi mode, int64_t B, const float* X, const EpiArgs& e,
                        hipStream_t s);
+// Batched (MFMA GEMM) path for DENSE9 operators (gemm.hip).
+int gemm_state_tiles(int64_t B);
+int64_t gemm_splits(const Problem* p);
+tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const float* X,
+                               const EpiArgs& e, hipStream_t s);
+constexpr int64_t kMaxGemmStates = 128;
+
+constexpr int kNumShapes = 12;
+int default_shape(int64_t n);
 tm_status launch_pack(const float* src, int64_t B, int64_t n, int64_t np, float* dst, hipStream_t s);
 tm_status launch_control(Workspace* w, int64_t B, int integ, hipStream_t s);
 tm_status launch_commit(const Problem* p, Workspace* w, int64_t B, hipStream_t s);

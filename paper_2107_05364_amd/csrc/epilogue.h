@@ -1,0 +1,130 @@
+// Per-tile completion of a right-hand-side evaluation, shared by the fused
+// matvec kernel and the elementwise pass of the batched (GEMM) path.
+//
+// Given H_d of tile a in state s, adds the local effective-field terms
+// (paper Sec. 2.3: exchange sum_b w_ab (m_b - m_a) with w_ab = 2A S_ab /
+// (mu0 Ms_a V_a d_ab) and zero flux through free faces; uniaxial anisotropy
+// (2K/(mu0 Ms)) (m.e) e; applied field), evaluates the Landau-Lifshitz
+// right-hand side -c1 m x H - c2 m x (m x H) (Sec. 2.1) and completes the
+// requested Runge-Kutta stage (Sec. 3.1).
+#pragma once
+
+#include "common.h"
+
+namespace tmag {
+namespace {
+
+// Dormand-Prince 5(4): fifth-order weights b and embedded fourth-order b*;
+// the error weights are b - b*.
+__device__ constexpr double kDpB[7] = {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192,
+                                       -2187.0 / 6784, 11.0 / 84, 0.0};
+__device__ constexpr double kDpBs[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640,
+                                        -92097.0 / 339200, 187.0 / 2100, 1.0 / 40};
+
+template <Epi MODE>
+__device__ void finish_tile(const DevProblem& P, const float* __restrict__ X, int64_t sx,
+                            const EpiArgs& E, int s, int a, float hd0, float hd1, float hd2,
+                            double* rmax, double* dmax) {
+    const int64_t o = s * sx + 3 * static_cast<int64_t>(a);
+    if constexpr (MODE == Epi::HD) {
+        float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
+        out[0] = hd0; out[1] = hd1; out[2] = hd2;
+        return;
+    } else {
+        const float* x = X + s * sx;
+        const float m0 = x[3 * a], m1 = x[3 * a + 1], m2 = x[3 * a + 2];
+        float H0 = hd0, H1 = hd1, H2 = hd2;
+        const int32_t j0 = P.nbr_ptr[a], j1 = P.nbr_ptr[a + 1];
+        for (int32_t j = j0; j < j1; ++j) {
+            const int32_t b = P.nbr_idx[j];
+            const float w = P.nbr_w[j];
+            H0 += w * (x[3 * b] - m0);
+            H1 += w * (x[3 * b + 1] - m1);
+            H2 += w * (x[3 * b + 2] - m2);
+        }
+        if (P.ku) {
+            const float e0 = P.easy[3 * a], e1 = P.easy[3 * a + 1], e2 = P.easy[3 * a + 2];
+            const float g = P.ku[a] * (m0 * e0 + m1 * e1 + m2 * e2);
+            H0 += g * e0; H1 += g * e1; H2 += g * e2;
+        }
+        if (E.Ha) {
+            H0 += E.Ha[3 * s]; H1 += E.Ha[3 * s + 1]; H2 += E.Ha[3 * s + 2];
+        }
+        if constexpr (MODE == Epi::HEFF) {
+            float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
+            out[0] = H0; out[1] = H1; out[2] = H2;
+            return;
+        } else {
+            // m x H and m x (m x H)
+            const float p0 = m1 * H2 - m2 * H1, p1 = m2 * H0 - m0 * H2, p2 = m0 * H1 - m1 * H0;
+            const float q0 = m1 * p2 - m2 * p1, q1 = m2 * p0 - m0 * p2, q2 = m0 * p1 - m1 * p0;
+            const float k0 = -P.c1 * p0 - P.c2 * q0;
+            const float k1 = -P.c1 * p1 - P.c2 * q1;
+            const float k2 = -P.c1 * p2 - P.c2 * q2;
+            if constexpr (MODE == Epi::DMDT) {
+                float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
+                out[0] = k0; out[1] = k1; out[2] = k2;
+                return;
+            } else if constexpr (MODE == Epi::STAGE) {
+                float* out = E.out + o;
+                out[0] = k0; out[1] = k1; out[2] = k2;
+                const float h = static_cast<float>(E.h[s]);
+                float c0 = E.coef[E.nprev] * k0, c1 = E.coef[E.nprev] * k1,
+                      c2 = E.coef[E.nprev] * k2;
+                for (int j = 0; j < E.nprev; ++j) {
+                    const float* kj = E.kprev[j] + o;
+                    c0 += E.coef[j] * kj[0]; c1 += E.coef[j] * kj[1]; c2 += E.coef[j] * kj[2];
+                }
+                const float* y = E.y + o;
+                float* yn = E.ynext + o;
+                yn[0] = y[0] + h * c0; yn[1] = y[1] + h * c1; yn[2] = y[2] + h * c2;
+                return;
+            } else if constexpr (MODE == Epi::RK4_FINAL) {
+                const double hd = E.h[s];
+                if (hd == 0.0) return;
+                const float h = static_cast<float>(hd);
+                float c0 = E.coef[E.nprev] * k0, c1 = E.coef[E.nprev] * k1,
+                      c2 = E.coef[E.nprev] * k2;
+                for (int j = 0; j < E.nprev; ++j) {
+                    const float* kj = E.kprev[j] + o;
+                    c0 += E.coef[j] * kj[0]; c1 += E.coef[j] * kj[1]; c2 += E.coef[j] * kj[2];
+                }
+                float* y = E.y_mut + o;
+                float v0 = y[0] + h * c0, v1 = y[1] + h * c1, v2 = y[2] + h * c2;
+                if (E.renorm) {
+                    const float r = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+                    v0 *= r; v1 *= r; v2 *= r;
+                }
+                y[0] = v0; y[1] = v1; y[2] = v2;
+                return;
+            } else {  // DP_LAST: k7 at the fifth-order solution, float64 error estimate
+                float* out = E.out + o;
+                out[0] = k0; out[1] = k1; out[2] = k2;
+                const double h = E.h[s];
+                double e0 = (kDpB[6] - kDpBs[6]) * k0, e1 = (kDpB[6] - kDpBs[6]) * k1,
+                       e2 = (kDpB[6] - kDpBs[6]) * k2;
+#pragma unroll
+                for (int j = 0; j < 6; ++j) {
+                    const double w = kDpB[j] - kDpBs[j];
+                    const float* kj = E.kprev[j] + o;
+                    e0 += w * kj[0]; e1 += w * kj[1]; e2 += w * kj[2];
+                }
+                const double atol = E.params[RP_ATOL], rtol = E.params[RP_RTOL];
+                const float* y = E.y + o;
+                const double s0 = atol + rtol * fmax(fabs((double)y[0]), fabs((double)m0));
+                const double s1 = atol + rtol * fmax(fabs((double)y[1]), fabs((double)m1));
+                const double s2 = atol + rtol * fmax(fabs((double)y[2]), fabs((double)m2));
+                const double r0 = fabs(h * e0) / s0, r1 = fabs(h * e1) / s1, r2 = fabs(h * e2) / s2;
+                // a NaN anywhere must win the max: map it to +inf (fmax drops NaN)
+                const bool bad = !(r0 == r0) || !(r1 == r1) || !(r2 == r2);
+                *rmax = bad ? INFINITY : fmax(r0, fmax(r1, r2));
+                const double d = sqrt((double)k0 * k0 + (double)k1 * k1 + (double)k2 * k2);
+                *dmax = (d == d) ? d : INFINITY;
+                return;
+            }
+        }
+    }
+}
+
+}  // namespace
+}  // namespace tmag

@@ -20,6 +20,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "epilogue.h"
 
 namespace tmag {
 namespace {
@@ -34,120 +35,23 @@ struct MvArgs {
     int64_t sx;       // 3 * np
 };
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 __device__ inline float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
 
-// Dormand-Prince 5(4): fifth-order weights b and embedded fourth-order b*;
-// the error weights are b - b*.
-__device__ constexpr double kDpB[7] = {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192,
-                                       -2187.0 / 6784, 11.0 / 84, 0.0};
-__device__ constexpr double kDpBs[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640,
-                                        -92097.0 / 339200, 187.0 / 2100, 1.0 / 40};
-
-template <Epi MODE>
-__device__ void finish_tile(const DevProblem& P, const MvArgs& M, const EpiArgs& E, int s, int a,
-                            float hd0, float hd1, float hd2, double* rmax, double* dmax) {
-    const int64_t o = s * M.sx + 3 * static_cast<int64_t>(a);
-    if constexpr (MODE == Epi::HD) {
-        float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
-        out[0] = hd0; out[1] = hd1; out[2] = hd2;
-        return;
+// Operator stream: each entry is read exactly once per launch, so NT = 1
+// marks the loads nontemporal (the cache may drop the lines first).
+template <int NT>
+__device__ inline float4 ldT(const float* p) {
+    if constexpr (NT) {
+        const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+        return make_float4(v.x, v.y, v.z, v.w);
     } else {
-        const float* x = M.X + s * M.sx;
-        const float m0 = x[3 * a], m1 = x[3 * a + 1], m2 = x[3 * a + 2];
-        float H0 = hd0, H1 = hd1, H2 = hd2;
-        const int32_t j0 = P.nbr_ptr[a], j1 = P.nbr_ptr[a + 1];
-        for (int32_t j = j0; j < j1; ++j) {
-            const int32_t b = P.nbr_idx[j];
-            const float w = P.nbr_w[j];
-            H0 += w * (x[3 * b] - m0);
-            H1 += w * (x[3 * b + 1] - m1);
-            H2 += w * (x[3 * b + 2] - m2);
-        }
-        if (P.ku) {
-            const float e0 = P.easy[3 * a], e1 = P.easy[3 * a + 1], e2 = P.easy[3 * a + 2];
-            const float g = P.ku[a] * (m0 * e0 + m1 * e1 + m2 * e2);
-            H0 += g * e0; H1 += g * e1; H2 += g * e2;
-        }
-        if (E.Ha) {
-            H0 += E.Ha[3 * s]; H1 += E.Ha[3 * s + 1]; H2 += E.Ha[3 * s + 2];
-        }
-        if constexpr (MODE == Epi::HEFF) {
-            float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
-            out[0] = H0; out[1] = H1; out[2] = H2;
-            return;
-        } else {
-            // m x H and m x (m x H)
-            const float p0 = m1 * H2 - m2 * H1, p1 = m2 * H0 - m0 * H2, p2 = m0 * H1 - m1 * H0;
-            const float q0 = m1 * p2 - m2 * p1, q1 = m2 * p0 - m0 * p2, q2 = m0 * p1 - m1 * p0;
-            const float k0 = -P.c1 * p0 - P.c2 * q0;
-            const float k1 = -P.c1 * p1 - P.c2 * q1;
-            const float k2 = -P.c1 * p2 - P.c2 * q2;
-            if constexpr (MODE == Epi::DMDT) {
-                float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
-                out[0] = k0; out[1] = k1; out[2] = k2;
-                return;
-            } else if constexpr (MODE == Epi::STAGE) {
-                float* out = E.out + o;
-                out[0] = k0; out[1] = k1; out[2] = k2;
-                const float h = static_cast<float>(E.h[s]);
-                float c0 = E.coef[E.nprev] * k0, c1 = E.coef[E.nprev] * k1,
-                      c2 = E.coef[E.nprev] * k2;
-                for (int j = 0; j < E.nprev; ++j) {
-                    const float* kj = E.kprev[j] + o;
-                    c0 += E.coef[j] * kj[0]; c1 += E.coef[j] * kj[1]; c2 += E.coef[j] * kj[2];
-                }
-                const float* y = E.y + o;
-                float* yn = E.ynext + o;
-                yn[0] = y[0] + h * c0; yn[1] = y[1] + h * c1; yn[2] = y[2] + h * c2;
-                return;
-            } else if constexpr (MODE == Epi::RK4_FINAL) {
-                const double hd = E.h[s];
-                if (hd == 0.0) return;
-                const float h = static_cast<float>(hd);
-                float c0 = E.coef[E.nprev] * k0, c1 = E.coef[E.nprev] * k1,
-                      c2 = E.coef[E.nprev] * k2;
-                for (int j = 0; j < E.nprev; ++j) {
-                    const float* kj = E.kprev[j] + o;
-                    c0 += E.coef[j] * kj[0]; c1 += E.coef[j] * kj[1]; c2 += E.coef[j] * kj[2];
-                }
-                float* y = E.y_mut + o;
-                float v0 = y[0] + h * c0, v1 = y[1] + h * c1, v2 = y[2] + h * c2;
-                if (E.renorm) {
-                    const float r = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
-                    v0 *= r; v1 *= r; v2 *= r;
-                }
-                y[0] = v0; y[1] = v1; y[2] = v2;
-                return;
-            } else {  // DP_LAST: k7 at the fifth-order solution, float64 error estimate
-                float* out = E.out + o;
-                out[0] = k0; out[1] = k1; out[2] = k2;
-                const double h = E.h[s];
-                double e0 = (kDpB[6] - kDpBs[6]) * k0, e1 = (kDpB[6] - kDpBs[6]) * k1,
-                       e2 = (kDpB[6] - kDpBs[6]) * k2;
-#pragma unroll
-                for (int j = 0; j < 6; ++j) {
-                    const double w = kDpB[j] - kDpBs[j];
-                    const float* kj = E.kprev[j] + o;
-                    e0 += w * kj[0]; e1 += w * kj[1]; e2 += w * kj[2];
-                }
-                const double atol = E.params[RP_ATOL], rtol = E.params[RP_RTOL];
-                const float* y = E.y + o;
-                const double s0 = atol + rtol * fmax(fabs((double)y[0]), fabs((double)m0));
-                const double s1 = atol + rtol * fmax(fabs((double)y[1]), fabs((double)m1));
-                const double s2 = atol + rtol * fmax(fabs((double)y[2]), fabs((double)m2));
-                const double r0 = fabs(h * e0) / s0, r1 = fabs(h * e1) / s1, r2 = fabs(h * e2) / s2;
-                // a NaN anywhere must win the max: map it to +inf (fmax drops NaN)
-                const bool bad = !(r0 == r0) || !(r1 == r1) || !(r2 == r2);
-                *rmax = bad ? INFINITY : fmax(r0, fmax(r1, r2));
-                const double d = sqrt((double)k0 * k0 + (double)k1 * k1 + (double)k2 * k2);
-                *dmax = (d == d) ? d : INFINITY;
-                return;
-            }
-        }
+        return *reinterpret_cast<const float4*>(p);
     }
 }
 
-template <int BLOCK, int TT, Epi MODE>
+template <int BLOCK, int TT, int NT, Epi MODE>
 __global__ __launch_bounds__(BLOCK) void k_field(DevProblem P, MvArgs M, EpiArgs E) {
     constexpr int NW = BLOCK / 64;
     const int s = blockIdx.y;
@@ -169,9 +73,10 @@ __global__ __launch_bounds__(BLOCK) void k_field(DevProblem P, MvArgs M, EpiArgs
 #pragma unroll
         for (int t = 0; t < TT; ++t) {
             const float* tp = M.T + rowoff[t] + b;
-            const float4 xx = ld4(tp), xy = ld4(tp + M.plane), xz = ld4(tp + 2 * M.plane);
-            const float4 yy = ld4(tp + 3 * M.plane), yz = ld4(tp + 4 * M.plane),
-                         zz = ld4(tp + 5 * M.plane);
+            const float4 xx = ldT<NT>(tp), xy = ldT<NT>(tp + M.plane),
+                         xz = ldT<NT>(tp + 2 * M.plane);
+            const float4 yy = ldT<NT>(tp + 3 * M.plane), yz = ldT<NT>(tp + 4 * M.plane),
+                         zz = ldT<NT>(tp + 5 * M.plane);
             float hx = acc[t][0], hy = acc[t][1], hz = acc[t][2];
             hx += xx.x * mx0 + xy.x * my0 + xz.x * mz0;
             hy += xy.x * mx0 + yy.x * my0 + yz.x * mz0;
@@ -218,7 +123,7 @@ __global__ __launch_bounds__(BLOCK) void k_field(DevProblem P, MvArgs M, EpiArgs
             for (int w = 0; w < NW; ++w) v += red[w][3 * lane + c];
             h[c] = -v;
         }
-        finish_tile<MODE>(P, M, E, s, a0 + lane, h[0], h[1], h[2], &rmax, &dmax);
+        finish_tile<MODE>(P, M.X, M.sx, E, s, a0 + lane, h[0], h[1], h[2], &rmax, &dmax);
     }
     if constexpr (MODE == Epi::DP_LAST) {
 #pragma unroll
@@ -233,20 +138,22 @@ __global__ __launch_bounds__(BLOCK) void k_field(DevProblem P, MvArgs M, EpiArgs
     }
 }
 
-template <int BLOCK, int TT>
+template <int BLOCK, int TT, int NT>
 tm_status launch_tt(const DevProblem& P, const MvArgs& M, Epi mode, int64_t B, const EpiArgs& e,
                     hipStream_t st) {
     const dim3 grid(static_cast<unsigned>((M.n + TT - 1) / TT), static_cast<unsigned>(B));
     const dim3 block(BLOCK);
     switch (mode) {
-        case Epi::HD: k_field<BLOCK, TT, Epi::HD><<<grid, block, 0, st>>>(P, M, e); break;
-        case Epi::HEFF: k_field<BLOCK, TT, Epi::HEFF><<<grid, block, 0, st>>>(P, M, e); break;
-        case Epi::DMDT: k_field<BLOCK, TT, Epi::DMDT><<<grid, block, 0, st>>>(P, M, e); break;
-        case Epi::STAGE: k_field<BLOCK, TT, Epi::STAGE><<<grid, block, 0, st>>>(P, M, e); break;
+        case Epi::HD: k_field<BLOCK, TT, NT, Epi::HD><<<grid, block, 0, st>>>(P, M, e); break;
+        case Epi::HEFF: k_field<BLOCK, TT, NT, Epi::HEFF><<<grid, block, 0, st>>>(P, M, e); break;
+        case Epi::DMDT: k_field<BLOCK, TT, NT, Epi::DMDT><<<grid, block, 0, st>>>(P, M, e); break;
+        case Epi::STAGE: k_field<BLOCK, TT, NT, Epi::STAGE><<<grid, block, 0, st>>>(P, M, e); break;
         case Epi::RK4_FINAL:
-            k_field<BLOCK, TT, Epi::RK4_FINAL><<<grid, block, 0, st>>>(P, M, e);
+            k_field<BLOCK, TT, NT, Epi::RK4_FINAL><<<grid, block, 0, st>>>(P, M, e);
             break;
-        case Epi::DP_LAST: k_field<BLOCK, TT, Epi::DP_LAST><<<grid, block, 0, st>>>(P, M, e); break;
+        case Epi::DP_LAST:
+            k_field<BLOCK, TT, NT, Epi::DP_LAST><<<grid, block, 0, st>>>(P, M, e);
+            break;
     }
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
@@ -432,8 +339,11 @@ DevProblem Problem::dev() const {
 tm_status launch_field(const Problem* p, Epi mode, int64_t B, const float* X, const EpiArgs& e,
                        hipStream_t s) {
     const Tensor* T = p->T;
+    if (T->layout == TM_LAYOUT_DENSE9 && T->prec != TM_PREC_FP64)
+        return launch_field_batched(p, mode, B, X, e, s);
     TM_REQUIRE(T->layout == TM_LAYOUT_SYM6 && T->prec == TM_PREC_FP32, TM_EINVAL,
-               "the single-state field path needs an FP32 SYM6 operator");
+               "field evaluation needs an FP32 SYM6 operator or a DENSE9 FP32 / BF16X3 / "
+               "FP16X3 operator (FP64 operators are for verification)");
     MvArgs M;
     M.n = static_cast<int32_t>(p->n);
     M.ld = T->ld;
@@ -443,11 +353,33 @@ tm_status launch_field(const Problem* p, Epi mode, int64_t B, const float* X, co
     M.X = X;
     M.sx = 3 * p->np;
     const DevProblem P = p->dev();
+    const int shape = p->shape >= 0 ? p->shape : default_shape(p->n);
+    switch (shape) {
+        case 0: return launch_tt<64, 2, 0>(P, M, mode, B, e, s);
+        case 1: return launch_tt<128, 2, 0>(P, M, mode, B, e, s);
+        case 2: return launch_tt<128, 4, 0>(P, M, mode, B, e, s);
+        case 3: return launch_tt<256, 2, 0>(P, M, mode, B, e, s);
+        case 4: return launch_tt<256, 4, 0>(P, M, mode, B, e, s);
+        case 5: return launch_tt<256, 8, 0>(P, M, mode, B, e, s);
+        case 6: return launch_tt<512, 4, 0>(P, M, mode, B, e, s);
+        case 7: return launch_tt<512, 8, 0>(P, M, mode, B, e, s);
+        case 8: return launch_tt<256, 2, 1>(P, M, mode, B, e, s);
+        case 9: return launch_tt<256, 4, 1>(P, M, mode, B, e, s);
+        case 10: return launch_tt<128, 1, 0>(P, M, mode, B, e, s);
+        case 11: return launch_tt<256, 1, 0>(P, M, mode, B, e, s);
+        default: break;
+    }
+    set_error("unknown field-kernel shape %d", shape);
+    return TM_EINVAL;
+}
+
+int default_shape(int64_t n) {
     // narrow workgroups for short rows so that every lane streams data
-    if (M.ld <= 256) return launch_tt<64, 2>(P, M, mode, B, e, s);
-    if (M.ld <= 1024) return launch_tt<128, 2>(P, M, mode, B, e, s);
-    if (p->n <= 4096) return launch_tt<256, 4>(P, M, mode, B, e, s);
-    return launch_tt<256, 8>(P, M, mode, B, e, s);
+    const int64_t ld = round_up(n, 4);
+    if (ld <= 256) return 0;
+    if (ld <= 1024) return 1;
+    if (n <= 4096) return 4;
+    return 5;
 }
 
 tm_status launch_pack(const float* src, int64_t B, int64_t n, int64_t np, float* dst,

@@ -1,0 +1,342 @@
+// Batched demag product on the matrix cores: many states that share one
+// geometry turn H_d = -N (Ms m) into one GEMM per right-hand-side evaluation
+// (paper Sec. 3.1: the demag operator is a dense 3N x 3N matrix applied to
+// the 3N-vector m; here to B such vectors at once).
+//
+//   C[r][s] = sum_k A[r][k] X[s][k],  A = stored operator (DENSE9, row-major,
+//   K contiguous), X[s][3b+j] = (Ms_b / Ms_ref) m_{s,b,j}, H_d = -Ms_ref C.
+//
+// Precisions (accumulation always float32):
+//   FP32   : v_mfma_f32_16x16x4_f32, A and X in float32;
+//   BF16X3 : A = Ah + Al, X = Xh + Xl in bf16; C = Ah Xh + Ah Xl + Al Xh
+//            with v_mfma_f32_16x16x32_bf16 (the lo*lo term is below the
+//            float32 rounding of the result);
+//   FP16X3 : as BF16X3 with fp16 and a power-of-two scale per operator row
+//            (the row maximum maps to 2^13..2^14, far entries stay normal);
+//            the scale is removed in the GEMM epilogue.
+//
+// Work split: a workgroup (4 waves) owns 128 operator rows x all states and
+// one K range (split-K); each wave owns two 16-row MFMA tiles.  The X chunk
+// of the K range is staged once per workgroup in LDS (row-padded so the
+// 16-byte reads of 16 lanes hit distinct banks) and reused by the 8 row
+// tiles; operator rows are read straight from memory, 16 bytes per lane,
+// each 128-byte line fully used.  Partial sums go to part[split][state][row]
+// and a fixed-order elementwise pass adds the splits, finishes the
+// effective field and the Runge-Kutta stage per tile.  The summation order
+// depends only on the problem size, never on the batch.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "common.h"
+#include "epilogue.h"
+
+namespace tmag {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+constexpr int kRowsPerBlock = 128;  // 4 waves x 2 tiles x 16 rows
+constexpr int kKC = 64;             // K elements staged per chunk
+
+struct GemmArgs {
+    int64_t ld;         // K extent (= 3 np) and operator row stride
+    int64_t bpad;       // padded state count (multiple of 16)
+    const void* Ahi;    // FP32: the operator; split: hi part
+    const void* Alo;    // split: lo part
+    const float* rscale;// FP16X3: 1/scale per row
+    const void* Xhi;    // [bpad][ld]
+    const void* Xlo;
+    float* part;        // [splits][bpad][rows]
+    int64_t rows;       // padded operator rows (multiple of 128)
+    int64_t kper;       // K elements per split (multiple of kKC)
+};
+
+template <int PREC>
+struct Elt;
+template <>
+struct Elt<0> { using T = float; static constexpr int kPerLane = 4; };
+template <>
+struct Elt<1> { using T = __bf16; static constexpr int kPerLane = 8; };
+template <>
+struct Elt<2> { using T = _Float16; static constexpr int kPerLane = 8; };
+
+// LDS row of one state's chunk: kKC elements + 16 bytes of padding
+template <int PREC>
+constexpr int lds_row_bytes() { return kKC * static_cast<int>(sizeof(typename Elt<PREC>::T)) + 16; }
+
+template <int PREC, int NST>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
+    using T = typename Elt<PREC>::T;
+    constexpr bool SPLIT = PREC != 0;
+    constexpr int RB = lds_row_bytes<PREC>();
+    constexpr int NS = NST * 16;
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    unsigned char* xh_s = lds;
+    unsigned char* xl_s = lds + NS * RB;
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, j = lane & 15;
+    const int64_t rowbase = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock + wave * 32;
+    const int64_t kb = static_cast<int64_t>(blockIdx.y) * G.kper;
+    const int64_t ke = min(kb + G.kper, G.ld);
+
+    v4f acc[2][NST];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int s = 0; s < NST; ++s) acc[r][s] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    const T* Ah = static_cast<const T*>(G.Ahi);
+    const T* Al = static_cast<const T*>(G.Alo);
+    const T* Xh = static_cast<const T*>(G.Xhi);
+    const T* Xl = static_cast<const T*>(G.Xlo);
+    constexpr int CHUNK16 = kKC * static_cast<int>(sizeof(T)) / 16;  // 16-byte pieces per state row
+
+    for (int64_t k0 = kb; k0 < ke; k0 += kKC) {
+        // stage X[0..NS)[k0..k0+kKC) into LDS (16-byte pieces)
+        __syncthreads();
+        for (int q = threadIdx.x; q < NS * CHUNK16; q += 256) {
+            const int st = q / CHUNK16, pc = q % CHUNK16;
+            const int64_t off = static_cast<int64_t>(st) * G.ld + k0;
+            const uint4 vh = *reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(Xh + off) + 16 * pc);
+            *reinterpret_cast<uint4*>(xh_s + st * RB + 16 * pc) = vh;
+            if constexpr (SPLIT) {
+                const uint4 vl = *reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(Xl + off) + 16 * pc);
+                *reinterpret_cast<uint4*>(xl_s + st * RB + 16 * pc) = vl;
+            }
+        }
+        __syncthreads();
+        if constexpr (PREC == 0) {
+            // 4 sub-steps of 16 k; lane group g covers k = 16 sub + 4 g + q
+#pragma unroll
+            for (int sub = 0; sub < 4; ++sub) {
+                const int kk = 16 * sub + 4 * g;
+                float4 a[2];
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt)
+                    a[rt] = *reinterpret_cast<const float4*>(Ah + (rowbase + 16 * rt + j) * G.ld + k0 + kk);
+#pragma unroll
+                for (int st = 0; st < NST; ++st) {
+                    const float4 b = *reinterpret_cast<const float4*>(xh_s + (16 * st + j) * RB + 4 * kk);
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt) {
+                        acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].x, b.x, acc[rt][st], 0, 0, 0);
+                        acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].y, b.y, acc[rt][st], 0, 0, 0);
+                        acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].z, b.z, acc[rt][st], 0, 0, 0);
+                        acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].w, b.w, acc[rt][st], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+            using V8 = typename std::conditional<PREC == 1, v8bf, v8h>::type;
+            // 2 sub-steps of 32 k; lane group g covers k = 32 sub + 8 g .. + 7
+#pragma unroll
+            for (int sub = 0; sub < 2; ++sub) {
+                const int kk = 32 * sub + 8 * g;
+                V8 ah[2], al[2];
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt) {
+                    const int64_t off = (rowbase + 16 * rt + j) * G.ld + k0 + kk;
+                    ah[rt] = *reinterpret_cast<const V8*>(Ah + off);
+                    al[rt] = *reinterpret_cast<const V8*>(Al + off);
+                }
+#pragma unroll
+                for (int st = 0; st < NST; ++st) {
+                    const V8 bh = *reinterpret_cast<const V8*>(xh_s + (16 * st + j) * RB + 2 * kk);
+                    const V8 bl = *reinterpret_cast<const V8*>(xl_s + (16 * st + j) * RB + 2 * kk);
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt) {
+                        if constexpr (PREC == 1) {
+                            acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rt], bh, acc[rt][st], 0, 0, 0);
+                            acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rt], bl, acc[rt][st], 0, 0, 0);
+                            acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rt], bh, acc[rt][st], 0, 0, 0);
+                        } else {
+                            acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rt], bh, acc[rt][st], 0, 0, 0);
+                            acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rt], bl, acc[rt][st], 0, 0, 0);
+                            acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[rt], bh, acc[rt][st], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // D[4 g + r][j] of tile (rt, st) -> part[split][state 16 st + j][row rowbase + 16 rt + 4 g + r]
+    float* out = G.part + static_cast<int64_t>(blockIdx.y) * G.bpad * G.rows;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        const int64_t r0 = rowbase + 16 * rt + 4 * g;
+        float4 sc = make_float4(1.f, 1.f, 1.f, 1.f);
+        if constexpr (PREC == 2) sc = *reinterpret_cast<const float4*>(G.rscale + r0);
+#pragma unroll
+        for (int st = 0; st < NST; ++st) {
+            const v4f v = acc[rt][st];
+            *reinterpret_cast<float4*>(out + (16 * st + j) * G.rows + r0) =
+                make_float4(v.x * sc.x, v.y * sc.y, v.z * sc.z, v.w * sc.w);
+        }
+    }
+}
+
+// Right operand from the (padded) stage input: (Ms_b / Ms_ref) m, as float32
+// or split into hi + lo.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_prep(int64_t B, int64_t ld, int32_t n, const float* __restrict__ Y,
+                                              const float* __restrict__ Ms, float inv_ref,
+                                              void* __restrict__ xh, void* __restrict__ xl) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= B * ld) return;
+    const int64_t k = i % ld;
+    const int64_t b = k / 3;
+    const float v = (b < n) ? Y[i] * (Ms[b] * inv_ref) : 0.0f;
+    if constexpr (PREC == 0) {
+        static_cast<float*>(xh)[i] = v;
+    } else if constexpr (PREC == 1) {
+        const __bf16 h = static_cast<__bf16>(v);
+        static_cast<__bf16*>(xh)[i] = h;
+        static_cast<__bf16*>(xl)[i] = static_cast<__bf16>(v - static_cast<float>(h));
+    } else {
+        const _Float16 h = static_cast<_Float16>(v);
+        static_cast<_Float16*>(xh)[i] = h;
+        static_cast<_Float16*>(xl)[i] = static_cast<_Float16>(v - static_cast<float>(h));
+    }
+}
+
+// Sum of the split-K partials in fixed order, then the per-tile finish.
+template <Epi MODE>
+__global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __restrict__ part,
+                                                int64_t splits, int64_t bpad, int64_t rows,
+                                                float scale, const float* __restrict__ X, int64_t sx,
+                                                EpiArgs E) {
+    const int s = blockIdx.y;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    double rmax = 0.0, dmax = 0.0;
+    if (a < P.n) {
+        float h0 = 0.f, h1 = 0.f, h2 = 0.f;
+        for (int64_t sp = 0; sp < splits; ++sp) {
+            const float* pp = part + (sp * bpad + s) * rows + 3 * static_cast<int64_t>(a);
+            h0 += pp[0]; h1 += pp[1]; h2 += pp[2];
+        }
+        finish_tile<MODE>(P, X, sx, E, s, a, -scale * h0, -scale * h1, -scale * h2, &rmax, &dmax);
+    }
+    if constexpr (MODE == Epi::DP_LAST) {
+        __shared__ double red[2][4];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
+            dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
+        }
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        if (lane == 0) {
+            red[0][wave] = rmax;
+            red[1][wave] = dmax;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < 4; ++w) {
+                rmax = fmax(rmax, red[0][w]);
+                dmax = fmax(dmax, red[1][w]);
+            }
+            atomicMax(E.err + s, static_cast<unsigned long long>(__double_as_longlong(rmax)));
+            atomicMax(E.dmx + s, static_cast<unsigned long long>(__double_as_longlong(dmax)));
+        }
+    }
+}
+
+template <int PREC, int NST>
+tm_status launch_gemm_t(const GemmArgs& G, int64_t rowblocks, int64_t splits, hipStream_t s) {
+    const size_t lds = static_cast<size_t>(NST * 16) * lds_row_bytes<PREC>() * (PREC ? 2 : 1);
+    k_gemm<PREC, NST><<<dim3(static_cast<unsigned>(rowblocks), static_cast<unsigned>(splits)), 256, lds, s>>>(G);
+    TM_TRY_HIP(hipGetLastError());
+    return TM_OK;
+}
+
+template <int PREC>
+tm_status launch_gemm_p(int nst, const GemmArgs& G, int64_t rowblocks, int64_t splits, hipStream_t s) {
+    switch (nst) {
+        case 1: return launch_gemm_t<PREC, 1>(G, rowblocks, splits, s);
+        case 2: return launch_gemm_t<PREC, 2>(G, rowblocks, splits, s);
+        case 4: return launch_gemm_t<PREC, 4>(G, rowblocks, splits, s);
+        case 8: return launch_gemm_t<PREC, 8>(G, rowblocks, splits, s);
+        default: break;
+    }
+    set_error("batched product: unsupported state-tile count %d", nst);
+    return TM_EINVAL;
+}
+
+}  // namespace
+
+int gemm_state_tiles(int64_t B) {
+    const int64_t t = (B + 15) / 16;
+    return t <= 1 ? 1 : t <= 2 ? 2 : t <= 4 ? 4 : 8;
+}
+
+int64_t gemm_splits(const Problem* p) {
+    const int64_t rowblocks = p->T->rows / kRowsPerBlock;
+    const int64_t kchunks = p->T->ld / kKC;
+    int64_t s = (512 + rowblocks - 1) / rowblocks;
+    return std::max<int64_t>(1, std::min<int64_t>(s, std::min<int64_t>(kchunks, 16)));
+}
+
+tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const float* X,
+                               const EpiArgs& e, hipStream_t s) {
+    const Tensor* T = p->T;
+    Workspace* w = p->ws.get();
+    TM_REQUIRE(w && w->part && B <= 128 && w->bpad >= 16 * gemm_state_tiles(B), TM_EINVAL,
+               "batched product: workspace not prepared for %lld states", static_cast<long long>(B));
+    const int prec = T->prec == TM_PREC_FP32 ? 0 : T->prec == TM_PREC_BF16X3 ? 1 : 2;
+    const int64_t ld = T->ld;
+    // right operand
+    const void* xh = X;
+    const void* xl = nullptr;
+    if (prec != 0 || !p->uniform_ms) {
+        const int64_t cnt = B * ld;
+        const unsigned grid = static_cast<unsigned>((cnt + 255) / 256);
+        const float inv = static_cast<float>(1.0 / p->ms_ref);
+        if (prec == 0)
+            k_prep<0><<<grid, 256, 0, s>>>(B, ld, static_cast<int32_t>(p->n), X, p->Ms, inv, w->xh, nullptr);
+        else if (prec == 1)
+            k_prep<1><<<grid, 256, 0, s>>>(B, ld, static_cast<int32_t>(p->n), X, p->Ms, inv, w->xh, w->xl);
+        else
+            k_prep<2><<<grid, 256, 0, s>>>(B, ld, static_cast<int32_t>(p->n), X, p->Ms, inv, w->xh, w->xl);
+        TM_TRY_HIP(hipGetLastError());
+        xh = w->xh;
+        xl = w->xl;
+    }
+    GemmArgs G;
+    G.ld = ld;
+    G.bpad = w->bpad;
+    G.Ahi = T->data;
+    G.Alo = T->lo;
+    G.rscale = T->rscale;
+    G.Xhi = xh;
+    G.Xlo = xl;
+    G.part = w->part;
+    G.rows = T->rows;
+    const int64_t splits = w->part_splits;
+    G.kper = round_up((ld + splits - 1) / splits, kKC);
+    const int64_t used_splits = (ld + G.kper - 1) / G.kper;
+    const int64_t rowblocks = T->rows / kRowsPerBlock;
+    const int nst = gemm_state_tiles(B);
+    tm_status st = prec == 0   ? launch_gemm_p<0>(nst, G, rowblocks, used_splits, s)
+                   : prec == 1 ? launch_gemm_p<1>(nst, G, rowblocks, used_splits, s)
+                               : launch_gemm_p<2>(nst, G, rowblocks, used_splits, s);
+    if (st != TM_OK) return st;
+    // X holds (Ms_b / Ms_ref) m (or m itself when Ms is uniform): H_d = -Ms_ref C
+    const float scale = static_cast<float>(p->ms_ref);
+    const DevProblem P = p->dev();
+    const dim3 grid(static_cast<unsigned>((p->n + 255) / 256), static_cast<unsigned>(B));
+    const int64_t sx = 3 * p->np;
+    switch (mode) {
+        case Epi::HD: k_finish<Epi::HD><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, scale, X, sx, e); break;
+        case Epi::HEFF: k_finish<Epi::HEFF><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, scale, X, sx, e); break;
+        case Epi::DMDT: k_finish<Epi::DMDT><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, scale, X, sx, e); break;
+        case Epi::STAGE: k_finish<Epi::STAGE><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, scale, X, sx, e); break;
+        case Epi::RK4_FINAL: k_finish<Epi::RK4_FINAL><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, scale, X, sx, e); break;
+        case Epi::DP_LAST: k_finish<Epi::DP_LAST><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, scale, X, sx, e); break;
+    }
+    TM_TRY_HIP(hipGetLastError());
+    return TM_OK;
+}
+
+}  // namespace tmag

@@ -341,34 +341,117 @@ extern "C" tm_status tm_run(tm_problem* pp, tm_integrator integ, int64_t B, floa
     return TM_OK;
 }
 
-extern "C" tm_status tm_profile_field(tm_problem* pp, int64_t B, int32_t iters, hipStream_t s,
-                                      double* avg_ms, int64_t* bytes_out) {
-    Problem* p = reinterpret_cast<Problem*>(pp);
-    TM_REQUIRE(p && avg_ms && B >= 1 && iters >= 1, TM_EINVAL, "tm_profile_field: bad arguments");
-    TM_TRY_HIP(hipSetDevice(p->ctx->device));
-    tm_status st = ensure_workspace(p, B);
-    if (st != TM_OK) return st;
+namespace tmag {
+namespace {
+
+// Times `iters` launches of one epilogue variant of the field kernel on the
+// problem's workspace (inputs and outputs never alias).
+tm_status time_field(Problem* p, int64_t B, int mode, int32_t iters, hipStream_t s, double* avg_ms) {
     Workspace* w = p->ws.get();
-    // the stage-2 launch of a Dormand-Prince attempt: reads ya, k1, y; writes k2, yb
     const float* kp[6] = {w->k[0], w->k[1], w->k[2], w->k[3], w->k[4], w->k[5]};
-    double c[7] = {kDpA[2][0], kDpA[2][1]};
-    EpiArgs e = stage_args(w, w->k[1], kp, 1, c, w->yb);
+    double c[7] = {kDpA[2][0], kDpA[2][1], 0, 0, 0, 0, 0};
+    EpiArgs e;
+    Epi ep;
+    const float* X;
+    if (mode == 1) {
+        e = EpiArgs{};
+        e.out = w->hd;
+        e.out_stride = 3 * p->np;
+        ep = Epi::HD;
+        X = w->ya;
+    } else if (mode == 2) {
+        const double none[7] = {0, 0, 0, 0, 0, 0, 0};
+        e = stage_args(w, w->k[6], kp, 6, none, nullptr);
+        ep = Epi::DP_LAST;
+        X = w->y5;
+    } else {
+        // the stage-2 launch of a Dormand-Prince attempt: reads ya, k1, y; writes k2, yb
+        e = stage_args(w, w->k[1], kp, 1, c, w->yb);
+        ep = Epi::STAGE;
+        X = w->ya;
+    }
     hipEvent_t e0, e1;
     TM_TRY_HIP(hipEventCreate(&e0));
     TM_TRY_HIP(hipEventCreate(&e1));
-    st = launch_field(p, Epi::STAGE, B, w->ya, e, s);  // untimed first launch
+    tm_status st = launch_field(p, ep, B, X, e, s);  // untimed first launch
     if (st == TM_OK && hipEventRecord(e0, s) != hipSuccess) st = TM_EDEVICE;
-    for (int32_t i = 0; i < iters && st == TM_OK; ++i) st = launch_field(p, Epi::STAGE, B, w->ya, e, s);
+    for (int32_t i = 0; i < iters && st == TM_OK; ++i) st = launch_field(p, ep, B, X, e, s);
     float ms = 0.0f;
     if (st == TM_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess)) {
-        set_error("tm_profile_field: event timing failed");
+        set_error("field kernel timing: event failure");
         st = TM_EDEVICE;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (st == TM_OK) *avg_ms = static_cast<double>(ms) / iters;
+    return st;
+}
+
+}  // namespace
+}  // namespace tmag
+
+extern "C" tm_status tm_profile_field_mode(tm_problem* pp, int64_t B, int32_t mode, int32_t iters,
+                                           hipStream_t s, double* avg_ms, int64_t* bytes_out) {
+    Problem* p = reinterpret_cast<Problem*>(pp);
+    TM_REQUIRE(p && avg_ms && B >= 1 && iters >= 1 && mode >= 0 && mode <= 2, TM_EINVAL,
+               "tm_profile_field: bad arguments");
+    TM_TRY_HIP(hipSetDevice(p->ctx->device));
+    tm_status st = ensure_workspace(p, B);
     if (st != TM_OK) return st;
-    *avg_ms = static_cast<double>(ms) / iters;
+    st = time_field(p, B, mode, iters, s, avg_ms);
+    if (st != TM_OK) return st;
     if (bytes_out) *bytes_out = 24 * p->n * p->n + 24 * p->n * B;
+    return TM_OK;
+}
+
+extern "C" tm_status tm_profile_field(tm_problem* pp, int64_t B, int32_t iters, hipStream_t s,
+                                      double* avg_ms, int64_t* bytes_out) {
+    return tm_profile_field_mode(pp, B, 0, iters, s, avg_ms, bytes_out);
+}
+
+extern "C" int32_t tm_num_shapes(void) { return kNumShapes; }
+
+extern "C" tm_status tm_problem_set_shape(tm_problem* pp, int32_t shape) {
+    Problem* p = reinterpret_cast<Problem*>(pp);
+    TM_REQUIRE(p && shape >= -1 && shape < kNumShapes, TM_EINVAL, "tm_problem_set_shape: bad shape");
+    if (p->shape != shape && p->ws) {
+        // captured graphs hold the old launch shape
+        if (p->ws->graph1) (void)hipGraphExecDestroy(p->ws->graph1);
+        if (p->ws->graphK) (void)hipGraphExecDestroy(p->ws->graphK);
+        p->ws->graph1 = p->ws->graphK = nullptr;
+    }
+    p->shape = shape;
+    return TM_OK;
+}
+
+extern "C" tm_status tm_problem_tune(tm_problem* pp, int64_t B, int32_t iters, hipStream_t s,
+                                     int32_t* chosen, double* best_ms) {
+    Problem* p = reinterpret_cast<Problem*>(pp);
+    TM_REQUIRE(p && B >= 1 && iters >= 1, TM_EINVAL, "tm_problem_tune: bad arguments");
+    TM_TRY_HIP(hipSetDevice(p->ctx->device));
+    tm_status st = ensure_workspace(p, B);
+    if (st != TM_OK) return st;
+    const int keep = p->shape;
+    int best = -1;
+    double best_t = 1e30;
+    for (int sh = 0; sh < kNumShapes; ++sh) {
+        p->shape = sh;
+        double ms = 0.0;
+        st = time_field(p, B, 0, iters, s, &ms);
+        if (st != TM_OK) {
+            p->shape = keep;
+            return st;
+        }
+        if (ms < best_t) {
+            best_t = ms;
+            best = sh;
+        }
+    }
+    p->shape = keep;
+    st = tm_problem_set_shape(pp, best);
+    if (st != TM_OK) return st;
+    if (chosen) *chosen = best;
+    if (best_ms) *best_ms = best_t;
     return TM_OK;
 }

@@ -34,7 +34,8 @@ EXPORTS = [
     "tm_geometry_create", "tm_geometry_hash", "tm_geometry_info", "tm_geometry_destroy",
     "tm_tensor_assemble", "tm_tensor_get", "tm_tensor_rows", "tm_tensor_bytes", "tm_tensor_release",
     "tm_problem_create", "tm_problem_destroy", "tm_demag", "tm_heff", "tm_dmdt", "tm_energy",
-    "tm_run", "tm_profile_field", "tm_server_create", "tm_server_submit", "tm_server_poll", "tm_server_destroy",
+    "tm_run", "tm_profile_field", "tm_profile_field_mode", "tm_num_shapes", "tm_problem_set_shape",
+    "tm_problem_tune", "tm_server_create", "tm_server_submit", "tm_server_poll", "tm_server_destroy",
 ]
 
 
@@ -126,6 +127,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "tm_energy": (i32, [vp, i64, vp, vp, vp, vp]),
         "tm_run": (i32, [vp, i32, i64, vp, vp, vp, vp, vp, P(tm_run_cfg), P(tm_run_stats), vp]),
         "tm_profile_field": (i32, [vp, i64, i32, vp, P(d), P(i64)]),
+        "tm_profile_field_mode": (i32, [vp, i64, i32, i32, vp, P(d), P(i64)]),
+        "tm_num_shapes": (i32, []),
+        "tm_problem_set_shape": (i32, [vp, i32]),
+        "tm_problem_tune": (i32, [vp, i64, i32, vp, P(i32), P(d)]),
         "tm_server_create": (i32, [vp, P(tm_server_cfg), P(vp)]),
         "tm_server_submit": (i32, [vp, P(tm_request), P(u64)]),
         "tm_server_poll": (i32, [vp, u64, i32, P(tm_result), P(C.c_float)]),
@@ -360,6 +365,28 @@ def tm_profile_field(p, B: int, iters: int):
     ms, nb = C.c_double(), C.c_int64()
     _check(load().tm_profile_field(p, int(B), int(iters), _stream(), C.byref(ms), C.byref(nb)))
     return ms.value, nb.value
+
+
+def tm_profile_field_mode(p, B: int, mode: int, iters: int):
+    ms, nb = C.c_double(), C.c_int64()
+    _check(load().tm_profile_field_mode(p, int(B), int(mode), int(iters), _stream(), C.byref(ms),
+                                        C.byref(nb)))
+    return ms.value, nb.value
+
+
+def tm_num_shapes() -> int:
+    return int(load().tm_num_shapes())
+
+
+def tm_problem_set_shape(p, shape: int) -> None:
+    _check(load().tm_problem_set_shape(p, int(shape)))
+
+
+def tm_problem_tune(p, B: int = 1, iters: int = 20):
+    """(chosen shape, its mean ms per launch)."""
+    ch, ms = C.c_int32(), C.c_double()
+    _check(load().tm_problem_tune(p, int(B), int(iters), _stream(), C.byref(ch), C.byref(ms)))
+    return ch.value, ms.value
 
 
 # ------------------------------------------------------------ convenience

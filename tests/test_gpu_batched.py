@@ -1,0 +1,137 @@
+"""GPU parity of the batched path: many states sharing one operator, the
+demag product as one MFMA GEMM (DENSE9 operator) in float32 or bf16 / fp16
+hi + lo split precision with float32 accumulation.
+
+Tolerances on H_d against the FP64 oracle (relative 2-norm and max-norm):
+  FP32   <= 1e-5
+  BF16X3 <= 1e-3 (three bf16 products carry ~16 significant bits)
+  FP16X3 <= 2e-5 (three fp16 products with per-row scaling carry ~22 bits)
+The measured errors are printed.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_helpers import build, close, device_state, rel_errors, tilemag
+from paper_2107_05364_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-5, 1: 1e-3, 2: 2e-5}
+NAMES = {0: "fp32", 1: "bf16x3", 2: "fp16x3"}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tmg():
+    return tilemag()
+
+
+@pytest.fixture(scope="module")
+def ctx(tmg):
+    c = tmg.Context(0)
+    yield c
+    try:
+        c.close()
+    except tmg.TilemagError:
+        pass
+
+
+@pytest.fixture(scope="module")
+def film_ref(orc):
+    wl = W.hysteresis_batch(B=128)
+    T = orc.assemble(wl.centers, wl.sizes)
+    m = wl.m0.astype(np.float32)
+    # FP64 oracle product for all states: one library matmul of the oracle's operator
+    H = -(8.0e5 * m.astype(np.float64).reshape(128, -1)) @ T.T
+    return wl, m, H.reshape(128, wl.n, 3)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_batched_demag_film_128_states(tmg, ctx, film_ref, prec):
+    wl, m, H = film_ref
+    _say("batched demag %s B=128 n=%d" % (NAMES[prec], wl.n))
+    g, T, p = build(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha, store=prec,
+                    layout=tmg.TM_LAYOUT_DENSE9)
+    got = p.demag(device_state(m)).cpu().numpy()
+    e2, emax = rel_errors(got, H)
+    _say("  %s: rel2 %.3e relmax %.3e" % (NAMES[prec], e2, emax))
+    assert e2 <= TOL[prec] and emax <= TOL[prec]
+    close(g, T, p)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("B", [1, 3, 33])
+def test_batched_demag_ragged(tmg, ctx, orc, prec, B):
+    """Non-uniform tiles and per-tile Ms, a batch that is not a multiple of
+    16 and a tile count that is not a multiple of 64."""
+    wl = W.refined_slab(n_target=777, lx=200e-9, ly=60e-9, lz=20e-9)
+    n = wl.n
+    Ms = 8.0e5 * (0.75 + 0.5 * W.uniform(9, n))
+    g, T, p = build(tmg, ctx, wl.centers, wl.sizes, Ms=Ms, store=prec, layout=tmg.TM_LAYOUT_DENSE9)
+    m = np.stack([W.random_unit_vectors(40 + k, n) for k in range(B)]).astype(np.float32)
+    got = p.demag(device_state(m)).cpu().numpy()
+    Tref = orc.assemble(wl.centers, wl.sizes)
+    for k in range(B):
+        want = orc.demag(Tref, Ms, m[k].astype(np.float64))
+        e2, emax = rel_errors(got[k], want)
+        assert e2 <= TOL[prec] and emax <= TOL[prec], (k, e2, emax)
+    close(g, T, p)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_state_is_batch_invariant(tmg, ctx, prec):
+    """A state's demag field is bit-identical alone and in a batch of 40."""
+    wl = W.thin_film(nx=40, ny=10)
+    g, T, p = build(tmg, ctx, wl.centers, wl.sizes, store=prec, layout=tmg.TM_LAYOUT_DENSE9)
+    m = np.stack([W.film_texture(wl.centers, 200e-9, k) for k in range(40)]).astype(np.float32)
+    many = p.demag(device_state(m)).cpu().numpy()
+    one = p.demag(device_state(m[17:18])).cpu().numpy()
+    assert np.array_equal(many[17], one[0])
+    close(g, T, p)
+
+
+def test_batched_dp45_matches_matvec_path(tmg, ctx):
+    """DP45 on 8 states to a common end time: the FP32 GEMM path and the FP32
+    matvec path (different summation orders) agree within the float32
+    resolution of the tolerance-1e-6 integration."""
+    import torch
+
+    wl = W.hysteresis_batch(B=8, nx=40, ny=10)
+    Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
+    ga, Ta, pa = build(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha, layout=tmg.TM_LAYOUT_DENSE9)
+    gb, Tb, pb = build(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha)
+    ma, mb = device_state(wl.m0), device_state(wl.m0)
+    ta, _, sa, _ = pa.run(ma, Ha, tmg.TM_DP45, dt=1e-14, max_steps=1 << 20, t_end=20e-12)
+    tb, _, sb, _ = pb.run(mb, Ha, tmg.TM_DP45, dt=1e-14, max_steps=1 << 20, t_end=20e-12)
+    assert torch.allclose(ta, tb, rtol=0, atol=1e-24)
+    d = (ma - mb).abs().max().item()
+    _say("gemm vs matvec path after 20 ps: max|dm| %.2e, steps %s / %s"
+         % (d, sa.cpu().tolist(), sb.cpu().tolist()))
+    assert d <= 2e-5
+    close(ga, Ta, pa, gb, Tb, pb)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_split_precision_hysteresis_run(tmg, ctx, prec):
+    """A short batched hysteresis run in split precision stays within the
+    tolerance-level distance of the FP32 run (same states, same end time)."""
+    import torch
+
+    wl = W.hysteresis_batch(B=16, nx=40, ny=10)
+    Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
+    g1, T1, p1 = build(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha, layout=tmg.TM_LAYOUT_DENSE9)
+    g2, T2, p2 = build(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha, store=prec,
+                       layout=tmg.TM_LAYOUT_DENSE9)
+    a, b = device_state(wl.m0), device_state(wl.m0)
+    p1.run(a, Ha, tmg.TM_DP45, dt=1e-14, max_steps=1 << 20, t_end=10e-12)
+    p2.run(b, Ha, tmg.TM_DP45, dt=1e-14, max_steps=1 << 20, t_end=10e-12)
+    d = (a - b).abs().max().item()
+    _say("split vs fp32 hysteresis run, 10 ps: max|dm| %.2e" % d)
+    assert d <= 1e-3
+    close(g1, T1, p1, g2, T2, p2)
