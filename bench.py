@@ -37,6 +37,13 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=60,
                     help="attempted steps of the oracle in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="counter runs: one 1 GiB device copy (calibration) and the stage kernel "
+                         "of the film workload only")
+    ap.add_argument("--serving-count", type=int, default=24)
     return ap.parse_args()
 
 
@@ -62,6 +69,174 @@ def cpu_baseline(wl, nsteps):
             "assembly_s": round(t_asm, 3)}
 
 
+def batched_section(tmg, W, torch, attempts=60, profile_iters=20):
+    """B = 128 states on the film geometry sharing one DENSE9 operator: one
+    MFMA GEMM per right-hand side, in float32 and in bf16 / fp16 hi + lo
+    split precision.  The H_d error is measured against the product with the
+    float64 operator assembled by the library (float64 on the host)."""
+    wl = W.hysteresis_batch(B=128)
+    n, B = wl.n, wl.batch
+    ctx = tmg.Context(0)
+    geom = tmg.Geometry(ctx, wl.centers, wl.sizes)
+    T64 = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP64, tmg.TM_LAYOUT_DENSE9)
+    A = T64.dense()
+    T64.close()
+    m32 = wl.m0.astype(np.float32)
+    ref = -(wl.Ms * m32.astype(np.float64).reshape(B, -1)) @ A.T
+    del A
+    Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
+    out = {"workload": "hysteresis film 100x25x1 (N=2500), B=128 states, +80..-80 mT, DP45",
+           "err_reference": "H_d from the library's FP64 operator, FP64 product on the host"}
+    peaks = {"fp32": 157.3, "bf16x3": 2500.0, "fp16x3": 2500.0}
+    for prec, name in ((tmg.TM_PREC_FP32, "fp32"), (tmg.TM_PREC_BF16X3, "bf16x3"),
+                       (tmg.TM_PREC_FP16X3, "fp16x3")):
+        T = tmg.Tensor(ctx, geom, prec, tmg.TM_LAYOUT_DENSE9)
+        p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+        m = torch.as_tensor(m32, device="cuda")
+        hd = p.demag(m).cpu().numpy().reshape(B, -1).astype(np.float64)
+        err2 = float(np.linalg.norm(hd - ref) / np.linalg.norm(ref))
+        errm = float(np.abs(hd - ref).max() / np.abs(ref).max())
+        rhs_ms, _ = tmg.tm_profile_field(p.handle, B, profile_iters)
+        flops = 2.0 * 9 * n * n * B * (3 if name != "fp32" else 1)
+        op_bytes = 36.0 * n * n
+        p.run(m, Ha, tmg.TM_DP45, dt=1e-14, max_steps=1 << 40, max_attempts=10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tt, dd, steps, st = p.run(m, Ha, tmg.TM_DP45, dt=1e-14, max_steps=1 << 40,
+                                  max_attempts=attempts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"state_steps_per_s": round(B * attempts / el, 1),
+                     "ms_per_step": round(el * 1e3 / attempts, 4),
+                     "rhs_us": round(rhs_ms * 1e3, 2),
+                     "mfma_tflops": round(flops / (rhs_ms * 1e-3) / 1e12, 2),
+                     "mfma_frac": round(flops / (rhs_ms * 1e-3) / 1e12 / peaks[name], 4),
+                     "operator_gbs": round(op_bytes / (rhs_ms * 1e-3) / 1e9, 1),
+                     "hd_rel_err_2norm": err2, "hd_rel_err_max": errm,
+                     "accepted_min": int(st.accepted_min), "rejected": int(st.rejected)}
+        p.close()
+        T.close()
+    geom.close()
+    ctx.close()
+    return out
+
+
+def large_section(tmg, W, torch, attempts=20, profile_iters=10):
+    """The 20000-tile refined slab (edges 2.5-20 nm, 1000 x 250 x 20 nm): FP64
+    operator assembly on the GPU, the stage kernel streaming a 9.6 GB SYM6
+    operator (no cache can hold it: the HBM roofline proper), a few single-state
+    DP45 steps, and 32 states through the DENSE9 bf16 hi+lo GEMM path."""
+    wl = W.refined_slab(n_target=20000, B=32)
+    n = wl.n
+    ctx = tmg.Context(0)
+    geom = tmg.Geometry(ctx, wl.centers, wl.sizes)
+    out = {"workload": "refined slab N=%d (%d ordered face pairs), alpha=0.1" % (n, geom.nfaces)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_SYM6)
+    torch.cuda.synchronize()
+    asm = time.perf_counter() - t0
+    out["assembly_ms"] = round(asm * 1e3, 1)
+    out["assembly_gpairs_s"] = round(n * n / asm / 1e9, 2)
+    p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+    ms, nb = tmg.tm_profile_field(p.handle, 1, profile_iters)
+    out["stage_kernel_us"] = round(ms * 1e3, 1)
+    out["stage_kernel_gbs"] = round(nb / (ms * 1e-3) / 1e9, 1)
+    out["stage_kernel_hbm_frac"] = round(nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    m = torch.as_tensor(wl.m0[:1].astype(np.float32), device="cuda")
+    p.run(m, None, tmg.TM_DP45, dt=1e-14, max_steps=1 << 40, max_attempts=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.run(m, None, tmg.TM_DP45, dt=1e-14, max_steps=1 << 40, max_attempts=attempts)
+    torch.cuda.synchronize()
+    out["single_steps_per_s"] = round(attempts / (time.perf_counter() - t0), 2)
+    p.close()
+    T.close()
+    T9 = tmg.Tensor(ctx, geom, tmg.TM_PREC_BF16X3, tmg.TM_LAYOUT_DENSE9)
+    p9 = tmg.Problem(ctx, geom, T9, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+    m = torch.as_tensor(wl.m0.astype(np.float32), device="cuda")
+    ms, _ = tmg.tm_profile_field(p9.handle, 32, profile_iters)
+    out["batch32_bf16x3_rhs_us"] = round(ms * 1e3, 1)
+    out["batch32_bf16x3_operator_gbs"] = round(36.0 * n * n / (ms * 1e-3) / 1e9, 1)
+    p9.run(m, None, tmg.TM_DP45, dt=1e-14, max_steps=1 << 40, max_attempts=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p9.run(m, None, tmg.TM_DP45, dt=1e-14, max_steps=1 << 40, max_attempts=attempts)
+    torch.cuda.synchronize()
+    out["batch32_state_steps_per_s"] = round(32 * attempts / (time.perf_counter() - t0), 2)
+    p9.close()
+    T9.close()
+    geom.close()
+    ctx.close()
+    return out
+
+
+def serving_section(tmg, W, torch, count=24, n_max=4000, max_steps=3000, slots=8):
+    """Poisson stream of relaxation requests (bounded sample of the serving
+    workload: `count` requests, tile counts log-uniform in [500, n_max]):
+    the continuous-batching server against serial FIFO plain-FP32 solves of
+    the same requests (service times measured one by one, queueing from the
+    same arrival times)."""
+    Ms, A, alpha = 8.0e5, 1.3e-11, 0.5
+    stop = 1e-4 * W.GAMMA0 * Ms
+    reqs = W.serving_stream(count=count, n_max=n_max)
+    kw = dict(Ms=Ms, A_exch=A, alpha=alpha, dmdt_stop=stop, max_steps=max_steps, dt0=1e-14)
+    ctx = tmg.Context(0)
+    srv = tmg.Server(ctx, max_slots=slots, max_groups=16, steps_per_round=64)
+    t0 = time.perf_counter()
+    tks = []
+    for r in reqs:
+        d = t0 + r.arrival - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        tks.append(srv.submit(r.centers, r.sizes, r.m0, r.Ha, **kw))
+    res = [srv.poll(t)[0] for t in tks]
+    span = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([r.latency_ms for r in res])
+    conv = sum(1 for r in res if r.status == 0)
+    hits = sum(1 for r in res if r.cache_hit)
+    # serial FIFO baseline on the same device (operator cache kept, as a
+    # plain solver would keep its operator between repeated geometries)
+    svc = []
+    cache = {}
+    for r in reqs:
+        ts = time.perf_counter()
+        key = (r.centers.shape[0], r.centers.tobytes())
+        if key not in cache:
+            g = tmg.Geometry(ctx, r.centers, r.sizes)
+            T = tmg.Tensor(ctx, g)
+            cache[key] = (g, T)
+        g, T = cache[key]
+        p = tmg.Problem(ctx, g, T, Ms, A, alpha)
+        m = torch.as_tensor(r.m0[None].astype(np.float32), device="cuda")
+        Ha = torch.as_tensor(np.asarray(r.Ha, np.float32)[None], device="cuda")
+        p.run(m, Ha, tmg.TM_DP45, dt=1e-14, max_steps=max_steps, dmdt_stop=stop, check=False)
+        torch.cuda.synchronize()
+        p.close()
+        svc.append(time.perf_counter() - ts)
+    end, lat_s = 0.0, []
+    for r, sv in zip(reqs, svc):
+        start = max(r.arrival, end)
+        end = start + sv
+        lat_s.append((end - r.arrival) * 1e3)
+    for g, T in cache.values():
+        T.close()
+        g.close()
+    ctx.close()
+    lat_s = np.array(lat_s)
+    return {"workload": "Poisson stream 20 req/s, %d requests, N log-uniform 500-%d on 5x5x3 nm "
+                        "grids, 30%% repeated geometries, relax to max|dm/dt| < 1e-4 gamma0 Ms "
+                        "(cap %d steps)" % (count, n_max, max_steps),
+            "server": {"throughput_req_s": round(count / span, 3),
+                       "p50_ms": round(float(np.percentile(lat, 50)), 1),
+                       "p99_ms": round(float(np.percentile(lat, 99)), 1),
+                       "converged": conv, "cache_hits": hits, "slots": slots},
+            "serial_fp32": {"throughput_req_s": round(count / end, 3),
+                            "p50_ms": round(float(np.percentile(lat_s, 50)), 1),
+                            "p99_ms": round(float(np.percentile(lat_s, 99)), 1)}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -74,6 +249,14 @@ def main():
     from paper_2107_05364_amd import workloads as W
 
     tmg.load()
+    if args.profile_only:
+        # a plain copy of known size: the counters of this dispatch calibrate
+        # FETCH_SIZE / WRITE_SIZE against 1 GiB read and 1 GiB written
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = W.thin_film()
     n = wl.n
     ctx = tmg.Context(0)
@@ -85,6 +268,15 @@ def main():
     asm_ms = (time.perf_counter() - t0) * 1e3
     p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
 
+    if args.profile_only:
+        ms, nb = tmg.tm_profile_field(p.handle, 1, args.profile_iters)
+        print(json.dumps({"profile_only": True, "stage_kernel_us": round(ms * 1e3, 3),
+                          "bytes_per_launch": nb, "launches": args.profile_iters + 1}), flush=True)
+        p.close()
+        T.close()
+        geom.close()
+        ctx.close()
+        return
     m = torch.as_tensor(wl.m0.astype(np.float32), device="cuda")
     Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
     t = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -130,12 +322,21 @@ def main():
                      "kernel": "k_field<256,4,STAGE> (fused demag matvec + H_eff + LL + stage)",
                      "avg_launch_us": round(avg_ms * 1e3, 3), "bytes_per_launch": bytes_per},
     }
-    if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     p.close()
     T.close()
     geom.close()
     ctx.close()
+    if not args.no_batched:
+        bat = batched_section(tmg, W, torch)
+        best = max(v["state_steps_per_s"] for k, v in bat.items() if isinstance(v, dict))
+        bat["vs_single_fp32_solve"] = round(best / rec["value"], 2)
+        rec["batched"] = bat
+    if not args.no_large:
+        rec["large"] = large_section(tmg, W, torch)
+    if not args.no_serving:
+        rec["serving"] = serving_section(tmg, W, torch, count=args.serving_count)
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(rec), flush=True)
 
 

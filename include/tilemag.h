@@ -279,7 +279,9 @@ typedef struct {
 } tm_request;
 
 typedef struct {
-    int32_t status;          /* TM_OK, TM_EBUSY (still running), TM_ESTEP, TM_ENONFINITE */
+    int32_t status;          /* TM_OK (equilibrium reached), TM_EBUSY (still running),
+                                TM_ESTEP (step cap reached first, or step underflow),
+                                TM_ENONFINITE, TM_ENOMEM (larger than the whole budget) */
     int64_t steps;           /* accepted steps */
     double t;                /* simulated time [s] */
     double latency_ms;       /* submit -> completion wall time */

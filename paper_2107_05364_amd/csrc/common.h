@@ -206,7 +206,7 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
                                const EpiArgs& e, hipStream_t s);
 constexpr int64_t kMaxGemmStates = 128;
 
-constexpr int kNumShapes = 12;
+constexpr int kNumShapes = 16;
 int default_shape(int64_t n);
 tm_status launch_pack(const float* src, int64_t B, int64_t n, int64_t np, float* dst, hipStream_t s);
 tm_status launch_control(Workspace* w, int64_t B, int integ, hipStream_t s);
@@ -227,6 +227,6 @@ enum RunParam { RP_ATOL = 0, RP_RTOL, RP_TEND, RP_DTMIN, RP_DMDT_STOP, RP_MAX_ST
                 RP_COUNT };
 
 // Per-state flag bits.
-constexpr int32_t FLAG_DONE = 1, FLAG_NONFINITE = 2, FLAG_STEP = 4;
+constexpr int32_t FLAG_DONE = 1, FLAG_NONFINITE = 2, FLAG_STEP = 4, FLAG_CAPPED = 8;
 
 }  // namespace tmag

@@ -51,8 +51,12 @@ __device__ inline float4 ldT(const float* p) {
     }
 }
 
-template <int BLOCK, int TT, int NT, Epi MODE>
-__global__ __launch_bounds__(BLOCK) void k_field(DevProblem P, MvArgs M, EpiArgs E) {
+// WPE caps the waves per SIMD the compiler schedules for: with few resident
+// waves a lower cap lets every 16-byte operator load of an iteration stay in
+// flight at once (more registers per lane) instead of trading it for occupancy.
+template <int BLOCK, int TT, int NT, int WPE, Epi MODE>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, WPE))) void k_field(
+    DevProblem P, MvArgs M, EpiArgs E) {
     constexpr int NW = BLOCK / 64;
     const int s = blockIdx.y;
     const int a0 = blockIdx.x * TT;
@@ -138,21 +142,21 @@ __global__ __launch_bounds__(BLOCK) void k_field(DevProblem P, MvArgs M, EpiArgs
     }
 }
 
-template <int BLOCK, int TT, int NT>
+template <int BLOCK, int TT, int NT, int WPE>
 tm_status launch_tt(const DevProblem& P, const MvArgs& M, Epi mode, int64_t B, const EpiArgs& e,
                     hipStream_t st) {
     const dim3 grid(static_cast<unsigned>((M.n + TT - 1) / TT), static_cast<unsigned>(B));
     const dim3 block(BLOCK);
     switch (mode) {
-        case Epi::HD: k_field<BLOCK, TT, NT, Epi::HD><<<grid, block, 0, st>>>(P, M, e); break;
-        case Epi::HEFF: k_field<BLOCK, TT, NT, Epi::HEFF><<<grid, block, 0, st>>>(P, M, e); break;
-        case Epi::DMDT: k_field<BLOCK, TT, NT, Epi::DMDT><<<grid, block, 0, st>>>(P, M, e); break;
-        case Epi::STAGE: k_field<BLOCK, TT, NT, Epi::STAGE><<<grid, block, 0, st>>>(P, M, e); break;
+        case Epi::HD: k_field<BLOCK, TT, NT, WPE, Epi::HD><<<grid, block, 0, st>>>(P, M, e); break;
+        case Epi::HEFF: k_field<BLOCK, TT, NT, WPE, Epi::HEFF><<<grid, block, 0, st>>>(P, M, e); break;
+        case Epi::DMDT: k_field<BLOCK, TT, NT, WPE, Epi::DMDT><<<grid, block, 0, st>>>(P, M, e); break;
+        case Epi::STAGE: k_field<BLOCK, TT, NT, WPE, Epi::STAGE><<<grid, block, 0, st>>>(P, M, e); break;
         case Epi::RK4_FINAL:
-            k_field<BLOCK, TT, NT, Epi::RK4_FINAL><<<grid, block, 0, st>>>(P, M, e);
+            k_field<BLOCK, TT, NT, WPE, Epi::RK4_FINAL><<<grid, block, 0, st>>>(P, M, e);
             break;
         case Epi::DP_LAST:
-            k_field<BLOCK, TT, NT, Epi::DP_LAST><<<grid, block, 0, st>>>(P, M, e);
+            k_field<BLOCK, TT, NT, WPE, Epi::DP_LAST><<<grid, block, 0, st>>>(P, M, e);
             break;
     }
     TM_TRY_HIP(hipGetLastError());
@@ -221,8 +225,10 @@ __global__ void k_control(int64_t B, int integ, const double* __restrict__ prm,
     const double fac = (e == 0.0) ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(e, -0.2)));
     double dn = hh * fac;
     t[s] = tn;
-    done = static_cast<double>(steps[s]) >= max_steps || (t_end > 0.0 && tn >= t_end) ||
-           (ok && prm[RP_DMDT_STOP] > 0.0 && dm < prm[RP_DMDT_STOP]);
+    const bool converged = ok && prm[RP_DMDT_STOP] > 0.0 && dm < prm[RP_DMDT_STOP];
+    done = static_cast<double>(steps[s]) >= max_steps || (t_end > 0.0 && tn >= t_end) || converged;
+    // a state waiting for equilibrium that stops at the step cap is marked
+    if (done && !converged && prm[RP_DMDT_STOP] > 0.0) f |= FLAG_CAPPED;
     if (t_end > 0.0 && tn + dn > t_end) dn = t_end - tn;
     dt[s] = done ? hh * fac : dn;
     if (done) {
@@ -355,18 +361,22 @@ tm_status launch_field(const Problem* p, Epi mode, int64_t B, const float* X, co
     const DevProblem P = p->dev();
     const int shape = p->shape >= 0 ? p->shape : default_shape(p->n);
     switch (shape) {
-        case 0: return launch_tt<64, 2, 0>(P, M, mode, B, e, s);
-        case 1: return launch_tt<128, 2, 0>(P, M, mode, B, e, s);
-        case 2: return launch_tt<128, 4, 0>(P, M, mode, B, e, s);
-        case 3: return launch_tt<256, 2, 0>(P, M, mode, B, e, s);
-        case 4: return launch_tt<256, 4, 0>(P, M, mode, B, e, s);
-        case 5: return launch_tt<256, 8, 0>(P, M, mode, B, e, s);
-        case 6: return launch_tt<512, 4, 0>(P, M, mode, B, e, s);
-        case 7: return launch_tt<512, 8, 0>(P, M, mode, B, e, s);
-        case 8: return launch_tt<256, 2, 1>(P, M, mode, B, e, s);
-        case 9: return launch_tt<256, 4, 1>(P, M, mode, B, e, s);
-        case 10: return launch_tt<128, 1, 0>(P, M, mode, B, e, s);
-        case 11: return launch_tt<256, 1, 0>(P, M, mode, B, e, s);
+        case 0: return launch_tt<64, 2, 0, 8>(P, M, mode, B, e, s);
+        case 1: return launch_tt<128, 2, 0, 8>(P, M, mode, B, e, s);
+        case 2: return launch_tt<128, 4, 0, 8>(P, M, mode, B, e, s);
+        case 3: return launch_tt<256, 2, 0, 8>(P, M, mode, B, e, s);
+        case 4: return launch_tt<256, 4, 0, 8>(P, M, mode, B, e, s);
+        case 5: return launch_tt<256, 8, 0, 8>(P, M, mode, B, e, s);
+        case 6: return launch_tt<512, 4, 0, 8>(P, M, mode, B, e, s);
+        case 7: return launch_tt<512, 8, 0, 8>(P, M, mode, B, e, s);
+        case 8: return launch_tt<256, 2, 1, 8>(P, M, mode, B, e, s);
+        case 9: return launch_tt<256, 4, 1, 8>(P, M, mode, B, e, s);
+        case 10: return launch_tt<128, 1, 0, 8>(P, M, mode, B, e, s);
+        case 11: return launch_tt<256, 1, 0, 8>(P, M, mode, B, e, s);
+        case 12: return launch_tt<256, 4, 0, 2>(P, M, mode, B, e, s);
+        case 13: return launch_tt<256, 8, 0, 2>(P, M, mode, B, e, s);
+        case 14: return launch_tt<128, 4, 0, 2>(P, M, mode, B, e, s);
+        case 15: return launch_tt<512, 8, 0, 2>(P, M, mode, B, e, s);
         default: break;
     }
     set_error("unknown field-kernel shape %d", shape);

@@ -336,6 +336,8 @@ void tm_server::run() {
                     finish(g, i, TM_ENONFINITE);
                 else if (f & FLAG_STEP)
                     finish(g, i, TM_ESTEP);
+                else if (f & FLAG_CAPPED)
+                    finish(g, i, TM_ESTEP);  // step cap reached before equilibrium
                 else if (f & FLAG_DONE)
                     finish(g, i, TM_OK);
             }

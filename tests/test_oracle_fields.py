@@ -181,3 +181,22 @@ def test_sp4_parameters_match_paper():
     # alpha_LL / gamma_LL = 0.02 (the film's damping)
     assert abs(g["alpha_LL"] / g["gamma_LL"] - wl.alpha) < 1e-12
     assert wl.gamma0 == g["gamma_LL"]
+
+
+def test_oracle_regression_fixture():
+    """The oracle still produces the values frozen in tests/golden (written
+    by tests/golden/make_oracle_regression.py from the oracle alone)."""
+    import importlib.util
+
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    spec = importlib.util.spec_from_file_location("mk", os.path.join(here, "make_oracle_regression.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    with open(os.path.join(here, "oracle_regression.json")) as f:
+        want = json.load(f)
+    got = mk.compute()
+    for key in ("blocks",):
+        for b in want[key]:
+            np.testing.assert_allclose(got[key][b], want[key][b], rtol=1e-13, atol=1e-17)
+    for key in ("demag_first_tiles", "energy", "rk4_10_steps_first_tiles"):
+        np.testing.assert_allclose(got[key], want[key], rtol=1e-12, atol=1e-30)
