@@ -14,6 +14,7 @@ timed separately.
 Prints one JSON line.  Run with no arguments for the default configuration.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -34,7 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--profile-iters", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=60,
+    ap.add_argument("--cpu-steps", type=int, default=1000,
                     help="attempted steps of the oracle in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -45,6 +46,33 @@ def parse():
                          "of the film workload only")
     ap.add_argument("--serving-count", type=int, default=24)
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ["paper_2107_05364_amd/csrc/fieldstep.hip", "paper_2107_05364_amd/csrc/epilogue.h",
+                  "paper_2107_05364_amd/csrc/common.h"]
+COUNTERS = os.path.join(ROOT, "profiles", "k_field_stage_film_N2500_counters.md")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kname):
+    """HBM bytes per launch of the stage kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, calibrated against a 1 GiB copy),
+    or None when the kernel sources or the kernel instance changed since."""
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    vals = dict(ln.split(":", 1) for ln in text.splitlines() if ln.startswith(("source_hash:", "kernel:", "traffic_bytes_per_launch:")))
+    if vals.get("source_hash", "").strip() != kernel_source_hash() or vals.get("kernel", "").strip() != kname:
+        return None
+    return int(vals["traffic_bytes_per_launch"].strip())
 
 
 def cpu_baseline(wl, nsteps):
@@ -139,6 +167,8 @@ def large_section(tmg, W, torch, attempts=20, profile_iters=10):
     out["assembly_ms"] = round(asm * 1e3, 1)
     out["assembly_gpairs_s"] = round(n * n / asm / 1e9, 2)
     p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+    shape, _ = tmg.tm_problem_tune(p.handle, 1, 3)
+    out["stage_kernel_shape"] = shape
     ms, nb = tmg.tm_profile_field(p.handle, 1, profile_iters)
     out["stage_kernel_us"] = round(ms * 1e3, 1)
     out["stage_kernel_gbs"] = round(nb / (ms * 1e-3) / 1e9, 1)
@@ -267,6 +297,8 @@ def main():
     torch.cuda.synchronize()
     asm_ms = (time.perf_counter() - t0) * 1e3
     p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+    # project autotuner: fastest launch shape of the fused stage kernel for this N
+    shape, _ = tmg.tm_problem_tune(p.handle, 1, 50)
 
     if args.profile_only:
         ms, nb = tmg.tm_profile_field(p.handle, 1, args.profile_iters)
@@ -297,6 +329,9 @@ def main():
     # the stream it runs on
     avg_ms, bytes_per = tmg.tm_profile_field(p.handle, 1, args.profile_iters)
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+    bl, tt, nt, wpe = tmg.tm_shape_info(shape)
+    kname = "k_field<%d,%d,%d,%d,STAGE>" % (bl, tt, nt, wpe)
+    traffic = counter_traffic(kname)
 
     rec = {
         "metric": "LLG steps/s",
@@ -315,11 +350,12 @@ def main():
                                "adaptive DP45, fp32 SYM6 operator",
                    "n_tiles": n, "batch": 1, "integrator": "DP45", "operator": "fp32 sym6",
                    "accepted_steps": accepted, "rejected_steps": int(st.rejected),
+                   "stage_kernel_shape": shape,
                    "simulated_ns": round(float(tt.cpu()[0]) * 1e9, 4),
                    "assembly_ms": round(asm_ms, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_field<256,4,STAGE> (fused demag matvec + H_eff + LL + stage)",
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": kname + " (fused demag matvec + H_eff + LL + stage update)",
                      "avg_launch_us": round(avg_ms * 1e3, 3), "bytes_per_launch": bytes_per},
     }
     p.close()

@@ -244,6 +244,15 @@ tm_status tm_profile_field_mode(tm_problem* p, int64_t B, int32_t mode, int32_t 
  * load kind) the fused field kernel is compiled for. */
 int32_t tm_num_shapes(void);
 
+/* Launch parameters of shape `shape`: workgroup threads, target tiles per
+ * workgroup, nontemporal operator loads (0/1), waves-per-SIMD cap. */
+tm_status tm_shape_info(int32_t shape, int32_t* threads, int32_t* tiles, int32_t* nontemporal,
+                        int32_t* waves_cap);
+
+/* Launch shape p's field kernel uses now (the default for its tile count
+ * until tm_problem_set_shape or tm_problem_tune changes it). */
+tm_status tm_problem_shape(const tm_problem* p, int32_t* shape);
+
 /* Fixes the launch shape of p's field kernel (0 <= shape < tm_num_shapes(),
  * or -1 for the default chosen from the tile count).  The shape sets the
  * summation order of the demag product, so results are bitwise reproducible

@@ -62,7 +62,7 @@ Workspace::~Workspace() {
     float* fl[] = {y, ya, yb, y5, k[0], k[1], k[2], k[3], k[4], k[5], k[6], Ha, hd, part};
     for (float* p : fl)
         if (p) (void)hipFree(p);
-    void* vp[] = {xh, xl, t, h, dt, err, dmx, steps, rejected, flags, acc, params, esum};
+    void* vp[] = {xh, xl, t, h, dt, errp, dmxp, steps, rejected, flags, acc, params, esum};
     for (void* p : vp)
         if (p) (void)hipFree(p);
     if (host_params) (void)hipHostFree(host_params);
@@ -577,8 +577,8 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
         splits = gemm_splits(p);
         pbytes = splits * bcap * T->rows * 4;
     }
-    int64_t bytes = 12 * sb + bcap * 12 + bcap * (8 * 5 + 8 * 2 + 4 * 2) + RP_COUNT * 8 +
-                    nblk * bcap * 32 + xbytes + pbytes;
+    int64_t bytes = 12 * sb + bcap * 12 + bcap * (8 * 7 + 8 * 2 + 4 * 2) + 16 * bcap * n + 64 +
+                    RP_COUNT * 8 + nblk * bcap * 32 + xbytes + pbytes;
     {
         std::lock_guard<std::mutex> lk(p->ctx->mu);
         const int64_t old = p->ws ? p->ws->bytes : 0;
@@ -611,8 +611,10 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->t), bcap * 8);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->h), bcap * 8);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->dt), bcap * 8);
-    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->err), bcap * 8);
-    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->dmx), bcap * 8);
+    w->pstride = n;  // at most one partial per target tile (one tile per block)
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->errp), bcap * n * 8);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->dmxp), bcap * n * 8);
+
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->steps), bcap * 8);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->rejected), bcap * 8);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->flags), bcap * 4);

@@ -150,8 +150,10 @@ struct Workspace {
     double* t = nullptr;
     double* h = nullptr;      // step used by the current attempt (0: frozen)
     double* dt = nullptr;     // proposal
-    unsigned long long* err = nullptr;  // float64 bits, atomic max
-    unsigned long long* dmx = nullptr;
+    double* errp = nullptr;   // [B][pstride] per-block maxima of the scaled error
+    double* dmxp = nullptr;   // [B][pstride] per-block maxima of |dm/dt|
+    int64_t pstride = 0;
+
     int64_t* steps = nullptr;
     int64_t* rejected = nullptr;
     int32_t* flags = nullptr;
@@ -191,8 +193,9 @@ struct EpiArgs {
     float* ynext;          // STAGE: next stage input
     const double* h;       // [B] step of this attempt
     const double* params;  // RunParams (atol, rtol, ...)
-    unsigned long long* err;
-    unsigned long long* dmx;
+    double* errp;          // DP_LAST: per-block partial maxima, [B][pstride]
+    double* dmxp;
+    int64_t pstride;
     int32_t renorm;
 };
 
@@ -206,11 +209,36 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
                                const EpiArgs& e, hipStream_t s);
 constexpr int64_t kMaxGemmStates = 128;
 
-constexpr int kNumShapes = 16;
+// Launch shapes of the fused field kernel: (index, workgroup threads,
+// target tiles per workgroup, nontemporal operator loads, waves-per-SIMD cap).
+#define TM_FIELD_SHAPES(X)        \
+    X(0, 64, 2, 0, 8)             \
+    X(1, 128, 2, 0, 8)            \
+    X(2, 128, 4, 0, 8)            \
+    X(3, 256, 2, 0, 8)            \
+    X(4, 256, 4, 0, 8)            \
+    X(5, 256, 8, 0, 8)            \
+    X(6, 512, 4, 0, 8)            \
+    X(7, 512, 8, 0, 8)            \
+    X(8, 256, 2, 1, 8)            \
+    X(9, 256, 4, 1, 8)            \
+    X(10, 128, 1, 0, 8)           \
+    X(11, 256, 1, 0, 8)           \
+    X(12, 256, 4, 0, 2)           \
+    X(13, 256, 8, 0, 2)           \
+    X(14, 128, 4, 0, 2)           \
+    X(15, 512, 8, 0, 2)           \
+    X(16, 256, 1, 1, 8)           \
+    X(17, 128, 1, 1, 8)           \
+    X(18, 256, 4, 1, 2)           \
+    X(19, 256, 8, 1, 2)
+constexpr int kNumShapes = 20;
 int default_shape(int64_t n);
 tm_status launch_pack(const float* src, int64_t B, int64_t n, int64_t np, float* dst, hipStream_t s);
 tm_status launch_control(Workspace* w, int64_t B, int integ, hipStream_t s);
 tm_status launch_commit(const Problem* p, Workspace* w, int64_t B, hipStream_t s);
+// blocks per state of the last-stage launch = partial maxima to reduce
+int64_t last_stage_blocks(const Problem* p);
 tm_status launch_energy(const Problem* p, int64_t B, const float* X, const float* Ha,
                         const float* Hd, double* E, hipStream_t s);
 

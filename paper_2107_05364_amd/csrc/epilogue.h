@@ -126,5 +126,59 @@ __device__ void finish_tile(const DevProblem& P, const float* __restrict__ X, in
     }
 }
 
+
+// Dormand-Prince step control of one state: acceptance from the scaled
+// max-norm error e (accept iff e <= 1), next step h * min(5, max(0.2,
+// 0.9 e^-1/5)) (5 when e == 0), capped at t_end; done at the step cap, at
+// t_end, or (accepted) when max_a |dm/dt|_a falls below the threshold.
+struct Decision {
+    int acc;
+    double t, dt, h;
+    int64_t steps, rejected;
+    int32_t flags;
+};
+
+__device__ Decision dp_decide(const double* __restrict__ prm, double e, double dm, double hh,
+                              double t, double dt, int64_t steps, int64_t rej, int32_t f) {
+    Decision d{0, t, dt, 0.0, steps, rej, f};
+    if (f & (FLAG_DONE | FLAG_NONFINITE | FLAG_STEP)) return d;
+    if (!(e == e) || e == INFINITY || !(dm == dm)) {
+        d.flags = f | FLAG_NONFINITE;
+        return d;
+    }
+    const double t_end = prm[RP_TEND];
+    const bool ok = e <= 1.0;
+    if (ok) {
+        d.t = t + hh;
+        d.steps = steps + 1;
+    } else {
+        d.rejected = rej + 1;
+    }
+    d.acc = ok ? 1 : 0;
+    const double fac = (e == 0.0) ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(e, -0.2)));
+    double dn = hh * fac;
+    const bool converged = ok && prm[RP_DMDT_STOP] > 0.0 && dm < prm[RP_DMDT_STOP];
+    const bool done = static_cast<double>(d.steps) >= prm[RP_MAX_STEPS] ||
+                      (t_end > 0.0 && d.t >= t_end) || converged;
+    if (done && !converged && prm[RP_DMDT_STOP] > 0.0) d.flags |= FLAG_CAPPED;
+    if (t_end > 0.0 && d.t + dn > t_end) dn = t_end - d.t;
+    d.dt = done ? hh * fac : dn;
+    if (done)
+        d.flags |= FLAG_DONE;
+    else if (dn < prm[RP_DTMIN])
+        d.flags |= FLAG_STEP;
+    d.h = (d.flags & (FLAG_DONE | FLAG_STEP)) ? 0.0 : dn;
+    return d;
+}
+
+// Last stage: store the block's maxima (already reduced over the wave) for
+// the commit pass, which reduces them per state in fixed order.
+__device__ inline void report_partials(const EpiArgs& E, double rmax, double dmax, int lane) {
+    if (lane == 0) {
+        E.errp[blockIdx.y * E.pstride + blockIdx.x] = rmax;
+        E.dmxp[blockIdx.y * E.pstride + blockIdx.x] = dmax;
+    }
+}
+
 }  // namespace
 }  // namespace tmag

@@ -58,67 +58,77 @@ template <int BLOCK, int TT, int NT, int WPE, Epi MODE>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, WPE))) void k_field(
     DevProblem P, MvArgs M, EpiArgs E) {
     constexpr int NW = BLOCK / 64;
+    constexpr bool STEPPING = MODE == Epi::STAGE || MODE == Epi::RK4_FINAL || MODE == Epi::DP_LAST;
     const int s = blockIdx.y;
     const int a0 = blockIdx.x * TT;
-    const float* x = M.X + s * M.sx;
-    float acc[TT][3];
-#pragma unroll
-    for (int t = 0; t < TT; ++t) acc[t][0] = acc[t][1] = acc[t][2] = 0.0f;
-    int64_t rowoff[TT];
-#pragma unroll
-    for (int t = 0; t < TT; ++t) rowoff[t] = static_cast<int64_t>(min(a0 + t, M.n - 1)) * M.ld;
-
-    for (int64_t b = 4 * static_cast<int64_t>(threadIdx.x); b < M.ld; b += 4 * BLOCK) {
-        const float4 q0 = ld4(x + 3 * b), q1 = ld4(x + 3 * b + 4), q2 = ld4(x + 3 * b + 8);
-        const float4 ms = ld4(M.Ms + b);
-        const float mx0 = q0.x * ms.x, mx1 = q0.w * ms.y, mx2 = q1.z * ms.z, mx3 = q2.y * ms.w;
-        const float my0 = q0.y * ms.x, my1 = q1.x * ms.y, my2 = q1.w * ms.z, my3 = q2.z * ms.w;
-        const float mz0 = q0.z * ms.x, mz1 = q1.y * ms.y, mz2 = q2.x * ms.z, mz3 = q2.w * ms.w;
-#pragma unroll
-        for (int t = 0; t < TT; ++t) {
-            const float* tp = M.T + rowoff[t] + b;
-            const float4 xx = ldT<NT>(tp), xy = ldT<NT>(tp + M.plane),
-                         xz = ldT<NT>(tp + 2 * M.plane);
-            const float4 yy = ldT<NT>(tp + 3 * M.plane), yz = ldT<NT>(tp + 4 * M.plane),
-                         zz = ldT<NT>(tp + 5 * M.plane);
-            float hx = acc[t][0], hy = acc[t][1], hz = acc[t][2];
-            hx += xx.x * mx0 + xy.x * my0 + xz.x * mz0;
-            hy += xy.x * mx0 + yy.x * my0 + yz.x * mz0;
-            hz += xz.x * mx0 + yz.x * my0 + zz.x * mz0;
-            hx += xx.y * mx1 + xy.y * my1 + xz.y * mz1;
-            hy += xy.y * mx1 + yy.y * my1 + yz.y * mz1;
-            hz += xz.y * mx1 + yz.y * my1 + zz.y * mz1;
-            hx += xx.z * mx2 + xy.z * my2 + xz.z * mz2;
-            hy += xy.z * mx2 + yy.z * my2 + yz.z * mz2;
-            hz += xz.z * mx2 + yz.z * my2 + zz.z * mz2;
-            hx += xx.w * mx3 + xy.w * my3 + xz.w * mz3;
-            hy += xy.w * mx3 + yy.w * my3 + yz.w * mz3;
-            hz += xz.w * mx3 + yz.w * my3 + zz.w * mz3;
-            acc[t][0] = hx; acc[t][1] = hy; acc[t][2] = hz;
-        }
-    }
-    // fixed-order reduction: butterfly inside each wave, then across waves
-#pragma unroll
-    for (int t = 0; t < TT; ++t)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float v = acc[t][c];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            acc[t][c] = v;
-        }
-    __shared__ float red[NW][TT * 3];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
+    // a state that is done or failed has h = 0: its stages are skipped (the
+    // last stage still reports to the step control)
+    bool frozen = false;
+    if constexpr (STEPPING) frozen = E.h[s] == 0.0;
+    if constexpr (MODE == Epi::STAGE || MODE == Epi::RK4_FINAL) {
+        if (frozen) return;
+    }
+    __shared__ float red[NW][TT * 3];
+    if (!frozen) {
+        const float* x = M.X + s * M.sx;
+        float acc[TT][3];
+#pragma unroll
+        for (int t = 0; t < TT; ++t) acc[t][0] = acc[t][1] = acc[t][2] = 0.0f;
+        int64_t rowoff[TT];
+#pragma unroll
+        for (int t = 0; t < TT; ++t) rowoff[t] = static_cast<int64_t>(min(a0 + t, M.n - 1)) * M.ld;
+
+        for (int64_t b = 4 * static_cast<int64_t>(threadIdx.x); b < M.ld; b += 4 * BLOCK) {
+            const float4 q0 = ld4(x + 3 * b), q1 = ld4(x + 3 * b + 4), q2 = ld4(x + 3 * b + 8);
+            const float4 ms = ld4(M.Ms + b);
+            const float mx0 = q0.x * ms.x, mx1 = q0.w * ms.y, mx2 = q1.z * ms.z, mx3 = q2.y * ms.w;
+            const float my0 = q0.y * ms.x, my1 = q1.x * ms.y, my2 = q1.w * ms.z, my3 = q2.z * ms.w;
+            const float mz0 = q0.z * ms.x, mz1 = q1.y * ms.y, mz2 = q2.x * ms.z, mz3 = q2.w * ms.w;
+#pragma unroll
+            for (int t = 0; t < TT; ++t) {
+                const float* tp = M.T + rowoff[t] + b;
+                const float4 xx = ldT<NT>(tp), xy = ldT<NT>(tp + M.plane),
+                             xz = ldT<NT>(tp + 2 * M.plane);
+                const float4 yy = ldT<NT>(tp + 3 * M.plane), yz = ldT<NT>(tp + 4 * M.plane),
+                             zz = ldT<NT>(tp + 5 * M.plane);
+                float hx = acc[t][0], hy = acc[t][1], hz = acc[t][2];
+                hx += xx.x * mx0 + xy.x * my0 + xz.x * mz0;
+                hy += xy.x * mx0 + yy.x * my0 + yz.x * mz0;
+                hz += xz.x * mx0 + yz.x * my0 + zz.x * mz0;
+                hx += xx.y * mx1 + xy.y * my1 + xz.y * mz1;
+                hy += xy.y * mx1 + yy.y * my1 + yz.y * mz1;
+                hz += xz.y * mx1 + yz.y * my1 + zz.y * mz1;
+                hx += xx.z * mx2 + xy.z * my2 + xz.z * mz2;
+                hy += xy.z * mx2 + yy.z * my2 + yz.z * mz2;
+                hz += xz.z * mx2 + yz.z * my2 + zz.z * mz2;
+                hx += xx.w * mx3 + xy.w * my3 + xz.w * mz3;
+                hy += xy.w * mx3 + yy.w * my3 + yz.w * mz3;
+                hz += xz.w * mx3 + yz.w * my3 + zz.w * mz3;
+                acc[t][0] = hx; acc[t][1] = hy; acc[t][2] = hz;
+            }
+        }
+        // fixed-order reduction: butterfly inside each wave, then across waves
 #pragma unroll
         for (int t = 0; t < TT; ++t)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) red[wave][3 * t + c] = acc[t][c];
+            for (int c = 0; c < 3; ++c) {
+                float v = acc[t][c];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                acc[t][c] = v;
+            }
+        if (lane == 0) {
+#pragma unroll
+            for (int t = 0; t < TT; ++t)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) red[wave][3 * t + c] = acc[t][c];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (wave != 0) return;
     double rmax = 0.0, dmax = 0.0;
-    if (lane < TT && a0 + lane < M.n) {
+    if (!frozen && lane < TT && a0 + lane < M.n) {
         float h[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -135,10 +145,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, WPE)))
             rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
             dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
         }
-        if (lane == 0) {
-            atomicMax(E.err + s, static_cast<unsigned long long>(__double_as_longlong(rmax)));
-            atomicMax(E.dmx + s, static_cast<unsigned long long>(__double_as_longlong(dmax)));
-        }
+        report_partials(E, rmax, dmax, lane);
     }
 }
 
@@ -173,101 +180,102 @@ __global__ void k_pack(const float* __restrict__ src, int64_t n, int64_t np, int
     dst[i] = (r < 3 * n) ? src[s * 3 * n + r] : 0.0f;
 }
 
-// Per-state step control after the last stage (one thread per state).
-__global__ void k_control(int64_t B, int integ, const double* __restrict__ prm,
-                          double* __restrict__ t, double* __restrict__ h, double* __restrict__ dt,
-                          unsigned long long* __restrict__ err, unsigned long long* __restrict__ dmx,
-                          int64_t* __restrict__ steps, int64_t* __restrict__ rejected,
-                          int32_t* __restrict__ flags, int32_t* __restrict__ acc) {
+// RK4 step bookkeeping after the final stage (one thread per state).
+__global__ void k_control_rk4(int64_t B, const double* __restrict__ prm, double* __restrict__ t,
+                              double* __restrict__ h, double* __restrict__ dt,
+                              int64_t* __restrict__ steps, int32_t* __restrict__ flags) {
     const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= B) return;
-    const double t_end = prm[RP_TEND];
-    const double max_steps = prm[RP_MAX_STEPS];
-    const double e = __longlong_as_double(static_cast<long long>(err[s]));
-    const double dm = __longlong_as_double(static_cast<long long>(dmx[s]));
-    err[s] = 0ull;
-    dmx[s] = 0ull;
     int32_t f = flags[s];
     if (f & (FLAG_DONE | FLAG_NONFINITE | FLAG_STEP)) {
-        acc[s] = 0;
         h[s] = 0.0;
         return;
     }
-    const double hh = h[s];
-    double tn = t[s];
-    bool done = false;
-    if (integ == TM_RK4) {
-        tn += hh;
-        steps[s] += 1;
-        acc[s] = 1;
-        done = static_cast<double>(steps[s]) >= max_steps || (t_end > 0.0 && tn >= t_end);
-        t[s] = tn;
-        if (done) f |= FLAG_DONE;
-        flags[s] = f;
-        const double dn = dt[s];
-        h[s] = done ? 0.0 : (t_end > 0.0 ? fmin(dn, t_end - tn) : dn);
-        return;
-    }
-    if (!(e == e) || e == INFINITY || !(dm == dm)) {
-        flags[s] = f | FLAG_NONFINITE;
-        acc[s] = 0;
-        h[s] = 0.0;
-        return;
-    }
-    const bool ok = e <= 1.0;
-    if (ok) {
-        tn += hh;
-        steps[s] += 1;
-    } else {
-        rejected[s] += 1;
-    }
-    acc[s] = ok ? 1 : 0;
-    const double fac = (e == 0.0) ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(e, -0.2)));
-    double dn = hh * fac;
+    const double t_end = prm[RP_TEND];
+    const double tn = t[s] + h[s];
+    steps[s] += 1;
     t[s] = tn;
-    const bool converged = ok && prm[RP_DMDT_STOP] > 0.0 && dm < prm[RP_DMDT_STOP];
-    done = static_cast<double>(steps[s]) >= max_steps || (t_end > 0.0 && tn >= t_end) || converged;
-    // a state waiting for equilibrium that stops at the step cap is marked
-    if (done && !converged && prm[RP_DMDT_STOP] > 0.0) f |= FLAG_CAPPED;
-    if (t_end > 0.0 && tn + dn > t_end) dn = t_end - tn;
-    dt[s] = done ? hh * fac : dn;
-    if (done) {
-        f |= FLAG_DONE;
-    } else if (dn < prm[RP_DTMIN]) {
-        f |= FLAG_STEP;
-    }
+    const bool done = static_cast<double>(steps[s]) >= prm[RP_MAX_STEPS] || (t_end > 0.0 && tn >= t_end);
+    if (done) f |= FLAG_DONE;
     flags[s] = f;
-    h[s] = (f & (FLAG_DONE | FLAG_STEP)) ? 0.0 : dn;
+    const double dn = dt[s];
+    h[s] = done ? 0.0 : (t_end > 0.0 ? fmin(dn, t_end - tn) : dn);
 }
 
-// Accept / reject (DP45): on acceptance y <- y5 (renormalised), k1 <- k7;
-// then the next attempt's stage-2 input y + h a21 k1.
-__global__ void k_commit(int32_t n, int64_t np, int64_t B, float* __restrict__ y,
-                         float* __restrict__ k1, const float* __restrict__ y5,
-                         const float* __restrict__ k7, float* __restrict__ ya,
-                         const double* __restrict__ h, const int32_t* __restrict__ acc,
-                         const double* __restrict__ prm) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= B * np) return;
-    const int64_t s = i / np, a = i % np;
-    if (a >= n) return;
-    const int64_t o = s * 3 * np + 3 * a;
-    float v0 = y[o], v1 = y[o + 1], v2 = y[o + 2];
-    float g0 = k1[o], g1 = k1[o + 1], g2 = k1[o + 2];
-    if (acc[s]) {
-        v0 = y5[o]; v1 = y5[o + 1]; v2 = y5[o + 2];
-        if (prm[RP_RENORM] != 0.0) {
-            const float r = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
-            v0 *= r; v1 *= r; v2 *= r;
-        }
-        g0 = k7[o]; g1 = k7[o + 1]; g2 = k7[o + 2];
-        y[o] = v0; y[o + 1] = v1; y[o + 2] = v2;
-        k1[o] = g0; k1[o + 1] = g1; k1[o + 2] = g2;
+// Accept / reject of a Dormand-Prince attempt: one block per state reduces
+// the state's per-block error and |dm/dt| partials of the last stage (fixed
+// order), decides (dp_decide), writes the state's step control and applies
+// the step to every tile -- on acceptance y <- y5 (renormalised), k1 <- k7 --
+// then forms the next attempt's stage-2 input y + h a21 k1.  No block
+// depends on another.
+constexpr int kCommitThreads = 1024;
+
+__global__ __launch_bounds__(kCommitThreads) void k_commit(
+    int32_t n, int64_t np, float* __restrict__ y, float* __restrict__ k1,
+    const float* __restrict__ y5, const float* __restrict__ k7, float* __restrict__ ya,
+    const double* __restrict__ errp, const double* __restrict__ dmxp, int64_t pstride, int64_t nblk,
+    double* __restrict__ t, double* __restrict__ h, double* __restrict__ dt,
+    int64_t* __restrict__ steps, int64_t* __restrict__ rejected, int32_t* __restrict__ flags,
+    int32_t* __restrict__ acc, const double* __restrict__ prm) {
+    constexpr int NW = kCommitThreads / 64;
+    __shared__ double r0[NW], r1[NW];
+    const int64_t s = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double e = 0.0, dm = 0.0;
+    for (int64_t i = threadIdx.x; i < nblk; i += kCommitThreads) {
+        e = fmax(e, errp[s * pstride + i]);
+        dm = fmax(dm, dmxp[s * pstride + i]);
     }
-    const float hh = static_cast<float>(h[s]) * (1.0f / 5.0f);
-    ya[o] = v0 + hh * g0;
-    ya[o + 1] = v1 + hh * g1;
-    ya[o + 2] = v2 + hh * g2;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        e = fmax(e, __shfl_xor(e, off, 64));
+        dm = fmax(dm, __shfl_xor(dm, off, 64));
+    }
+    if (lane == 0) {
+        r0[wave] = e;
+        r1[wave] = dm;
+    }
+    __syncthreads();
+    e = r0[0];
+    dm = r1[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+        e = fmax(e, r0[w]);
+        dm = fmax(dm, r1[w]);
+    }
+    const Decision d = dp_decide(prm, e, dm, h[s], t[s], dt[s], steps[s], rejected[s], flags[s]);
+    __syncthreads();  // every thread has read the old control values
+    if (threadIdx.x == 0) {
+        t[s] = d.t;
+        dt[s] = d.dt;
+        h[s] = d.h;
+        steps[s] = d.steps;
+        rejected[s] = d.rejected;
+        flags[s] = d.flags;
+        acc[s] = d.acc;
+    }
+    const bool renorm = prm[RP_RENORM] != 0.0;
+    const float hh = static_cast<float>(d.h) * (1.0f / 5.0f);
+    for (int64_t a = threadIdx.x; a < n; a += kCommitThreads) {
+        const int64_t o = s * 3 * np + 3 * a;
+        float v0, v1, v2, g0, g1, g2;
+        if (d.acc) {
+            v0 = y5[o]; v1 = y5[o + 1]; v2 = y5[o + 2];
+            if (renorm) {
+                const float r = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+                v0 *= r; v1 *= r; v2 *= r;
+            }
+            g0 = k7[o]; g1 = k7[o + 1]; g2 = k7[o + 2];
+            y[o] = v0; y[o + 1] = v1; y[o + 2] = v2;
+            k1[o] = g0; k1[o + 1] = g1; k1[o + 2] = g2;
+        } else {
+            v0 = y[o]; v1 = y[o + 1]; v2 = y[o + 2];
+            g0 = k1[o]; g1 = k1[o + 1]; g2 = k1[o + 2];
+        }
+        ya[o] = v0 + hh * g0;
+        ya[o + 1] = v1 + hh * g1;
+        ya[o + 2] = v2 + hh * g2;
+    }
 }
 
 // Energy terms per state in float64: block partial sums, then a fixed-order
@@ -361,22 +369,10 @@ tm_status launch_field(const Problem* p, Epi mode, int64_t B, const float* X, co
     const DevProblem P = p->dev();
     const int shape = p->shape >= 0 ? p->shape : default_shape(p->n);
     switch (shape) {
-        case 0: return launch_tt<64, 2, 0, 8>(P, M, mode, B, e, s);
-        case 1: return launch_tt<128, 2, 0, 8>(P, M, mode, B, e, s);
-        case 2: return launch_tt<128, 4, 0, 8>(P, M, mode, B, e, s);
-        case 3: return launch_tt<256, 2, 0, 8>(P, M, mode, B, e, s);
-        case 4: return launch_tt<256, 4, 0, 8>(P, M, mode, B, e, s);
-        case 5: return launch_tt<256, 8, 0, 8>(P, M, mode, B, e, s);
-        case 6: return launch_tt<512, 4, 0, 8>(P, M, mode, B, e, s);
-        case 7: return launch_tt<512, 8, 0, 8>(P, M, mode, B, e, s);
-        case 8: return launch_tt<256, 2, 1, 8>(P, M, mode, B, e, s);
-        case 9: return launch_tt<256, 4, 1, 8>(P, M, mode, B, e, s);
-        case 10: return launch_tt<128, 1, 0, 8>(P, M, mode, B, e, s);
-        case 11: return launch_tt<256, 1, 0, 8>(P, M, mode, B, e, s);
-        case 12: return launch_tt<256, 4, 0, 2>(P, M, mode, B, e, s);
-        case 13: return launch_tt<256, 8, 0, 2>(P, M, mode, B, e, s);
-        case 14: return launch_tt<128, 4, 0, 2>(P, M, mode, B, e, s);
-        case 15: return launch_tt<512, 8, 0, 2>(P, M, mode, B, e, s);
+#define TM_SHAPE(i, BL, TT, NT, WPE) \
+    case i: return launch_tt<BL, TT, NT, WPE>(P, M, mode, B, e, s);
+        TM_FIELD_SHAPES(TM_SHAPE)
+#undef TM_SHAPE
         default: break;
     }
     set_error("unknown field-kernel shape %d", shape);
@@ -384,12 +380,14 @@ tm_status launch_field(const Problem* p, Epi mode, int64_t B, const float* X, co
 }
 
 int default_shape(int64_t n) {
-    // narrow workgroups for short rows so that every lane streams data
+    // measured on MI355X: one target tile per workgroup while the operator
+    // is cache-sized; nontemporal streaming once it is far larger than the
+    // 256 MB Infinity Cache
     const int64_t ld = round_up(n, 4);
     if (ld <= 256) return 0;
-    if (ld <= 1024) return 1;
-    if (n <= 4096) return 4;
-    return 5;
+    if (ld <= 1024) return 10;
+    if (n <= 8192) return 11;
+    return 8;
 }
 
 tm_status launch_pack(const float* src, int64_t B, int64_t n, int64_t np, float* dst,
@@ -401,17 +399,29 @@ tm_status launch_pack(const float* src, int64_t B, int64_t n, int64_t np, float*
 }
 
 tm_status launch_control(Workspace* w, int64_t B, int integ, hipStream_t s) {
-    k_control<<<static_cast<unsigned>((B + 255) / 256), 256, 0, s>>>(
-        B, integ, w->params, w->t, w->h, w->dt, w->err, w->dmx, w->steps, w->rejected, w->flags,
-        w->acc);
+    (void)integ;
+    k_control_rk4<<<static_cast<unsigned>((B + 255) / 256), 256, 0, s>>>(B, w->params, w->t, w->h,
+                                                                         w->dt, w->steps, w->flags);
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
 }
 
+
+int64_t last_stage_blocks(const Problem* p) {
+    if (p->T->layout == TM_LAYOUT_DENSE9 && p->T->prec != TM_PREC_FP64) return (p->n + 255) / 256;
+    static const int tt_of_shape[kNumShapes] = {
+#define TM_SHAPE(i, BL, TT, NT, WPE) TT,
+        TM_FIELD_SHAPES(TM_SHAPE)
+#undef TM_SHAPE
+    };
+    const int sh = p->shape >= 0 ? p->shape : default_shape(p->n);
+    return (p->n + tt_of_shape[sh] - 1) / tt_of_shape[sh];
+}
+
 tm_status launch_commit(const Problem* p, Workspace* w, int64_t B, hipStream_t s) {
-    const int64_t cnt = B * p->np;
-    k_commit<<<static_cast<unsigned>((cnt + 255) / 256), 256, 0, s>>>(
-        static_cast<int32_t>(p->n), p->np, B, w->y, w->k[0], w->y5, w->k[6], w->ya, w->h, w->acc,
+    k_commit<<<static_cast<unsigned>(B), kCommitThreads, 0, s>>>(
+        static_cast<int32_t>(p->n), p->np, w->y, w->k[0], w->y5, w->k[6], w->ya, w->errp, w->dmxp,
+        w->pstride, last_stage_blocks(p), w->t, w->h, w->dt, w->steps, w->rejected, w->flags, w->acc,
         w->params);
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;

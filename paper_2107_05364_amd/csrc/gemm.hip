@@ -232,14 +232,10 @@ __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __res
             red[1][wave] = dmax;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int w = 1; w < 4; ++w) {
-                rmax = fmax(rmax, red[0][w]);
-                dmax = fmax(dmax, red[1][w]);
-            }
-            atomicMax(E.err + s, static_cast<unsigned long long>(__double_as_longlong(rmax)));
-            atomicMax(E.dmx + s, static_cast<unsigned long long>(__double_as_longlong(dmax)));
-        }
+        if (wave != 0) return;
+        rmax = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+        dmax = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+        report_partials(E, rmax, dmax, lane);
     }
 }
 

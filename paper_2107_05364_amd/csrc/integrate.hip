@@ -34,7 +34,6 @@ constexpr double kDpA[7][6] = {
 __global__ void k_init_run(int64_t B, const double* __restrict__ t_in, const double* __restrict__ dt_in,
                            const double* __restrict__ prm, double* __restrict__ t,
                            double* __restrict__ h, double* __restrict__ dt,
-                           unsigned long long* __restrict__ err, unsigned long long* __restrict__ dmx,
                            int64_t* __restrict__ steps, int64_t* __restrict__ rejected,
                            int32_t* __restrict__ flags, int32_t* __restrict__ acc) {
     const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -48,8 +47,6 @@ __global__ void k_init_run(int64_t B, const double* __restrict__ t_in, const dou
     if (prm[RP_MAX_STEPS] <= 0.0 || (t_end > 0.0 && t0 >= t_end)) f = FLAG_DONE;
     h[s] = f ? 0.0 : hh;
     flags[s] = f;
-    err[s] = 0ull;
-    dmx[s] = 0ull;
     steps[s] = 0;
     rejected[s] = 0;
     acc[s] = 0;
@@ -76,8 +73,9 @@ EpiArgs stage_args(Workspace* w, float* kout, const float* const* kprev, int npr
     e.ynext = ynext;
     e.h = w->h;
     e.params = w->params;
-    e.err = w->err;
-    e.dmx = w->dmx;
+    e.errp = w->errp;
+    e.dmxp = w->dmxp;
+    e.pstride = w->pstride;
     return e;
 }
 
@@ -104,9 +102,7 @@ tm_status dp_attempt(const Problem* p, Workspace* w, int64_t B, hipStream_t s) {
     EpiArgs e = stage_args(w, w->k[6], kp, 6, none, nullptr);
     tm_status r = launch_field(p, Epi::DP_LAST, B, w->y5, e, s);
     if (r != TM_OK) return r;
-    r = launch_control(w, B, TM_DP45, s);
-    if (r != TM_OK) return r;
-    return launch_commit(p, w, B, s);
+    return launch_commit(p, w, B, s);  // step control fused into the commit pass
 }
 
 // One classical RK4 step.
@@ -159,16 +155,13 @@ tm_status capture(const Problem* p, Workspace* w, int integ, int64_t B, int reno
 
 namespace {
 __global__ void k_init_slot(int64_t i, double dt0, double* __restrict__ t, double* __restrict__ h,
-                            double* __restrict__ dt, unsigned long long* __restrict__ err,
-                            unsigned long long* __restrict__ dmx, int64_t* __restrict__ steps,
+                            double* __restrict__ dt, int64_t* __restrict__ steps,
                             int64_t* __restrict__ rejected, int32_t* __restrict__ flags,
                             int32_t* __restrict__ acc) {
     if (threadIdx.x != 0) return;
     t[i] = 0.0;
     dt[i] = dt0;
     h[i] = dt0;
-    err[i] = 0ull;
-    dmx[i] = 0ull;
     steps[i] = 0;
     rejected[i] = 0;
     flags[i] = 0;
@@ -185,8 +178,7 @@ __global__ void k_free_slot(int64_t i, double* __restrict__ h, int32_t* __restri
 // Starts state `i` of a batch: control reset, k1 = f(y_i) and the first
 // stage input, touching no other state.
 tm_status start_slot(const Problem* p, Workspace* w, int64_t i, double dt0, hipStream_t s) {
-    k_init_slot<<<1, 64, 0, s>>>(i, dt0, w->t, w->h, w->dt, w->err, w->dmx, w->steps, w->rejected,
-                                 w->flags, w->acc);
+    k_init_slot<<<1, 64, 0, s>>>(i, dt0, w->t, w->h, w->dt, w->steps, w->rejected, w->flags, w->acc);
     TM_TRY_HIP(hipGetLastError());
     const int64_t o = i * 3 * p->np;
     const double c[1] = {kDpA[1][0]};
@@ -250,8 +242,7 @@ extern "C" tm_status tm_run(tm_problem* pp, tm_integrator integ, int64_t B, floa
     else
         TM_TRY_HIP(hipMemsetAsync(w->Ha, 0, B * 12, s));
     k_init_run<<<static_cast<unsigned>((B + 255) / 256), 256, 0, s>>>(
-        B, t, dt, w->params, w->t, w->h, w->dt, w->err, w->dmx, w->steps, w->rejected, w->flags,
-        w->acc);
+        B, t, dt, w->params, w->t, w->h, w->dt, w->steps, w->rejected, w->flags, w->acc);
     TM_TRY_HIP(hipGetLastError());
     if (integ == TM_DP45) {
         st = dp_first(p, w, B, s);
@@ -344,6 +335,11 @@ extern "C" tm_status tm_run(tm_problem* pp, tm_integrator integ, int64_t B, floa
 namespace tmag {
 namespace {
 
+__global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 // Times `iters` launches of one epilogue variant of the field kernel on the
 // problem's workspace (inputs and outputs never alias).
 tm_status time_field(Problem* p, int64_t B, int mode, int32_t iters, hipStream_t s, double* avg_ms) {
@@ -370,6 +366,9 @@ tm_status time_field(Problem* p, int64_t B, int mode, int32_t iters, hipStream_t
         ep = Epi::STAGE;
         X = w->ya;
     }
+    // stages of a state with h = 0 are skipped: give every state a step
+    k_fill<<<static_cast<unsigned>((B + 255) / 256), 256, 0, s>>>(w->h, B, 1e-15);
+    TM_TRY_HIP(hipGetLastError());
     hipEvent_t e0, e1;
     TM_TRY_HIP(hipEventCreate(&e0));
     TM_TRY_HIP(hipEventCreate(&e1));
@@ -411,6 +410,28 @@ extern "C" tm_status tm_profile_field(tm_problem* pp, int64_t B, int32_t iters, 
 }
 
 extern "C" int32_t tm_num_shapes(void) { return kNumShapes; }
+
+extern "C" tm_status tm_shape_info(int32_t shape, int32_t* threads, int32_t* tiles,
+                                   int32_t* nontemporal, int32_t* waves_cap) {
+    TM_REQUIRE(shape >= 0 && shape < kNumShapes, TM_EINVAL, "tm_shape_info: bad shape %d", shape);
+    static const int32_t tab[kNumShapes][4] = {
+#define TM_SHAPE(i, BL, TT, NT, WPE) {BL, TT, NT, WPE},
+        TM_FIELD_SHAPES(TM_SHAPE)
+#undef TM_SHAPE
+    };
+    if (threads) *threads = tab[shape][0];
+    if (tiles) *tiles = tab[shape][1];
+    if (nontemporal) *nontemporal = tab[shape][2];
+    if (waves_cap) *waves_cap = tab[shape][3];
+    return TM_OK;
+}
+
+extern "C" tm_status tm_problem_shape(const tm_problem* pp, int32_t* shape) {
+    const Problem* p = reinterpret_cast<const Problem*>(pp);
+    TM_REQUIRE(p && shape, TM_EINVAL, "tm_problem_shape: null argument");
+    *shape = p->shape >= 0 ? p->shape : default_shape(p->n);
+    return TM_OK;
+}
 
 extern "C" tm_status tm_problem_set_shape(tm_problem* pp, int32_t shape) {
     Problem* p = reinterpret_cast<Problem*>(pp);

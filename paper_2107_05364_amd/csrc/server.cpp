@@ -117,7 +117,7 @@ namespace {
 
 int64_t workspace_bytes(int64_t n, int64_t B) {
     const int64_t np = round_up(n, 64);
-    return 12 * B * 3 * np * 4 + B * 128 + 4096 + ((n + 255) / 256) * B * 32;
+    return 12 * B * 3 * np * 4 + B * 128 + 16 * B * n + 4096 + ((n + 255) / 256) * B * 32;
 }
 
 }  // namespace

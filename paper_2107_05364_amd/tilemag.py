@@ -34,7 +34,8 @@ EXPORTS = [
     "tm_geometry_create", "tm_geometry_hash", "tm_geometry_info", "tm_geometry_destroy",
     "tm_tensor_assemble", "tm_tensor_get", "tm_tensor_rows", "tm_tensor_bytes", "tm_tensor_release",
     "tm_problem_create", "tm_problem_destroy", "tm_demag", "tm_heff", "tm_dmdt", "tm_energy",
-    "tm_run", "tm_profile_field", "tm_profile_field_mode", "tm_num_shapes", "tm_problem_set_shape",
+    "tm_run", "tm_profile_field", "tm_profile_field_mode", "tm_num_shapes", "tm_shape_info",
+    "tm_problem_shape", "tm_problem_set_shape",
     "tm_problem_tune", "tm_server_create", "tm_server_submit", "tm_server_poll", "tm_server_destroy",
 ]
 
@@ -129,6 +130,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "tm_profile_field": (i32, [vp, i64, i32, vp, P(d), P(i64)]),
         "tm_profile_field_mode": (i32, [vp, i64, i32, i32, vp, P(d), P(i64)]),
         "tm_num_shapes": (i32, []),
+        "tm_shape_info": (i32, [i32, P(i32), P(i32), P(i32), P(i32)]),
+        "tm_problem_shape": (i32, [vp, P(i32)]),
         "tm_problem_set_shape": (i32, [vp, i32]),
         "tm_problem_tune": (i32, [vp, i64, i32, vp, P(i32), P(d)]),
         "tm_server_create": (i32, [vp, P(tm_server_cfg), P(vp)]),
@@ -376,6 +379,19 @@ def tm_profile_field_mode(p, B: int, mode: int, iters: int):
 
 def tm_num_shapes() -> int:
     return int(load().tm_num_shapes())
+
+
+def tm_shape_info(shape: int):
+    """(threads per workgroup, target tiles per workgroup, nontemporal, waves cap)."""
+    v = [C.c_int32() for _ in range(4)]
+    _check(load().tm_shape_info(int(shape), *[C.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def tm_problem_shape(p) -> int:
+    v = C.c_int32()
+    _check(load().tm_problem_shape(p, C.byref(v)))
+    return v.value
 
 
 def tm_problem_set_shape(p, shape: int) -> None:
