@@ -329,8 +329,7 @@ def main():
     # the stream it runs on
     avg_ms, bytes_per = tmg.tm_profile_field(p.handle, 1, args.profile_iters)
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9
-    bl, tt, nt, wpe = tmg.tm_shape_info(shape)
-    kname = "k_field<%d,%d,%d,%d,STAGE>" % (bl, tt, nt, wpe)
+    kname = "k_field<%d,%d,%d,%d,STAGE>" % tmg.tm_shape_info(shape)
     traffic = counter_traffic(kname)
 
     rec = {

@@ -173,8 +173,6 @@ tm_status tm_geometry_destroy(tm_geom* g) {
     return TM_OK;
 }
 
-static int64_t padded_tiles(int64_t n) { return round_up(n, 64); }
-
 tm_status tm_tensor_assemble(tm_ctx* c, const tm_geom* g, tm_prec store, tm_layout layout,
                              hipStream_t stream, tm_tensor** out) {
     TM_REQUIRE(c && g && out, TM_EINVAL, "tm_tensor_assemble: null argument");

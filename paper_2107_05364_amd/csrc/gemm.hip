@@ -36,9 +36,10 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 constexpr int kRowsPerBlock = 128;  // 4 waves x 2 tiles x 16 rows
-constexpr int kKC = 64;             // K elements staged per chunk
+constexpr int kKC = 128;            // K elements per chunk (X double-buffered in LDS)
 
 struct GemmArgs {
     int64_t ld;         // K extent (= 3 np) and operator row stride
@@ -66,21 +67,40 @@ struct Elt<2> { using T = _Float16; static constexpr int kPerLane = 8; };
 template <int PREC>
 constexpr int lds_row_bytes() { return kKC * static_cast<int>(sizeof(typename Elt<PREC>::T)) + 16; }
 
+// Software pipeline per K chunk c (kKC = 128): the operator rows and the X
+// tile of chunk c+1 are loaded into registers while the MFMAs of chunk c run
+// from LDS buffer c&1; the X tile then goes to buffer (c+1)&1, which no wave
+// reads any more (all passed the barrier after chunk c-1).  One barrier per
+// chunk.  A chunk carries enough MFMA work (split: 192 per wave) to cover
+// the latency of the next chunk's loads, and MFMAs are issued across
+// independent accumulators so that none waits for its predecessor.
 template <int PREC, int NST>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
     using T = typename Elt<PREC>::T;
     constexpr bool SPLIT = PREC != 0;
     constexpr int RB = lds_row_bytes<PREC>();
     constexpr int NS = NST * 16;
-    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-    unsigned char* xh_s = lds;
-    unsigned char* xl_s = lds + NS * RB;
+    constexpr int CHUNK16 = kKC * static_cast<int>(sizeof(T)) / 16;  // 16-byte pieces per state row
+    constexpr int XPIECES = NS * CHUNK16;
+    constexpr int XPT = (XPIECES + 255) / 256;  // pieces per thread and array
+    constexpr int BUF = NS * RB * (SPLIT ? 2 : 1);
+    constexpr int NSUB = PREC == 0 ? kKC / 16 : kKC / 32;
+    using AV = typename std::conditional<PREC == 0, float4,
+                                         typename std::conditional<PREC == 1, v8bf, v8h>::type>::type;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, j = lane & 15;
     const int64_t rowbase = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock + wave * 32;
     const int64_t kb = static_cast<int64_t>(blockIdx.y) * G.kper;
     const int64_t ke = min(kb + G.kper, G.ld);
+    const int nch = static_cast<int>((ke - kb) / kKC);
+
+    const T* Ah = static_cast<const T*>(G.Ahi);
+    const T* Al = static_cast<const T*>(G.Alo);
+    const unsigned char* Xh = static_cast<const unsigned char*>(G.Xhi);
+    const unsigned char* Xl = static_cast<const unsigned char*>(G.Xlo);
+    const int64_t xrow = G.ld * static_cast<int64_t>(sizeof(T));  // bytes per state row
 
     v4f acc[2][NST];
 #pragma unroll
@@ -88,78 +108,126 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
 #pragma unroll
         for (int s = 0; s < NST; ++s) acc[r][s] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    const T* Ah = static_cast<const T*>(G.Ahi);
-    const T* Al = static_cast<const T*>(G.Alo);
-    const T* Xh = static_cast<const T*>(G.Xhi);
-    const T* Xl = static_cast<const T*>(G.Xlo);
-    constexpr int CHUNK16 = kKC * static_cast<int>(sizeof(T)) / 16;  // 16-byte pieces per state row
+    v4u xh_r[XPT], xl_r[XPT];
+    AV ah_r[NSUB][2], al_r[NSUB][2], ah_n[NSUB][2], al_n[NSUB][2];
 
-    for (int64_t k0 = kb; k0 < ke; k0 += kKC) {
-        // stage X[0..NS)[k0..k0+kKC) into LDS (16-byte pieces)
-        __syncthreads();
-        for (int q = threadIdx.x; q < NS * CHUNK16; q += 256) {
-            const int st = q / CHUNK16, pc = q % CHUNK16;
-            const int64_t off = static_cast<int64_t>(st) * G.ld + k0;
-            const uint4 vh = *reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(Xh + off) + 16 * pc);
-            *reinterpret_cast<uint4*>(xh_s + st * RB + 16 * pc) = vh;
-            if constexpr (SPLIT) {
-                const uint4 vl = *reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(Xl + off) + 16 * pc);
-                *reinterpret_cast<uint4*>(xl_s + st * RB + 16 * pc) = vl;
+    auto load_x = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < XPT; ++q) {
+            const int idx = threadIdx.x + 256 * q;
+            if (XPIECES % 256 == 0 || idx < XPIECES) {
+                const int st = idx / CHUNK16, pc = idx % CHUNK16;
+                const int64_t off = st * xrow + k0 * static_cast<int64_t>(sizeof(T)) + 16 * pc;
+                xh_r[q] = *reinterpret_cast<const v4u*>(Xh + off);
+                if constexpr (SPLIT) xl_r[q] = *reinterpret_cast<const v4u*>(Xl + off);
             }
         }
-        __syncthreads();
-        if constexpr (PREC == 0) {
-            // 4 sub-steps of 16 k; lane group g covers k = 16 sub + 4 g + q
+    };
+    auto store_x = [&](int buf) {
+        unsigned char* base = lds + buf * BUF;
 #pragma unroll
-            for (int sub = 0; sub < 4; ++sub) {
-                const int kk = 16 * sub + 4 * g;
-                float4 a[2];
+        for (int q = 0; q < XPT; ++q) {
+            const int idx = threadIdx.x + 256 * q;
+            if (XPIECES % 256 == 0 || idx < XPIECES) {
+                const int st = idx / CHUNK16, pc = idx % CHUNK16;
+                *reinterpret_cast<v4u*>(base + st * RB + 16 * pc) = xh_r[q];
+                if constexpr (SPLIT) *reinterpret_cast<v4u*>(base + NS * RB + st * RB + 16 * pc) = xl_r[q];
+            }
+        }
+    };
+    // the next chunk's operator rows always land in ah_n / al_n and the MFMAs
+    // always read ah_r / al_r (fixed arrays keep everything in registers)
+    auto load_a_next = [&](int64_t k0) {
 #pragma unroll
-                for (int rt = 0; rt < 2; ++rt)
-                    a[rt] = *reinterpret_cast<const float4*>(Ah + (rowbase + 16 * rt + j) * G.ld + k0 + kk);
+        for (int sub = 0; sub < NSUB; ++sub)
 #pragma unroll
-                for (int st = 0; st < NST; ++st) {
-                    const float4 b = *reinterpret_cast<const float4*>(xh_s + (16 * st + j) * RB + 4 * kk);
-#pragma unroll
-                    for (int rt = 0; rt < 2; ++rt) {
-                        acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].x, b.x, acc[rt][st], 0, 0, 0);
-                        acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].y, b.y, acc[rt][st], 0, 0, 0);
-                        acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].z, b.z, acc[rt][st], 0, 0, 0);
-                        acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].w, b.w, acc[rt][st], 0, 0, 0);
-                    }
+            for (int rt = 0; rt < 2; ++rt) {
+                const int64_t row = rowbase + 16 * rt + j;
+                if constexpr (PREC == 0) {
+                    ah_n[sub][rt] = *reinterpret_cast<const float4*>(Ah + row * G.ld + k0 + 16 * sub + 4 * g);
+                } else {
+                    const int64_t off = row * G.ld + k0 + 32 * sub + 8 * g;
+                    ah_n[sub][rt] = *reinterpret_cast<const AV*>(Ah + off);
+                    al_n[sub][rt] = *reinterpret_cast<const AV*>(Al + off);
                 }
             }
-        } else {
-            using V8 = typename std::conditional<PREC == 1, v8bf, v8h>::type;
-            // 2 sub-steps of 32 k; lane group g covers k = 32 sub + 8 g .. + 7
+    };
+    auto rotate = [&]() {
 #pragma unroll
-            for (int sub = 0; sub < 2; ++sub) {
-                const int kk = 32 * sub + 8 * g;
-                V8 ah[2], al[2];
+        for (int sub = 0; sub < NSUB; ++sub)
 #pragma unroll
-                for (int rt = 0; rt < 2; ++rt) {
-                    const int64_t off = (rowbase + 16 * rt + j) * G.ld + k0 + kk;
-                    ah[rt] = *reinterpret_cast<const V8*>(Ah + off);
-                    al[rt] = *reinterpret_cast<const V8*>(Al + off);
-                }
+            for (int rt = 0; rt < 2; ++rt) {
+                ah_r[sub][rt] = ah_n[sub][rt];
+                if constexpr (SPLIT) al_r[sub][rt] = al_n[sub][rt];
+            }
+    };
+    auto compute = [&](int buf) {
+        const auto& hi = ah_r;
+        const auto& lo = al_r;
+        const unsigned char* xs = lds + buf * BUF;
 #pragma unroll
-                for (int st = 0; st < NST; ++st) {
-                    const V8 bh = *reinterpret_cast<const V8*>(xh_s + (16 * st + j) * RB + 2 * kk);
-                    const V8 bl = *reinterpret_cast<const V8*>(xl_s + (16 * st + j) * RB + 2 * kk);
+        for (int sub = 0; sub < NSUB; ++sub) {
+            if constexpr (PREC == 0) {
+                float4 b[NST];
 #pragma unroll
-                    for (int rt = 0; rt < 2; ++rt) {
-                        if constexpr (PREC == 1) {
-                            acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rt], bh, acc[rt][st], 0, 0, 0);
-                            acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rt], bl, acc[rt][st], 0, 0, 0);
-                            acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rt], bh, acc[rt][st], 0, 0, 0);
-                        } else {
-                            acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rt], bh, acc[rt][st], 0, 0, 0);
-                            acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rt], bl, acc[rt][st], 0, 0, 0);
-                            acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[rt], bh, acc[rt][st], 0, 0, 0);
+                for (int st = 0; st < NST; ++st)
+                    b[st] = *reinterpret_cast<const float4*>(xs + (16 * st + j) * RB + 4 * (16 * sub + 4 * g));
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int st = 0; st < NST; ++st)
+#pragma unroll
+                        for (int rt = 0; rt < 2; ++rt) {
+                            const float av = q == 0 ? hi[sub][rt].x : q == 1 ? hi[sub][rt].y : q == 2 ? hi[sub][rt].z : hi[sub][rt].w;
+                            const float bv = q == 0 ? b[st].x : q == 1 ? b[st].y : q == 2 ? b[st].z : b[st].w;
+                            acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[rt][st], 0, 0, 0);
                         }
+            } else {
+                const int kk = 32 * sub + 8 * g;
+#pragma unroll
+                for (int st = 0; st < NST; ++st) {
+                    const AV bh = *reinterpret_cast<const AV*>(xs + (16 * st + j) * RB + 2 * kk);
+                    const AV bl = *reinterpret_cast<const AV*>(xs + NS * RB + (16 * st + j) * RB + 2 * kk);
+                    // three independent products over two accumulators
+                    if constexpr (PREC == 1) {
+                        acc[0][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[sub][0], bh, acc[0][st], 0, 0, 0);
+                        acc[1][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[sub][1], bh, acc[1][st], 0, 0, 0);
+                        acc[0][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[sub][0], bl, acc[0][st], 0, 0, 0);
+                        acc[1][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[sub][1], bl, acc[1][st], 0, 0, 0);
+                        acc[0][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[sub][0], bh, acc[0][st], 0, 0, 0);
+                        acc[1][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[sub][1], bh, acc[1][st], 0, 0, 0);
+                    } else {
+                        acc[0][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi[sub][0], bh, acc[0][st], 0, 0, 0);
+                        acc[1][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi[sub][1], bh, acc[1][st], 0, 0, 0);
+                        acc[0][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi[sub][0], bl, acc[0][st], 0, 0, 0);
+                        acc[1][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi[sub][1], bl, acc[1][st], 0, 0, 0);
+                        acc[0][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo[sub][0], bh, acc[0][st], 0, 0, 0);
+                        acc[1][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo[sub][1], bh, acc[1][st], 0, 0, 0);
                     }
                 }
             }
+        }
+    };
+
+    if (nch > 0) {
+        load_x(kb);
+        load_a_next(kb);
+        rotate();
+        store_x(0);
+        __syncthreads();
+        for (int c = 0; c < nch; ++c) {
+            const bool more = c + 1 < nch;
+            const int64_t k1 = kb + static_cast<int64_t>(c + 1) * kKC;
+            if (more) {
+                load_x(k1);
+                load_a_next(k1);
+            }
+            compute(c & 1);
+            if (more) {
+                store_x((c + 1) & 1);
+                rotate();
+            }
+            __syncthreads();
         }
     }
     // D[4 g + r][j] of tile (rt, st) -> part[split][state 16 st + j][row rowbase + 16 rt + 4 g + r]
@@ -241,8 +309,7 @@ __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __res
 
 template <int PREC, int NST>
 tm_status launch_gemm_t(const GemmArgs& G, int64_t rowblocks, int64_t splits, hipStream_t s) {
-    const size_t lds = static_cast<size_t>(NST * 16) * lds_row_bytes<PREC>() * (PREC ? 2 : 1);
-    k_gemm<PREC, NST><<<dim3(static_cast<unsigned>(rowblocks), static_cast<unsigned>(splits)), 256, lds, s>>>(G);
+    k_gemm<PREC, NST><<<dim3(static_cast<unsigned>(rowblocks), static_cast<unsigned>(splits)), 256, 0, s>>>(G);
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
 }
@@ -270,7 +337,9 @@ int gemm_state_tiles(int64_t B) {
 int64_t gemm_splits(const Problem* p) {
     const int64_t rowblocks = p->T->rows / kRowsPerBlock;
     const int64_t kchunks = p->T->ld / kKC;
-    int64_t s = (512 + rowblocks - 1) / rowblocks;
+    // about one workgroup per CU (the split-precision kernel holds ~139 KB of LDS)
+    int64_t s = (256 + rowblocks - 1) / rowblocks;
+    if (s > 1 && rowblocks * s > 256 + rowblocks / 2) s -= 1;
     return std::max<int64_t>(1, std::min<int64_t>(s, std::min<int64_t>(kchunks, 16)));
 }
 
@@ -280,6 +349,9 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     Workspace* w = p->ws.get();
     TM_REQUIRE(w && w->part && B <= 128 && w->bpad >= 16 * gemm_state_tiles(B), TM_EINVAL,
                "batched product: workspace not prepared for %lld states", static_cast<long long>(B));
+    TM_REQUIRE(T->ld % kKC == 0 && T->rows % kRowsPerBlock == 0 && T->rows >= T->ld, TM_EINVAL,
+               "batched product: operator extent %lld x %lld is not a whole number of tiles",
+               static_cast<long long>(T->rows), static_cast<long long>(T->ld));
     const int prec = T->prec == TM_PREC_FP32 ? 0 : T->prec == TM_PREC_BF16X3 ? 1 : 2;
     const int64_t ld = T->ld;
     // right operand

@@ -116,7 +116,7 @@ struct tm_server {
 namespace {
 
 int64_t workspace_bytes(int64_t n, int64_t B) {
-    const int64_t np = round_up(n, 64);
+    const int64_t np = padded_tiles(n);
     return 12 * B * 3 * np * 4 + B * 128 + 16 * B * n + 4096 + ((n + 255) / 256) * B * 32;
 }
 
