@@ -49,6 +49,8 @@ def lib():
         L.orc_assemble.argtypes = [i64, d, d, d]
         L.orc_demag.argtypes = [i64, d, d, d, d]
         L.orc_demag_rows.argtypes = [i64, d, d, d, d, i64, C.POINTER(i64), d]
+        L.orc_threshold.argtypes = [i64, d, C.c_double]
+        L.orc_threshold.restype = C.c_double
         L.orc_faces.argtypes = [i64, d, d, i64, C.POINTER(i64), C.POINTER(i64), d, d]
         L.orc_faces.restype = i64
         L.orc_num_threads.restype = C.c_int
@@ -124,6 +126,19 @@ def demag(T, Ms, m) -> np.ndarray:
     out = np.empty((n, 3))
     lib().orc_demag(n, _p(T), _p(Ms), _p(m), _p(out))
     return out
+
+
+def threshold(T, frac: float):
+    """Copy of the dense operator with the smallest ``frac`` of its nonzero
+    entries (float32 magnitudes, ties at the cut included) set to zero and
+    self blocks kept (paper Sec. 4.3.1); returns (operator, cut), cut = -1
+    when nothing is removed."""
+    if not 0.0 <= frac <= 1.0:
+        raise ValueError("threshold fraction must lie in [0, 1]")
+    out = np.array(T, dtype=np.float64, order="C", copy=True)
+    n = out.shape[0] // 3
+    cut = lib().orc_threshold(n, _p(out), float(frac))
+    return out, float(cut)
 
 
 def demag_rows(centers, sizes, Ms, m, rows) -> np.ndarray:

@@ -149,6 +149,45 @@ void orc_demag(int64_t n, const double* T, const double* Ms, const double* m, do
     }
 }
 
+/* Thresholded operator (paper Sec. 4.3.1): of the nonzero entries of the
+ * dense operator, the fraction `frac` with the smallest magnitude is set to
+ * zero, and what is left is kept as a sparse matrix.  Readings of that
+ * passage: the ranking is over the magnitudes that float storage holds (each
+ * FP64 entry rounded to float32) and counts all 9 entries of every 3x3 block,
+ * self blocks included; with K nonzero entries the cut is the r-th smallest
+ * magnitude, r = ceil(frac K); every entry whose magnitude is at most the cut
+ * is removed (ties at the cut go too); entries of self blocks (a == b) are
+ * never removed.  frac = 0 removes nothing.  Works in place on T [3n][3n] and
+ * returns the cut (-1 when nothing is removed). */
+static int orc_cmp_double(const void* x, const void* y) {
+    double a = *(const double*)x, b = *(const double*)y;
+    return (a > b) - (a < b);
+}
+
+double orc_threshold(int64_t n, double* T, double frac) {
+    int64_t ld = 3 * n, K = 0;
+    double* v = (double*)malloc(sizeof(double) * (size_t)(ld * ld));
+    for (int64_t i = 0; i < ld * ld; ++i) {
+        double mag = fabs((double)(float)T[i]);
+        if (mag > 0.0) v[K++] = mag;
+    }
+    int64_t r = (int64_t)ceil(frac * (double)K);
+    if (r > K) r = K;
+    double cut = -1.0;
+    if (r > 0) {
+        qsort(v, (size_t)K, sizeof(double), orc_cmp_double);
+        cut = v[r - 1];
+        for (int64_t row = 0; row < ld; ++row)
+            for (int64_t col = 0; col < ld; ++col) {
+                if (row / 3 == col / 3) continue;
+                double* e = T + row * ld + col;
+                if (fabs((double)(float)*e) <= cut) *e = 0.0;
+            }
+    }
+    free(v);
+    return cut;
+}
+
 /* Same field at selected target tiles only, evaluating the tensor on the fly
  * (for meshes whose dense operator does not fit in host memory). */
 void orc_demag_rows(int64_t n, const double* centers, const double* sizes, const double* Ms,

@@ -23,10 +23,15 @@ MUTANTS = {
                      "dmdt[3 * a + 0] = -P->c1 * p0 + P->c2 * q0;"),
     "tableau_bstar": ("-92097.0 / 339200", "-92097.0 / 339000"),
     "demag_scale": ("const double k = 1.0 / (4.0 * ORC_PI);", "const double k = 1.0 / (4.0 * 3.14);"),
+    "threshold_ties_kept": ("if (fabs((double)(float)*e) <= cut) *e = 0.0;",
+                            "if (fabs((double)(float)*e) < cut) *e = 0.0;"),
+    "threshold_rank_floor": ("int64_t r = (int64_t)ceil(frac * (double)K);",
+                             "int64_t r = (int64_t)floor(frac * (double)K);"),
+    "threshold_self_blocks": ("if (row / 3 == col / 3) continue;", "if (row < 0) continue;"),
 }
 
 PIN_FILES = ["tests/test_oracle_tensor.py", "tests/test_oracle_fields.py",
-             "tests/test_oracle_dynamics.py"]
+             "tests/test_oracle_dynamics.py", "tests/test_oracle_threshold.py"]
 
 
 @pytest.mark.slow
