@@ -128,11 +128,14 @@ def demag(T, Ms, m) -> np.ndarray:
     return out
 
 
+ZERO_FLOOR = 1e-14  # magnitudes at or below this (as float32) count as zero when thresholding
+
+
 def threshold(T, frac: float):
     """Copy of the dense operator with the smallest ``frac`` of its nonzero
-    entries (float32 magnitudes, ties at the cut included) set to zero and
-    self blocks kept (paper Sec. 4.3.1); returns (operator, cut), cut = -1
-    when nothing is removed."""
+    entries (float32 magnitudes above ZERO_FLOOR, ties at the cut included)
+    set to zero and self blocks kept (paper Sec. 4.3.1); returns (operator,
+    cut), cut = -1 when nothing is removed."""
     if not 0.0 <= frac <= 1.0:
         raise ValueError("threshold fraction must lie in [0, 1]")
     out = np.array(T, dtype=np.float64, order="C", copy=True)

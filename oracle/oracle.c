@@ -154,11 +154,16 @@ void orc_demag(int64_t n, const double* T, const double* Ms, const double* m, do
  * zero, and what is left is kept as a sparse matrix.  Readings of that
  * passage: the ranking is over the magnitudes that float storage holds (each
  * FP64 entry rounded to float32) and counts all 9 entries of every 3x3 block,
- * self blocks included; with K nonzero entries the cut is the r-th smallest
+ * self blocks included; an entry counts as nonzero when its magnitude exceeds
+ * ORC_ZERO_FLOOR, the absolute accuracy of the float64 assembly (entries that
+ * vanish by symmetry come out as rounding noise of ~1e-17 or as exact zeros
+ * depending on the evaluation order; physical entries on meshes below 100 um
+ * are far larger); with K nonzero entries the cut is the r-th smallest
  * magnitude, r = ceil(frac K); every entry whose magnitude is at most the cut
  * is removed (ties at the cut go too); entries of self blocks (a == b) are
  * never removed.  frac = 0 removes nothing.  Works in place on T [3n][3n] and
  * returns the cut (-1 when nothing is removed). */
+#define ORC_ZERO_FLOOR 1e-14
 static int orc_cmp_double(const void* x, const void* y) {
     double a = *(const double*)x, b = *(const double*)y;
     return (a > b) - (a < b);
@@ -167,9 +172,10 @@ static int orc_cmp_double(const void* x, const void* y) {
 double orc_threshold(int64_t n, double* T, double frac) {
     int64_t ld = 3 * n, K = 0;
     double* v = (double*)malloc(sizeof(double) * (size_t)(ld * ld));
+    const double floor32 = (double)(float)ORC_ZERO_FLOOR;
     for (int64_t i = 0; i < ld * ld; ++i) {
         double mag = fabs((double)(float)T[i]);
-        if (mag > 0.0) v[K++] = mag;
+        if (mag > floor32) v[K++] = mag;
     }
     int64_t r = (int64_t)ceil(frac * (double)K);
     if (r > K) r = K;

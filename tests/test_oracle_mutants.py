@@ -28,6 +28,7 @@ MUTANTS = {
     "threshold_rank_floor": ("int64_t r = (int64_t)ceil(frac * (double)K);",
                              "int64_t r = (int64_t)floor(frac * (double)K);"),
     "threshold_self_blocks": ("if (row / 3 == col / 3) continue;", "if (row < 0) continue;"),
+    "threshold_no_zero_floor": ("if (mag > floor32) v[K++] = mag;", "if (mag > 0.0) v[K++] = mag;"),
 }
 
 PIN_FILES = ["tests/test_oracle_tensor.py", "tests/test_oracle_fields.py",

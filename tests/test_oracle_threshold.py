@@ -3,9 +3,10 @@ fraction of the nonzero tensor entries is truncated and the rest kept as a
 sparse matrix).
 
 Readings pinned here: magnitudes are ranked as float32 values, all 9 entries
-of every block count, the cut is the ceil(frac K)-th smallest of the K
-nonzero magnitudes, entries at or below the cut go (ties included), and self
-blocks are never truncated."""
+of every block count, an entry is nonzero when its magnitude exceeds the
+assembly's absolute accuracy (1e-14), the cut is the ceil(frac K)-th smallest
+of the K nonzero magnitudes, entries at or below the cut go (ties included),
+and self blocks are never truncated."""
 import math
 
 import numpy as np
@@ -28,12 +29,15 @@ def _mesh_mixed():
     return c, s
 
 
+FLOOR = float(np.float32(1e-14))
+
+
 def _brute(T, frac):
     """Reference by counting, no sorting: the cut is the smallest magnitude x
     among the nonzero entries with #{|v| <= x} >= ceil(frac K)."""
     n = T.shape[0] // 3
     mags = [abs(float(np.float32(v))) for v in T.ravel()]
-    nz = [v for v in mags if v > 0.0]
+    nz = [v for v in mags if v > FLOOR]
     K = len(nz)
     r = math.ceil(frac * K)
     if r == 0:
@@ -97,7 +101,7 @@ def test_ties_at_the_cut_are_removed(orc):
     c, s = W.grid(4, 4, 1, 5e-9, 5e-9, 5e-9)
     T = orc.assemble(c, s)
     mags = np.abs(T.astype(np.float32)).astype(np.float64)
-    K = int((mags > 0).sum())
+    K = int((mags > FLOOR).sum())
     self_blk = np.kron(np.eye(c.shape[0], dtype=bool), np.ones((3, 3), bool))
     hit_tie = False
     for frac in np.linspace(0.05, 0.95, 19):
@@ -106,10 +110,26 @@ def test_ties_at_the_cut_are_removed(orc):
         assert not removed[self_blk].any()
         at_cut = (mags == cut) & ~self_blk
         assert removed[at_cut].all()
-        lo = (mags <= cut) & (mags > 0)
+        lo = (mags <= cut) & (mags > FLOOR)
         assert lo.sum() >= math.ceil(frac * K)
         hit_tie |= at_cut.sum() > 1
     assert hit_tie
+
+
+def test_rounding_noise_is_not_ranked(orc):
+    """On the cube grid thousands of entries that vanish by symmetry come out
+    of the float64 assembly as ~1e-17 noise: they count as zero, so K (and
+    with it the cut) equals the count over magnitudes above 1e-14."""
+    wl = W.cube_grid()
+    T = orc.assemble(wl.centers, wl.sizes)
+    mags = np.abs(T.astype(np.float32)).astype(np.float64)
+    noise = (mags > 0) & (mags <= FLOOR)
+    assert noise.sum() > 1000
+    K = int((mags > FLOOR).sum())
+    t, cut = orc.threshold(T, 0.3)
+    srt = np.sort(mags[mags > FLOOR])
+    assert cut == srt[math.ceil(0.3 * K) - 1]
+    assert not (t[noise & (np.kron(np.eye(wl.n, dtype=bool), np.ones((3, 3), bool)) == 0)] != 0).any()
 
 
 def test_monotone_in_fraction(orc):
