@@ -41,36 +41,48 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-cube", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-threshold", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="counter runs: one 1 GiB device copy (calibration) and the stage kernel "
                          "of the film workload only")
     ap.add_argument("--serving-count", type=int, default=24)
+    ap.add_argument("--layout", choices=["psym6", "sym6"], default="sym6",
+                    help="operator layout of the headline run: pair-symmetric (the film's tiles "
+                         "are identical) or six planes")
     return ap.parse_args()
 
 
-KERNEL_SOURCES = ["paper_2107_05364_amd/csrc/fieldstep.hip", "paper_2107_05364_amd/csrc/epilogue.h",
-                  "paper_2107_05364_amd/csrc/common.h"]
-COUNTERS = os.path.join(ROOT, "profiles", "k_field_stage_film_N2500_counters.md")
+# dominant kernel of each headline layout: its sources and committed counter summary
+KERNELS = {
+    "sym6": (["paper_2107_05364_amd/csrc/fieldstep.hip", "paper_2107_05364_amd/csrc/epilogue.h",
+              "paper_2107_05364_amd/csrc/common.h"],
+             os.path.join(ROOT, "profiles", "k_field_stage_film_N2500_counters.md")),
+    "psym6": (["paper_2107_05364_amd/csrc/psym.hip", "paper_2107_05364_amd/csrc/common.h"],
+              os.path.join(ROOT, "profiles", "k_psym_tiles_film_N2500_counters.md")),
+}
 
 
-def kernel_source_hash():
+def kernel_source_hash(layout):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNELS[layout][0]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kname):
-    """HBM bytes per launch of the stage kernel from the committed counter
+def counter_traffic(layout, kname):
+    """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE runs, calibrated against a 1 GiB copy),
     or None when the kernel sources or the kernel instance changed since."""
     try:
-        text = open(COUNTERS).read()
+        text = open(KERNELS[layout][1]).read()
     except OSError:
         return None
     vals = dict(ln.split(":", 1) for ln in text.splitlines() if ln.startswith(("source_hash:", "kernel:", "traffic_bytes_per_launch:")))
-    if vals.get("source_hash", "").strip() != kernel_source_hash() or vals.get("kernel", "").strip() != kname:
+    if vals.get("source_hash", "").strip() != kernel_source_hash(layout) or vals.get("kernel", "").strip() != kname:
         return None
     return int(vals["traffic_bytes_per_launch"].strip())
 
@@ -201,6 +213,168 @@ def large_section(tmg, W, torch, attempts=20, profile_iters=10):
     return out
 
 
+def cube_section(tmg, W, torch, reps=5):
+    """The 8 x 8 x 8 grid of 5 nm cubes (N = 512), RK4 at dt = 1e-13 s for
+    200 steps with the float32 SYM6 operator (3 MB, cache-resident): a
+    launch- and latency-bound case."""
+    wl = W.cube_grid()
+    nsteps = wl.extra["steps"]
+    ctx = tmg.Context(0)
+    geom = tmg.Geometry(ctx, wl.centers, wl.sizes)
+    T = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_SYM6)
+    p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+    m = torch.as_tensor(wl.m0.astype(np.float32), device="cuda")
+    p.run(m.clone(), None, tmg.TM_RK4, dt=wl.extra["dt"], max_steps=nsteps)
+    torch.cuda.synchronize()
+    best = 1e30
+    for _ in range(reps):
+        mm = m.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.run(mm, None, tmg.TM_RK4, dt=wl.extra["dt"], max_steps=nsteps)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    ms, nb = tmg.tm_profile_field(p.handle, 1, 50)
+    p.close()
+    T.close()
+    geom.close()
+    ctx.close()
+    return {"workload": "8x8x8 cubes of 5 nm (N=512), alpha=0.5, RK4 dt=1e-13 s x %d steps, fp32 SYM6" % nsteps,
+            "steps_per_s": round(nsteps / best, 1), "us_per_step": round(best / nsteps * 1e6, 2),
+            "stage_kernel_us": round(ms * 1e3, 2)}
+
+
+def sp4_sweep_section(tmg, W, torch, attempts=300):
+    """The standard-problem-4 film at [20n, 5n, 1] tiles (edges 25/n x 25/n x
+    3 nm), n = 1..9 (N = 100 n^2): per-size stage-kernel time and bandwidth
+    (fp32 SYM6, tuned launch shape) and single-state DP45 steps per second."""
+    rows = []
+    for nn in range(1, 10):
+        wl = W.thin_film(nx=20 * nn, ny=5 * nn)
+        ctx = tmg.Context(0)
+        geom = tmg.Geometry(ctx, wl.centers, wl.sizes)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_SYM6)
+        torch.cuda.synchronize()
+        asm = time.perf_counter() - t0
+        p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+        shape, _ = tmg.tm_problem_tune(p.handle, 1, 10)
+        ms, nb = tmg.tm_profile_field(p.handle, 1, 50)
+        m = torch.as_tensor(wl.m0.astype(np.float32), device="cuda")
+        Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
+        dt = torch.full((1,), 1e-14, dtype=torch.float64, device="cuda")
+        p.run(m, Ha, tmg.TM_DP45, dt=dt, max_steps=1 << 40, max_attempts=20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.run(m, Ha, tmg.TM_DP45, dt=dt, max_steps=1 << 40, max_attempts=attempts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rows.append({"n": nn, "tiles": wl.n, "assembly_ms": round(asm * 1e3, 2), "shape": shape,
+                     "stage_kernel_us": round(ms * 1e3, 2),
+                     "stage_kernel_gbs": round(nb / (ms * 1e-3) / 1e9, 1),
+                     "steps_per_s": round(attempts / el, 1)})
+        p.close()
+        T.close()
+        geom.close()
+        ctx.close()
+    return {"workload": "SP4 film [20n,5n,1] tiles, n=1..9, one state, DP45, fp32 SYM6", "sizes": rows}
+
+
+def threshold_section(tmg, W, torch, attempts=300, fracs=(0.2, 0.4, 0.7)):
+    """Thresholded operator on the SP4 film at [160, 40, 1] tiles (N = 6400),
+    the paper's threshold study: for each removed fraction, the block-sparse
+    operator's size, the sparse stage kernel's time and bandwidth (bytes as
+    stored), the H_d error against the unthresholded float32 operator (random
+    m), and single-state DP45 steps per second, beside the dense SYM6 path."""
+    wl = W.thin_film(nx=160, ny=40)
+    n = wl.n
+    ctx = tmg.Context(0)
+    geom = tmg.Geometry(ctx, wl.centers, wl.sizes)
+    T = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_SYM6)
+    mr = torch.as_tensor(W.random_unit_vectors(9, n)[None].astype(np.float32), device="cuda")
+    Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
+
+    def measure(tensor, tune):
+        p = tmg.Problem(ctx, geom, tensor, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+        if tune:
+            tmg.tm_problem_tune(p.handle, 1, 10)
+        ms, nb = tmg.tm_profile_field(p.handle, 1, 50)
+        hd = p.demag(mr).cpu().numpy().astype(np.float64)
+        m = torch.as_tensor(wl.m0.astype(np.float32), device="cuda")
+        dt = torch.full((1,), 1e-14, dtype=torch.float64, device="cuda")
+        p.run(m, Ha, tmg.TM_DP45, dt=dt, max_steps=1 << 40, max_attempts=20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.run(m, Ha, tmg.TM_DP45, dt=dt, max_steps=1 << 40, max_attempts=attempts)
+        torch.cuda.synchronize()
+        sps = attempts / (time.perf_counter() - t0)
+        p.close()
+        return {"stage_kernel_us": round(ms * 1e3, 2), "bytes_per_launch": nb,
+                "stage_kernel_gbs": round(nb / (ms * 1e-3) / 1e9, 1),
+                "hbm_frac": round(nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "steps_per_s": round(sps, 1)}, hd
+
+    dense, hd_ref = measure(T, True)
+    out = {"workload": "SP4 film [160,40,1] tiles of 3.125x3.125x3 nm (N=%d), one state, DP45" % n,
+           "dense_sym6": dense, "thresholded": []}
+    for f in fracs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Tt = T.threshold(f)
+        torch.cuda.synchronize()
+        build_ms = (time.perf_counter() - t0) * 1e3
+        row, hd = measure(Tt, False)
+        row.update({"frac": f, "threshold_ms": round(build_ms, 1), "blocks": Tt.nnzb,
+                    "blocks_kept": round(Tt.nnzb / float(n * n), 4), "cut": Tt.cut,
+                    "operator_bytes_vs_dense": round(Tt.nbytes / (24.0 * n * n), 4),
+                    "hd_rel_err_vs_dense": float(np.linalg.norm(hd - hd_ref) / np.linalg.norm(hd_ref)),
+                    "speedup_vs_dense": round(row["steps_per_s"] / dense["steps_per_s"], 3)})
+        out["thresholded"].append(row)
+        Tt.close()
+    T.close()
+    geom.close()
+    ctx.close()
+    return out
+
+
+def peaks_section(torch):
+    """Achievable rates on this device for context: a 4 GiB device copy
+    (read + write bytes) and library GEMMs (torch.mm) in bf16 and fp32."""
+    out = {}
+    src = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = 1e30
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    out["copy_gbs"] = round(2 * src.numel() * 4 / best / 1e9, 1)
+    del src, dst
+    for dt, name in ((torch.bfloat16, "bf16"), (torch.float32, "fp32")):
+        a = torch.randn(8192, 8192, device="cuda").to(dt)
+        b = torch.randn(8192, 8192, device="cuda").to(dt)
+        c = torch.mm(a, b)
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            torch.mm(a, b, out=c)
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e-3)
+        out["library_gemm_%s_tflops" % name] = round(2 * 8192 ** 3 / best / 1e12, 1)
+        del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving_section(tmg, W, torch, count=24, n_max=4000, max_steps=3000, slots=8):
     """Poisson stream of relaxation requests (bounded sample of the serving
     workload: `count` requests, tile counts log-uniform in [500, n_max]):
@@ -293,15 +467,20 @@ def main():
     geom = tmg.Geometry(ctx, wl.centers, wl.sizes)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    T = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_SYM6)
+    psym = args.layout == "psym6"
+    T = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM6 if psym else tmg.TM_LAYOUT_SYM6)
     torch.cuda.synchronize()
     asm_ms = (time.perf_counter() - t0) * 1e3
     p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
     # project autotuner: fastest launch shape of the fused stage kernel for this N
+    # (the pair-symmetric layout has one kernel shape)
     shape, _ = tmg.tm_problem_tune(p.handle, 1, 50)
+    # dominant kernel: the operator pass (mode 3: the tile pass of the
+    # pair-symmetric layout; the fused stage kernel of the six-plane layout)
+    prof_mode = 3 if psym else 0
 
     if args.profile_only:
-        ms, nb = tmg.tm_profile_field(p.handle, 1, args.profile_iters)
+        ms, nb = tmg.tm_profile_field_mode(p.handle, 1, prof_mode, args.profile_iters)
         print(json.dumps({"profile_only": True, "stage_kernel_us": round(ms * 1e3, 3),
                           "bytes_per_launch": nb, "launches": args.profile_iters + 1}), flush=True)
         p.close()
@@ -325,12 +504,17 @@ def main():
     assert torch.isfinite(m).all().item(), "non-finite state after the timed run"
     accepted = int(steps.cpu()[0])
 
-    # dominant kernel: the fused field/stage kernel, timed with HIP events on
-    # the stream it runs on
-    avg_ms, bytes_per = tmg.tm_profile_field(p.handle, 1, args.profile_iters)
+    # dominant kernel, timed with HIP events on the stream it runs on
+    avg_ms, bytes_per = tmg.tm_profile_field_mode(p.handle, 1, prof_mode, args.profile_iters)
+    eval_ms, _ = tmg.tm_profile_field(p.handle, 1, args.profile_iters)
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9
-    kname = "k_field<%d,%d,%d,%d,STAGE>" % tmg.tm_shape_info(shape)
-    traffic = counter_traffic(kname)
+    if psym:
+        kname = "k_psym_tiles<true>"
+        kdesc = " (pair-symmetric tile pass of the demag product; + reduction/epilogue launch)"
+    else:
+        kname = "k_field<%d,%d,%d,%d,STAGE>" % tmg.tm_shape_info(shape)
+        kdesc = " (fused demag matvec + H_eff + LL + stage update)"
+    traffic = counter_traffic(args.layout, kname)
 
     rec = {
         "metric": "LLG steps/s",
@@ -346,16 +530,17 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "SP4 thin film 100x25x1 tiles of 5x5x3 nm (N=2500), one state, "
-                               "adaptive DP45, fp32 SYM6 operator",
-                   "n_tiles": n, "batch": 1, "integrator": "DP45", "operator": "fp32 sym6",
+                               "adaptive DP45, fp32 %s operator" % args.layout.upper(),
+                   "n_tiles": n, "batch": 1, "integrator": "DP45", "operator": "fp32 " + args.layout,
                    "accepted_steps": accepted, "rejected_steps": int(st.rejected),
                    "stage_kernel_shape": shape,
                    "simulated_ns": round(float(tt.cpu()[0]) * 1e9, 4),
                    "assembly_ms": round(asm_ms, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": kname + " (fused demag matvec + H_eff + LL + stage update)",
-                     "avg_launch_us": round(avg_ms * 1e3, 3), "bytes_per_launch": bytes_per},
+                     "kernel": kname + kdesc,
+                     "avg_launch_us": round(avg_ms * 1e3, 3), "bytes_per_launch": bytes_per,
+                     "field_evaluation_us": round(eval_ms * 1e3, 3)},
     }
     p.close()
     T.close()
@@ -368,8 +553,16 @@ def main():
         rec["batched"] = bat
     if not args.no_large:
         rec["large"] = large_section(tmg, W, torch)
+    if not args.no_cube:
+        rec["cube"] = cube_section(tmg, W, torch)
+    if not args.no_sweep:
+        rec["sp4_sweep"] = sp4_sweep_section(tmg, W, torch)
+    if not args.no_threshold:
+        rec["threshold"] = threshold_section(tmg, W, torch)
     if not args.no_serving:
         rec["serving"] = serving_section(tmg, W, torch, count=args.serving_count)
+    if not args.no_peaks:
+        rec["achievable_peaks"] = peaks_section(torch)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(rec), flush=True)

@@ -61,7 +61,12 @@ typedef enum {
 /* Layout of the stored operator. */
 typedef enum {
     TM_LAYOUT_SYM6 = 0,   /* 6 planes [6][N][ldN] of (xx,xy,xz,yy,yz,zz), each 3x3 block symmetric */
-    TM_LAYOUT_DENSE9 = 1  /* row-major [3N][ld3N] dense operator (MFMA GEMM operand) */
+    TM_LAYOUT_DENSE9 = 1, /* row-major [3N][ld3N] dense operator (MFMA GEMM operand) */
+    TM_LAYOUT_BSR6 = 2,   /* thresholded operator: block-sparse rows of 6-component blocks
+                             (made by tm_tensor_threshold only) */
+    TM_LAYOUT_PSYM6 = 3   /* pair-symmetric operator of a mesh of identical tiles: only the
+                             upper triangle of 64x64-block tiles, [pairs][6][64][64], since
+                             N^{ab} = N^{ba} there (about half the SYM6 bytes) */
 } tm_layout;
 
 typedef enum { TM_RK4 = 0, TM_DP45 = 1 } tm_integrator;
@@ -115,22 +120,54 @@ tm_status tm_geometry_destroy(tm_geom* g);
 /* Assembles (or finds in the context's cache) the dense demag operator of g:
  * block (a, b) is the analytical tensor of tile b at the centre of tile a
  * (paper Sec. 3), evaluated in float64 on the device and stored in
- * `store` precision and `layout`.  FP32 and FP64 support both layouts;
- * BF16X3 and FP16X3 require DENSE9.  The returned handle holds a reference;
+ * `store` precision and `layout`.  FP32 and FP64 support SYM6 and DENSE9;
+ * BF16X3 and FP16X3 require DENSE9.  PSYM6 (FP32 only) stores each
+ * symmetric pair of blocks once, which the paper's symmetry remark
+ * (Sec. 3.2) allows when all tiles are identical: it requires every tile to
+ * have the same edges (TM_EINVAL otherwise).  The returned handle holds a reference;
  * release it with tm_tensor_release.  The call blocks until the operator is
  * ready.  TM_ENOMEM if it does not fit the admission budget after evicting
  * unreferenced cached tensors. */
 tm_status tm_tensor_assemble(tm_ctx* ctx, const tm_geom* g, tm_prec store, tm_layout layout,
                              hipStream_t stream, tm_tensor** out);
 
+/* Thresholded operator (paper Sec. 4.3.1: the smallest fraction of the
+ * nonzero tensor entries is set to zero and the rest is kept as a sparse
+ * matrix).  `src` must be an FP32 SYM6 operator; `frac` in [0, 1].
+ * Ranking: the float32 magnitudes of all 9 entries of every 3x3 block (self
+ * blocks included) that are nonzero -- above 1e-14, the float64 assembly's
+ * absolute rounding level -- K of them; the cut is the
+ * ceil(frac K)-th smallest; every entry whose magnitude is at most the cut is
+ * set to zero (ties at the cut included), except in self blocks (a == b),
+ * which are kept whole.  frac = 0 removes nothing.
+ * The result is a new operator of layout TM_LAYOUT_BSR6, precision FP32: for
+ * each target tile, in ascending source order, the source tiles whose block
+ * keeps at least one entry, with its 6 components (removed ones are 0).  It
+ * is usable wherever an FP32 SYM6 operator is (tm_problem_create, one state
+ * or many; not the DENSE9 batched product), is cached under (geometry, frac)
+ * and is released with tm_tensor_release.  Blocking.
+ * Errors: TM_EINVAL (src not FP32 SYM6, frac outside [0, 1]), TM_ENOMEM. */
+tm_status tm_tensor_threshold(tm_ctx* ctx, const tm_tensor* src, double frac, hipStream_t stream,
+                              tm_tensor** out);
+
+/* Size of a BSR6 operator: stored blocks and the cut (the float32 magnitude
+ * at or below which entries were removed; -1 when none was). */
+tm_status tm_tensor_sparse_info(const tm_tensor* t, int64_t* nnzb, double* cut);
+
+/* Copies a BSR6 operator to host memory: row_ptr [n+1] (int64), col [nnzb]
+ * source tiles (int32), vals [6][nnzb] components (xx,xy,xz,yy,yz,zz), each
+ * caller-allocated.  Blocking.  TM_EINVAL for other layouts. */
+tm_status tm_tensor_sparse_get(const tm_tensor* t, int64_t* row_ptr, int32_t* col, float* vals);
+
 /* Reads back block (a, b) as stored (converted to double), row-major 3x3.
- * Blocking.  For split precisions returns (hi + lo) / scale. */
+ * Blocking.  For split precisions returns (hi + lo) / scale; for BSR6 the
+ * block if stored, else zeros. */
 tm_status tm_tensor_get(const tm_tensor* t, int64_t a, int64_t b, double out9[9]);
 
 /* Reads back the blocks of target tiles [a0, a0 + count) against every
  * source tile, as stored (converted to double; split precisions as
- * (hi + lo) / scale), into host out[count][n][9] (row-major 3x3 blocks).
- * Blocking. */
+ * (hi + lo) / scale; BSR6 blocks not stored as zeros), into host
+ * out[count][n][9] (row-major 3x3 blocks).  Blocking. */
 tm_status tm_tensor_rows(const tm_tensor* t, int64_t a0, int64_t count, double* out);
 
 /* Device bytes held by the stored operator. */
@@ -236,7 +273,8 @@ tm_status tm_profile_field(tm_problem* p, int64_t B, int32_t iters, hipStream_t 
 
 /* Same timing for one epilogue variant: mode 0 the stage update (as
  * tm_profile_field), 1 the demag field only, 2 the last Dormand-Prince stage
- * with its float64 error estimate. */
+ * with its float64 error estimate, 3 the operator pass alone (for PSYM6 the
+ * tile kernel without the reduction + epilogue launch; otherwise as 0). */
 tm_status tm_profile_field_mode(tm_problem* p, int64_t B, int32_t mode, int32_t iters,
                                 hipStream_t stream, double* avg_ms, int64_t* bytes_out);
 
@@ -260,7 +298,9 @@ tm_status tm_problem_shape(const tm_problem* p, int32_t* shape);
 tm_status tm_problem_set_shape(tm_problem* p, int32_t shape);
 
 /* Autotuner: times every shape (iters launches each, B states) and keeps the
- * fastest for p.  Blocking.  chosen / best_ms may be NULL. */
+ * fastest for p.  Blocking.  chosen / best_ms may be NULL.  For operators
+ * other than SYM6 (one kernel shape each) it only times that kernel and
+ * reports chosen = -1. */
 tm_status tm_problem_tune(tm_problem* p, int64_t B, int32_t iters, hipStream_t stream,
                           int32_t* chosen, double* best_ms);
 

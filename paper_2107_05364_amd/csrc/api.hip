@@ -40,10 +40,7 @@ tm_status admit_bytes(Ctx* c, int64_t bytes) {
         Tensor* T = *it;
         if (T->refs > 0) continue;
         c->used -= T->bytes;
-        (void)hipFree(T->data);
-        if (T->lo) (void)hipFree(T->lo);
-        if (T->rscale) (void)hipFree(T->rscale);
-        delete T;
+        free_tensor(T);
         it = c->cache.erase(it);
     }
     if (c->used + bytes <= c->budget) {
@@ -57,6 +54,16 @@ tm_status admit_bytes(Ctx* c, int64_t bytes) {
 }
 
 void release_bytes(Ctx* c, int64_t bytes) { c->used -= bytes; }
+
+void free_tensor(Tensor* T) {
+    if (T->data) (void)hipFree(T->data);
+    if (T->lo) (void)hipFree(T->lo);
+    if (T->rscale) (void)hipFree(T->rscale);
+    if (T->row_ptr) (void)hipFree(T->row_ptr);
+    if (T->col) (void)hipFree(T->col);
+    if (T->pairs) (void)hipFree(T->pairs);
+    delete static_cast<tm_tensor*>(T);  // every tensor is created as a tm_tensor
+}
 
 Workspace::~Workspace() {
     float* fl[] = {y, ya, yb, y5, k[0], k[1], k[2], k[3], k[4], k[5], k[6], Ha, hd, part};
@@ -76,11 +83,6 @@ Workspace::~Workspace() {
 }  // namespace tmag
 
 using namespace tmag;
-
-struct tm_ctx : Ctx {};
-struct tm_geom : Geom {};
-struct tm_tensor : Tensor {};
-struct tm_problem : Problem {};
 
 extern "C" {
 
@@ -112,12 +114,7 @@ tm_status tm_finalize(tm_ctx* c) {
         TM_REQUIRE(c->live_problems == 0 && c->live_servers == 0, TM_EBUSY,
                    "tm_finalize: %d problems and %d servers still alive", c->live_problems,
                    c->live_servers);
-        for (Tensor* T : c->cache) {
-            (void)hipFree(T->data);
-            if (T->lo) (void)hipFree(T->lo);
-            if (T->rscale) (void)hipFree(T->rscale);
-            delete T;
-        }
+        for (Tensor* T : c->cache) free_tensor(T);
         c->cache.clear();
     }
     delete c;
@@ -178,10 +175,18 @@ tm_status tm_tensor_assemble(tm_ctx* c, const tm_geom* g, tm_prec store, tm_layo
     TM_REQUIRE(c && g && out, TM_EINVAL, "tm_tensor_assemble: null argument");
     TM_REQUIRE(store >= TM_PREC_FP32 && store <= TM_PREC_FP64, TM_EINVAL,
                "tm_tensor_assemble: unknown precision %d", static_cast<int>(store));
-    TM_REQUIRE(layout == TM_LAYOUT_SYM6 || layout == TM_LAYOUT_DENSE9, TM_EINVAL,
-               "tm_tensor_assemble: unknown layout %d", static_cast<int>(layout));
+    TM_REQUIRE(layout == TM_LAYOUT_SYM6 || layout == TM_LAYOUT_DENSE9 || layout == TM_LAYOUT_PSYM6,
+               TM_EINVAL, "tm_tensor_assemble: layout %d cannot be assembled", static_cast<int>(layout));
     TM_REQUIRE(layout == TM_LAYOUT_DENSE9 || store == TM_PREC_FP32 || store == TM_PREC_FP64,
                TM_EINVAL, "tm_tensor_assemble: split precisions need the DENSE9 layout");
+    if (layout == TM_LAYOUT_PSYM6) {
+        TM_REQUIRE(store == TM_PREC_FP32, TM_EINVAL, "tm_tensor_assemble: PSYM6 is stored in FP32");
+        for (int64_t a = 1; a < g->n; ++a)
+            TM_REQUIRE(g->sizes[3 * a] == g->sizes[0] && g->sizes[3 * a + 1] == g->sizes[1] &&
+                           g->sizes[3 * a + 2] == g->sizes[2],
+                       TM_EINVAL, "tm_tensor_assemble: PSYM6 needs identical tiles (tile %lld differs)",
+                       static_cast<long long>(a));
+    }
     TM_TRY_HIP(hipSetDevice(c->device));
     std::unique_lock<std::mutex> lk(c->mu);
     for (auto it = c->cache.begin(); it != c->cache.end(); ++it) {
@@ -207,7 +212,18 @@ tm_status tm_tensor_assemble(tm_ctx* c, const tm_geom* g, tm_prec store, tm_layo
     T->layout = layout;
     size_t esz = store == TM_PREC_FP64 ? 8 : (store == TM_PREC_FP32 ? 4 : 2);
     int64_t main_bytes = 0, lo_bytes = 0, sc_bytes = 0;
-    if (layout == TM_LAYOUT_SYM6) {
+    std::vector<int32_t> pairs;
+    if (layout == TM_LAYOUT_PSYM6) {
+        T->nt = (n + kPsTile - 1) / kPsTile;
+        for (int64_t I = 0; I < T->nt; ++I)
+            for (int64_t J = I; J < T->nt; ++J) {
+                pairs.push_back(static_cast<int32_t>(I));
+                pairs.push_back(static_cast<int32_t>(J));
+            }
+        T->npairs = T->nt * (T->nt + 1) / 2;
+        main_bytes = T->npairs * 6 * kPsTile * kPsTile * 4;
+        lo_bytes = 0;
+    } else if (layout == TM_LAYOUT_SYM6) {
         T->ld = round_up(n, 4);
         T->plane = n * T->ld;
         T->rows = n;
@@ -219,18 +235,16 @@ tm_status tm_tensor_assemble(tm_ctx* c, const tm_geom* g, tm_prec store, tm_layo
         if (store == TM_PREC_BF16X3 || store == TM_PREC_FP16X3) lo_bytes = main_bytes;
         if (store == TM_PREC_FP16X3) sc_bytes = T->rows * 4;
     }
-    T->bytes = main_bytes + lo_bytes + sc_bytes;
+    const int64_t pair_bytes = static_cast<int64_t>(pairs.size()) * 4;
+    T->bytes = main_bytes + lo_bytes + sc_bytes + pair_bytes;
     tm_status st = admit_bytes(c, T->bytes);
     if (st != TM_OK) {
         delete T;
         return st;
     }
     auto fail = [&](tm_status code) {
-        if (T->data) (void)hipFree(T->data);
-        if (T->lo) (void)hipFree(T->lo);
-        if (T->rscale) (void)hipFree(T->rscale);
         release_bytes(c, T->bytes);
-        delete T;
+        free_tensor(T);
         return code;
     };
     if (hipMalloc(&T->data, main_bytes) != hipSuccess) {
@@ -240,6 +254,11 @@ tm_status tm_tensor_assemble(tm_ctx* c, const tm_geom* g, tm_prec store, tm_layo
     if (lo_bytes && hipMalloc(&T->lo, lo_bytes) != hipSuccess) return fail(TM_ENOMEM);
     if (sc_bytes && hipMalloc(reinterpret_cast<void**>(&T->rscale), sc_bytes) != hipSuccess)
         return fail(TM_ENOMEM);
+    if (pair_bytes) {
+        if (hipMalloc(reinterpret_cast<void**>(&T->pairs), pair_bytes) != hipSuccess) return fail(TM_ENOMEM);
+        if (hipMemcpy(T->pairs, pairs.data(), pair_bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(TM_EDEVICE);
+    }
     double *dc = nullptr, *ds = nullptr;
     if (hipMalloc(&dc, 3 * n * sizeof(double)) != hipSuccess ||
         hipMalloc(&ds, 3 * n * sizeof(double)) != hipSuccess) {
@@ -270,6 +289,13 @@ tm_status tm_tensor_get(const tm_tensor* T, int64_t a, int64_t b, double out9[9]
     TM_REQUIRE(T && out9, TM_EINVAL, "tm_tensor_get: null argument");
     TM_REQUIRE(a >= 0 && a < T->n && b >= 0 && b < T->n, TM_EINVAL, "tm_tensor_get: index out of range");
     TM_TRY_HIP(hipSetDevice(T->ctx->device));
+    if (T->layout == TM_LAYOUT_BSR6 || T->layout == TM_LAYOUT_PSYM6) {
+        std::vector<double> row(T->n * 9);
+        tm_status st = T->layout == TM_LAYOUT_BSR6 ? bsr_rows(T, a, 1, row.data()) : psym_rows(T, a, 1, row.data());
+        if (st != TM_OK) return st;
+        std::memcpy(out9, row.data() + b * 9, 9 * sizeof(double));
+        return TM_OK;
+    }
     if (T->layout == TM_LAYOUT_SYM6) {
         double v6[6];
         for (int cc = 0; cc < 6; ++cc) {
@@ -344,6 +370,8 @@ tm_status tm_tensor_rows(const tm_tensor* T, int64_t a0, int64_t count, double* 
     if (count == 0) return TM_OK;
     TM_TRY_HIP(hipSetDevice(T->ctx->device));
     const int64_t n = T->n;
+    if (T->layout == TM_LAYOUT_BSR6) return bsr_rows(T, a0, count, out);
+    if (T->layout == TM_LAYOUT_PSYM6) return psym_rows(T, a0, count, out);
     if (T->layout == TM_LAYOUT_SYM6) {
         const size_t esz = T->prec == TM_PREC_FP64 ? 8 : 4;
         std::vector<unsigned char> buf(6 * count * T->ld * esz);
@@ -575,6 +603,8 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
         splits = gemm_splits(p);
         pbytes = splits * bcap * T->rows * 4;
     }
+    const bool psym = T->layout == TM_LAYOUT_PSYM6;
+    if (psym) pbytes = psym_partial_floats(T, bcap) * 4;
     int64_t bytes = 12 * sb + bcap * 12 + bcap * (8 * 7 + 8 * 2 + 4 * 2) + 16 * bcap * n + 64 +
                     RP_COUNT * 8 + nblk * bcap * 32 + xbytes + pbytes;
     {
@@ -625,7 +655,7 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
         e = alloc(&w->xh, half);
         if (e == hipSuccess && T->prec != TM_PREC_FP32) e = alloc(&w->xl, half);
     }
-    if (dense && e == hipSuccess) {
+    if ((dense || psym) && e == hipSuccess) {
         e = alloc(reinterpret_cast<void**>(&w->part), pbytes);
         w->part_splits = splits;
     }

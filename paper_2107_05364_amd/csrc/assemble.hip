@@ -187,12 +187,49 @@ __global__ __launch_bounds__(256) void k_split_fp16_rows(int64_t ld, const float
     }
 }
 
+// PSYM6: tile pair p = (I, J), I <= J, holds block (al, bl) = tensor of tile
+// 64 J + bl at the centre of tile 64 I + al as planes [6][64][64]; blocks that
+// involve a padding index (>= n) are zero.
+__global__ __launch_bounds__(256) void k_assemble_psym6(int32_t n, const int32_t* __restrict__ pairs,
+                                                        const double* __restrict__ centers,
+                                                        const double* __restrict__ sizes,
+                                                        float* __restrict__ out) {
+    constexpr int TB = kPsTile * kPsTile;
+    const int64_t p = blockIdx.x;
+    const int64_t I = pairs[2 * p], J = pairs[2 * p + 1];
+    float* tile = out + p * 6 * TB;
+    for (int e = threadIdx.x + 256 * blockIdx.y; e < TB; e += 256 * gridDim.y) {
+        const int64_t a = kPsTile * I + e / kPsTile, b = kPsTile * J + e % kPsTile;
+        double t6[6] = {0, 0, 0, 0, 0, 0};
+        if (a < n && b < n) {
+            const double dx = centers[3 * a + 0] - centers[3 * b + 0];
+            const double dy = centers[3 * a + 1] - centers[3 * b + 1];
+            const double dz = centers[3 * a + 2] - centers[3 * b + 2];
+            cuboid_tensor(dx, dy, dz, 0.5 * sizes[3 * b + 0], 0.5 * sizes[3 * b + 1],
+                          0.5 * sizes[3 * b + 2], t6);
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) tile[c * TB + e] = static_cast<float>(t6[c]);
+    }
+}
+
 }  // namespace
+
+tm_status assemble_psym(Tensor* T, const double* d_centers, const double* d_sizes, hipStream_t s) {
+    TM_REQUIRE(T->layout == TM_LAYOUT_PSYM6 && T->prec == TM_PREC_FP32 && T->pairs, TM_EINVAL,
+               "pair-symmetric assembly: bad tensor");
+    const dim3 grid(static_cast<unsigned>(T->npairs), 4);
+    k_assemble_psym6<<<grid, 256, 0, s>>>(static_cast<int32_t>(T->n), T->pairs, d_centers, d_sizes,
+                                          static_cast<float*>(T->data));
+    TM_TRY_HIP(hipGetLastError());
+    return TM_OK;
+}
 
 tm_status assemble_device(Tensor* T, const double* d_centers, const double* d_sizes,
                           hipStream_t s) {
     const int32_t n = static_cast<int32_t>(T->n);
     const dim3 block(256);
+    if (T->layout == TM_LAYOUT_PSYM6) return assemble_psym(T, d_centers, d_sizes, s);
     if (T->layout == TM_LAYOUT_SYM6) {
         const dim3 grid(static_cast<unsigned>((T->ld + 255) / 256), static_cast<unsigned>(n));
         if (T->prec == TM_PREC_FP32)

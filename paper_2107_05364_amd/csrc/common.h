@@ -90,9 +90,23 @@ struct Tensor {
     void* data = nullptr; // fp32 / fp64 entries, or the hi part
     void* lo = nullptr;   // lo part of split precisions
     float* rscale = nullptr; // FP16X3: per-row 1/scale (power of two)
+    // BSR6 (thresholded): data = float [6][nnzb] components, row_ptr [n+1],
+    // col [nnzb] source tiles in ascending order per row
+    int64_t* row_ptr = nullptr;
+    int32_t* col = nullptr;
+    int64_t nnzb = 0;
+    // PSYM6 (pair-symmetric): data = float [npairs][6][64][64] tiles of the
+    // upper triangle, pairs = int32 [npairs][2] (I, J), I <= J, nt tiles a side
+    int32_t* pairs = nullptr;
+    int64_t npairs = 0, nt = 0;
+    double frac = -1.0;      // BSR6: removed fraction requested
+    double cut = -1.0;       // BSR6: magnitude cut (-1: nothing removed)
     int64_t bytes = 0;
     int refs = 0;
 };
+
+// Frees a tensor's device memory and the tensor (the ledger is the caller's).
+void free_tensor(Tensor* T);
 
 // Device-side description of the pieces of a problem the kernels read.
 struct DevProblem {
@@ -212,6 +226,20 @@ int64_t gemm_splits(const Problem* p);
 tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const float* X,
                                const EpiArgs& e, hipStream_t s);
 constexpr int64_t kMaxGemmStates = 128;
+// Thresholded (BSR6) operators (threshold.hip): field kernel and host read-back.
+tm_status launch_field_bsr(const Problem* p, Epi mode, int64_t B, const float* X, const EpiArgs& e,
+                           hipStream_t s);
+tm_status bsr_rows(const Tensor* T, int64_t a0, int64_t count, double* out);
+// Pair-symmetric (PSYM6) operators (psym.hip): tiles of kPsTile x kPsTile
+// blocks; assembly, field kernels (tile pass + fixed-order reduction with the
+// epilogue), partial-buffer size and host read-back.
+constexpr int kPsTile = 64;
+tm_status assemble_psym(Tensor* T, const double* d_centers, const double* d_sizes, hipStream_t s);
+tm_status launch_field_psym(const Problem* p, Epi mode, int64_t B, const float* X, const EpiArgs& e,
+                            hipStream_t s);
+int64_t psym_partial_floats(const Tensor* T, int64_t B);
+tm_status launch_psym_tiles(const Problem* p, int64_t B, const float* X, const double* h, hipStream_t s);
+tm_status psym_rows(const Tensor* T, int64_t a0, int64_t count, double* out);
 
 // Launch shapes of the fused field kernel: (index, workgroup threads,
 // target tiles per workgroup, nontemporal operator loads, waves-per-SIMD cap).
@@ -262,3 +290,10 @@ enum RunParam { RP_ATOL = 0, RP_RTOL, RP_TEND, RP_DTMIN, RP_DMDT_STOP, RP_MAX_ST
 constexpr int32_t FLAG_DONE = 1, FLAG_NONFINITE = 2, FLAG_STEP = 4, FLAG_CAPPED = 8;
 
 }  // namespace tmag
+
+// The opaque handles of the C ABI are the library's own objects.
+struct tm_ctx : tmag::Ctx {};
+struct tm_geom : tmag::Geom {};
+struct tm_tensor : tmag::Tensor {};
+struct tm_problem : tmag::Problem {};
+

@@ -372,9 +372,15 @@ tm_status time_field(Problem* p, int64_t B, int mode, int32_t iters, hipStream_t
     hipEvent_t e0, e1;
     TM_TRY_HIP(hipEventCreate(&e0));
     TM_TRY_HIP(hipEventCreate(&e1));
-    tm_status st = launch_field(p, ep, B, X, e, s);  // untimed first launch
+    // mode 3: the operator pass alone where the evaluation has more than one
+    // launch (the pair-symmetric tile pass); otherwise the whole evaluation
+    const bool tiles_only = mode == 3 && p->T->layout == TM_LAYOUT_PSYM6;
+    auto one = [&]() {
+        return tiles_only ? launch_psym_tiles(p, B, X, w->h, s) : launch_field(p, ep, B, X, e, s);
+    };
+    tm_status st = one();  // untimed first launch
     if (st == TM_OK && hipEventRecord(e0, s) != hipSuccess) st = TM_EDEVICE;
-    for (int32_t i = 0; i < iters && st == TM_OK; ++i) st = launch_field(p, ep, B, X, e, s);
+    for (int32_t i = 0; i < iters && st == TM_OK; ++i) st = one();
     float ms = 0.0f;
     if (st == TM_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess)) {
@@ -393,14 +399,23 @@ tm_status time_field(Problem* p, int64_t B, int mode, int32_t iters, hipStream_t
 extern "C" tm_status tm_profile_field_mode(tm_problem* pp, int64_t B, int32_t mode, int32_t iters,
                                            hipStream_t s, double* avg_ms, int64_t* bytes_out) {
     Problem* p = reinterpret_cast<Problem*>(pp);
-    TM_REQUIRE(p && avg_ms && B >= 1 && iters >= 1 && mode >= 0 && mode <= 2, TM_EINVAL,
+    TM_REQUIRE(p && avg_ms && B >= 1 && iters >= 1 && mode >= 0 && mode <= 3, TM_EINVAL,
                "tm_profile_field: bad arguments");
     TM_TRY_HIP(hipSetDevice(p->ctx->device));
     tm_status st = ensure_workspace(p, B);
     if (st != TM_OK) return st;
     st = time_field(p, B, mode, iters, s, avg_ms);
     if (st != TM_OK) return st;
-    if (bytes_out) *bytes_out = 24 * p->n * p->n + 24 * p->n * B;
+    if (bytes_out) {
+        // operator bytes as stored (SYM6: 24 n^2; DENSE9: 36 n^2 algorithmic;
+        // BSR6: row pointers, columns and six planes; PSYM6: the stored tile
+        // pairs) + states in and out
+        const Tensor* T = p->T;
+        const int64_t op = (T->layout == TM_LAYOUT_BSR6 || T->layout == TM_LAYOUT_PSYM6) ? T->bytes - (T->pairs ? T->npairs * 8 : 0)
+                           : T->layout == TM_LAYOUT_DENSE9 ? 36 * p->n * p->n
+                                                           : 24 * p->n * p->n;
+        *bytes_out = op + 24 * p->n * B;
+    }
     return TM_OK;
 }
 
@@ -453,6 +468,15 @@ extern "C" tm_status tm_problem_tune(tm_problem* pp, int64_t B, int32_t iters, h
     TM_TRY_HIP(hipSetDevice(p->ctx->device));
     tm_status st = ensure_workspace(p, B);
     if (st != TM_OK) return st;
+    if (p->T->layout != TM_LAYOUT_SYM6) {
+        // launch shapes belong to the dense SYM6 kernel; other layouts have one
+        double ms = 0.0;
+        st = time_field(p, B, 0, iters, s, &ms);
+        if (st != TM_OK) return st;
+        if (chosen) *chosen = -1;
+        if (best_ms) *best_ms = ms;
+        return TM_OK;
+    }
     const int keep = p->shape;
     int best = -1;
     double best_t = 1e30;

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libtilemag.so")
 TM_OK, TM_EINVAL, TM_ENOMEM, TM_EDEVICE = 0, -1, -2, -3
 TM_ENONFINITE, TM_ESTEP, TM_EBUSY, TM_ENOTFOUND = -4, -5, -6, -7
 TM_PREC_FP32, TM_PREC_BF16X3, TM_PREC_FP16X3, TM_PREC_FP64 = 0, 1, 2, 3
-TM_LAYOUT_SYM6, TM_LAYOUT_DENSE9 = 0, 1
+TM_LAYOUT_SYM6, TM_LAYOUT_DENSE9, TM_LAYOUT_BSR6, TM_LAYOUT_PSYM6 = 0, 1, 2, 3
 TM_RK4, TM_DP45 = 0, 1
 
 _STATUS_NAMES = {0: "TM_OK", -1: "TM_EINVAL", -2: "TM_ENOMEM", -3: "TM_EDEVICE",
@@ -32,7 +32,8 @@ _STATUS_NAMES = {0: "TM_OK", -1: "TM_EINVAL", -2: "TM_ENOMEM", -3: "TM_EDEVICE",
 EXPORTS = [
     "tm_last_error", "tm_version", "tm_init", "tm_finalize", "tm_set_memory_budget",
     "tm_geometry_create", "tm_geometry_hash", "tm_geometry_info", "tm_geometry_destroy",
-    "tm_tensor_assemble", "tm_tensor_get", "tm_tensor_rows", "tm_tensor_bytes", "tm_tensor_release",
+    "tm_tensor_assemble", "tm_tensor_threshold", "tm_tensor_sparse_info", "tm_tensor_sparse_get",
+    "tm_tensor_get", "tm_tensor_rows", "tm_tensor_bytes", "tm_tensor_release",
     "tm_problem_create", "tm_problem_destroy", "tm_demag", "tm_heff", "tm_dmdt", "tm_energy",
     "tm_run", "tm_profile_field", "tm_profile_field_mode", "tm_num_shapes", "tm_shape_info",
     "tm_problem_shape", "tm_problem_set_shape",
@@ -116,6 +117,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "tm_geometry_info": (i32, [vp, P(i64), P(i64)]),
         "tm_geometry_destroy": (i32, [vp]),
         "tm_tensor_assemble": (i32, [vp, vp, i32, i32, vp, P(vp)]),
+        "tm_tensor_threshold": (i32, [vp, vp, d, vp, P(vp)]),
+        "tm_tensor_sparse_info": (i32, [vp, P(i64), P(d)]),
+        "tm_tensor_sparse_get": (i32, [vp, P(i64), P(i32), P(C.c_float)]),
         "tm_tensor_get": (i32, [vp, i64, i64, P(d)]),
         "tm_tensor_rows": (i32, [vp, i64, i64, P(d)]),
         "tm_tensor_bytes": (i32, [vp, P(i64)]),
@@ -246,6 +250,31 @@ def tm_tensor_assemble(ctx, g, store=TM_PREC_FP32, layout=TM_LAYOUT_SYM6) -> C.c
     out = C.c_void_p()
     _check(load().tm_tensor_assemble(ctx, g, int(store), int(layout), _stream(), C.byref(out)))
     return out
+
+
+def tm_tensor_threshold(ctx, T, frac: float) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(load().tm_tensor_threshold(ctx, T, C.c_double(float(frac)), _stream(), C.byref(out)))
+    return out
+
+
+def tm_tensor_sparse_info(T):
+    """(stored blocks, magnitude cut or -1)."""
+    nb, cut = C.c_int64(), C.c_double()
+    _check(load().tm_tensor_sparse_info(T, C.byref(nb), C.byref(cut)))
+    return nb.value, cut.value
+
+
+def tm_tensor_sparse_get(T, n: int):
+    """(row_ptr int64 [n+1], col int32 [nnzb], vals float32 [6, nnzb])."""
+    nnzb, _ = tm_tensor_sparse_info(T)
+    rp = np.zeros(n + 1, np.int64)
+    col = np.zeros(max(nnzb, 1), np.int32)
+    vals = np.zeros((6, max(nnzb, 1)), np.float32)
+    _check(load().tm_tensor_sparse_get(T, rp.ctypes.data_as(C.POINTER(C.c_int64)),
+                                       col.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       vals.ctypes.data_as(C.POINTER(C.c_float))))
+    return rp, col[:nnzb], vals[:, :nnzb]
 
 
 def tm_tensor_get(T, a: int, b: int) -> np.ndarray:
@@ -448,6 +477,26 @@ class Tensor:
     def __init__(self, ctx: Context, geom: Geometry, store=TM_PREC_FP32, layout=TM_LAYOUT_SYM6):
         self.handle = tm_tensor_assemble(ctx.handle, geom.handle, store, layout)
         self.store, self.layout, self.n = store, layout, geom.n
+        self.ctx = ctx
+
+    def threshold(self, frac: float) -> "Tensor":
+        """Thresholded copy (BSR6) of this FP32 SYM6 operator (paper Sec. 4.3.1)."""
+        t = Tensor.__new__(Tensor)
+        t.handle = tm_tensor_threshold(self.ctx.handle, self.handle, frac)
+        t.store, t.layout, t.n, t.ctx = TM_PREC_FP32, TM_LAYOUT_BSR6, self.n, self.ctx
+        return t
+
+    def sparse(self):
+        """(row_ptr, col, vals) of a BSR6 operator on the host."""
+        return tm_tensor_sparse_get(self.handle, self.n)
+
+    @property
+    def nnzb(self) -> int:
+        return tm_tensor_sparse_info(self.handle)[0]
+
+    @property
+    def cut(self) -> float:
+        return tm_tensor_sparse_info(self.handle)[1]
 
     def block(self, a: int, b: int) -> np.ndarray:
         return tm_tensor_get(self.handle, a, b)

@@ -1,0 +1,184 @@
+"""GPU parity of the pair-symmetric operator (PSYM6: meshes of identical
+tiles, where N^{ab} = N^{ba}, store each pair of blocks once) through the C
+ABI, against the FP64 oracle's dense operator.
+
+Tolerances (as for the float32 SYM6 path):
+  stored blocks       |dN| <= 2^-24 |N| + 1e-14 against the oracle's N^{ab}
+  H_d / H_eff         relative 2-norm and max-norm error <= 1e-5
+  RK4, 200 steps      max |dm| <= 1e-4
+The summation order of the product depends only on the tile count, so a
+state's result is bitwise the same alone and in a batch.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_helpers import build, close, device_state, rel_errors, tilemag
+from paper_2107_05364_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tmg():
+    return tilemag()
+
+
+@pytest.fixture(scope="module")
+def ctx(tmg):
+    c = tmg.Context(0)
+    yield c
+    try:
+        c.close()
+    except tmg.TilemagError:
+        pass
+
+
+def _meshes():
+    cube = W.cube_grid()
+    return {
+        "cube8": (cube.centers, cube.sizes),
+        "grid13x5": W.grid(13, 5, 1, 5e-9, 4e-9, 3e-9),
+        "grid7x5x3": W.grid(7, 5, 3, 4e-9, 4e-9, 6e-9),
+        "single": (np.zeros((1, 3)), np.array([[5e-9, 4e-9, 3e-9]])),
+    }
+
+
+def _psym(tmg, ctx, c, s, alpha=0.5):
+    return build(tmg, ctx, c, s, alpha=alpha, layout=tmg.TM_LAYOUT_PSYM6)
+
+
+@pytest.mark.parametrize("name", ["cube8", "grid13x5", "grid7x5x3", "single"])
+def test_psym_blocks_match_oracle(tmg, ctx, orc, name):
+    c, s = _meshes()[name]
+    _say("psym blocks %s n=%d" % (name, c.shape[0]))
+    g = tmg.Geometry(ctx, c, s)
+    T = tmg.Tensor(ctx, g, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM6)
+    got = T.dense()
+    want = orc.assemble(c, s)
+    assert np.all(np.abs(got - want) <= 2.0**-24 * np.abs(want) + 1e-14)
+    # single blocks read back through the other entry point
+    n = c.shape[0]
+    for a, b in ((0, n - 1), (n - 1, 0), (n // 2, n // 3)):
+        assert np.array_equal(T.block(a, b), got[3 * a:3 * a + 3, 3 * b:3 * b + 3])
+    close(g, T)
+
+
+@pytest.mark.parametrize("name,B", [("cube8", 1), ("grid13x5", 3), ("grid7x5x3", 2), ("single", 1)])
+def test_psym_demag_and_heff(tmg, ctx, orc, name, B):
+    c, s = _meshes()[name]
+    n = c.shape[0]
+    _say("psym demag %s n=%d B=%d" % (name, n, B))
+    g, T, p = _psym(tmg, ctx, c, s)
+    m = np.stack([W.random_unit_vectors(60 + k, n) for k in range(B)])
+    md = device_state(m)
+    Hd = p.demag(md).cpu().numpy()
+    He = p.heff(md).cpu().numpy()
+    P = orc.Problem(c, s, 8.0e5, 1.3e-11, 0.5)
+    for k in range(B):
+        mk = m[k].astype(np.float32).astype(np.float64)
+        e2, emax = rel_errors(Hd[k], P.demag(mk))
+        assert e2 <= 1e-5 and emax <= 1e-5, ("demag", k, e2, emax)
+        e2, emax = rel_errors(He[k], P.heff(mk))
+        assert e2 <= 1e-5 and emax <= 1e-5, ("heff", k, e2, emax)
+    close(g, T, p)
+
+
+def test_psym_film_full(tmg, ctx, orc):
+    wl = W.thin_film()
+    g, T, p = _psym(tmg, ctx, wl.centers, wl.sizes)
+    m = wl.m0.astype(np.float32)
+    Hd = p.demag(device_state(m)).cpu().numpy()[0]
+    want = orc.demag(orc.assemble(wl.centers, wl.sizes), 8.0e5, m[0].astype(np.float64))
+    e2, emax = rel_errors(Hd, want)
+    assert e2 <= 1e-5 and emax <= 1e-5, (e2, emax)
+    # about half the bytes of the six-plane layout
+    assert T.nbytes < 0.56 * 24 * wl.n * wl.n
+    close(g, T, p)
+
+
+def test_psym_batch_invariance(tmg, ctx):
+    c, s = _meshes()["grid7x5x3"]
+    n = c.shape[0]
+    g, T, p = _psym(tmg, ctx, c, s)
+    m = np.stack([W.random_unit_vectors(80 + k, n) for k in range(4)])
+    H4 = p.demag(device_state(m)).cpu().numpy()
+    H1 = p.demag(device_state(m[2:3])).cpu().numpy()
+    assert np.array_equal(H4[2], H1[0])
+    close(g, T, p)
+
+
+def test_psym_rk4_cube_grid(tmg, ctx, orc):
+    wl = W.cube_grid()
+    _say("psym rk4 cube grid 200 steps")
+    g, T, p = _psym(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha)
+    m0 = wl.m0.astype(np.float32)
+    md = device_state(m0)
+    t, dt, steps, st = p.run(md, None, tmg.TM_RK4, dt=1e-13, max_steps=200)
+    got = md.cpu().numpy()[0]
+    P = orc.Problem(wl.centers, wl.sizes, wl.Ms, wl.A, wl.alpha)
+    want = P.rk4(m0[0].astype(np.float64), [0, 0, 0], 1e-13, 200)
+    assert int(steps.cpu()[0]) == 200
+    assert np.abs(got - want).max() <= 1e-4
+    assert np.abs(np.linalg.norm(got, axis=1) - 1).max() < 1e-6
+    close(g, T, p)
+
+
+def test_psym_dp45_one_step_film(tmg, ctx, orc):
+    import torch
+
+    wl = W.thin_film()
+    g, T, p = _psym(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha)
+    m0 = wl.m0.astype(np.float32)
+    Ha = wl.Ha.astype(np.float32)
+    md = device_state(m0)
+    t, dt, steps, st = p.run(md, torch.as_tensor(Ha, device="cuda"), tmg.TM_DP45, dt=2e-14,
+                             max_steps=1, max_attempts=1)
+    P = orc.Problem(wl.centers, wl.sizes, wl.Ms, wl.A, wl.alpha)
+    y = m0[0].astype(np.float64).copy()
+    k1 = P.rhs(y, Ha[0].astype(np.float64))
+    ok, dtn, tn, err, _ = P.dp45_attempt(y, k1, Ha[0].astype(np.float64), 2e-14, 0.0)
+    assert ok and int(steps.cpu()[0]) == 1
+    assert float(t.cpu()[0]) == tn
+    assert np.abs(md.cpu().numpy()[0] - y).max() <= 1e-5
+    assert abs(float(dt.cpu()[0]) / dtn - 1) < 1e-3
+    close(g, T, p)
+
+
+def test_psym_dp45_film_matches_six_plane_path(tmg, ctx):
+    """200 adaptive attempts on the film with PSYM6 and with SYM6: the two
+    operators hold the same float32 values, so the trajectories agree to the
+    float32 product's rounding (summation orders differ)."""
+    import torch
+
+    wl = W.thin_film()
+    Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
+    out = []
+    for layout in (tmg.TM_LAYOUT_PSYM6, tmg.TM_LAYOUT_SYM6):
+        g, T, p = build(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha, layout=layout)
+        md = device_state(wl.m0)
+        t, dt, steps, st = p.run(md, Ha, tmg.TM_DP45, dt=1e-14, max_steps=1 << 40, max_attempts=200,
+                                 t_end=2e-12)
+        out.append((md.cpu().numpy()[0], float(t.cpu()[0])))
+        close(g, T, p)
+    assert abs(out[0][1] - out[1][1]) <= 1e-6 * out[1][1] or out[0][1] == out[1][1]
+    assert np.abs(out[0][0] - out[1][0]).max() <= 1e-4
+
+
+def test_psym_rejects_unlike_tiles(tmg, ctx):
+    slab = W.refined_slab(n_target=300, lx=200e-9, ly=60e-9, lz=20e-9)
+    g = tmg.Geometry(ctx, slab.centers, slab.sizes)
+    with pytest.raises(tmg.TilemagError) as ei:
+        tmg.Tensor(ctx, g, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM6)
+    assert ei.value.status == tmg.TM_EINVAL
+    c, s = _meshes()["grid13x5"]
+    g2 = tmg.Geometry(ctx, c, s)
+    with pytest.raises(tmg.TilemagError):
+        tmg.Tensor(ctx, g2, tmg.TM_PREC_FP64, tmg.TM_LAYOUT_PSYM6)
+    close(g, g2)
