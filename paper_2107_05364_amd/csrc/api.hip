@@ -214,9 +214,14 @@ tm_status tm_tensor_assemble(tm_ctx* c, const tm_geom* g, tm_prec store, tm_layo
     int64_t main_bytes = 0, lo_bytes = 0, sc_bytes = 0;
     std::vector<int32_t> pairs;
     if (layout == TM_LAYOUT_PSYM6) {
+        // pair table: the diagonal pairs first, then I < J row by row
         T->nt = (n + kPsTile - 1) / kPsTile;
+        for (int64_t I = 0; I < T->nt; ++I) {
+            pairs.push_back(static_cast<int32_t>(I));
+            pairs.push_back(static_cast<int32_t>(I));
+        }
         for (int64_t I = 0; I < T->nt; ++I)
-            for (int64_t J = I; J < T->nt; ++J) {
+            for (int64_t J = I + 1; J < T->nt; ++J) {
                 pairs.push_back(static_cast<int32_t>(I));
                 pairs.push_back(static_cast<int32_t>(J));
             }

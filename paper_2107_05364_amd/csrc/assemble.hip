@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void k_split_fp16_rows(int64_t ld, const float
 }
 
 // PSYM6: tile pair p = (I, J), I <= J, holds block (al, bl) = tensor of tile
-// 64 J + bl at the centre of tile 64 I + al as planes [6][64][64]; blocks that
+// kPsTile J + bl at the centre of tile kPsTile I + al as planes [6][kPsTile][kPsTile]; blocks that
 // involve a padding index (>= n) are zero.
 __global__ __launch_bounds__(256) void k_assemble_psym6(int32_t n, const int32_t* __restrict__ pairs,
                                                         const double* __restrict__ centers,

@@ -95,7 +95,7 @@ struct Tensor {
     int64_t* row_ptr = nullptr;
     int32_t* col = nullptr;
     int64_t nnzb = 0;
-    // PSYM6 (pair-symmetric): data = float [npairs][6][64][64] tiles of the
+    // PSYM6 (pair-symmetric): data = float [npairs][6][kPsTile][kPsTile] tiles of the
     // upper triangle, pairs = int32 [npairs][2] (I, J), I <= J, nt tiles a side
     int32_t* pairs = nullptr;
     int64_t npairs = 0, nt = 0;
@@ -233,12 +233,13 @@ tm_status bsr_rows(const Tensor* T, int64_t a0, int64_t count, double* out);
 // Pair-symmetric (PSYM6) operators (psym.hip): tiles of kPsTile x kPsTile
 // blocks; assembly, field kernels (tile pass + fixed-order reduction with the
 // epilogue), partial-buffer size and host read-back.
-constexpr int kPsTile = 64;
+constexpr int kPsTile = 32;
 tm_status assemble_psym(Tensor* T, const double* d_centers, const double* d_sizes, hipStream_t s);
 tm_status launch_field_psym(const Problem* p, Epi mode, int64_t B, const float* X, const EpiArgs& e,
                             hipStream_t s);
 int64_t psym_partial_floats(const Tensor* T, int64_t B);
-tm_status launch_psym_tiles(const Problem* p, int64_t B, const float* X, const double* h, hipStream_t s);
+tm_status launch_psym_tiles(const Problem* p, int64_t B, const float* X, const double* h, const float* Ha,
+                            hipStream_t s);
 tm_status psym_rows(const Tensor* T, int64_t a0, int64_t count, double* out);
 
 // Launch shapes of the fused field kernel: (index, workgroup threads,

@@ -21,7 +21,33 @@ __device__ constexpr double kDpB[7] = {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 19
 __device__ constexpr double kDpBs[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640,
                                         -92097.0 / 339200, 187.0 / 2100, 1.0 / 40};
 
-template <Epi MODE>
+// Local effective-field terms of tile a in state s (exchange, anisotropy,
+// applied field), added to H; x is the state's stage input.
+__device__ inline void add_local_field(const DevProblem& P, const float* __restrict__ x,
+                                       const float* __restrict__ Ha, int s, int a, float m0, float m1,
+                                       float m2, float& H0, float& H1, float& H2) {
+    const int32_t j0 = P.nbr_ptr[a], j1 = P.nbr_ptr[a + 1];
+    for (int32_t j = j0; j < j1; ++j) {
+        const int32_t b = P.nbr_idx[j];
+        const float w = P.nbr_w[j];
+        H0 += w * (x[3 * b] - m0);
+        H1 += w * (x[3 * b + 1] - m1);
+        H2 += w * (x[3 * b + 2] - m2);
+    }
+    if (P.ku) {
+        const float e0 = P.easy[3 * a], e1 = P.easy[3 * a + 1], e2 = P.easy[3 * a + 2];
+        const float g = P.ku[a] * (m0 * e0 + m1 * e1 + m2 * e2);
+        H0 += g * e0; H1 += g * e1; H2 += g * e2;
+    }
+    if (Ha) {
+        H0 += Ha[3 * s]; H1 += Ha[3 * s + 1]; H2 += Ha[3 * s + 2];
+    }
+}
+
+// LOCAL = false: (hd0, hd1, hd2) already holds the whole effective field
+// (the caller added the local terms), so only the right-hand side and the
+// stage remain.
+template <Epi MODE, bool LOCAL = true>
 __device__ void finish_tile(const DevProblem& P, const float* __restrict__ X, int64_t sx,
                             const EpiArgs& E, int s, int a, float hd0, float hd1, float hd2,
                             double* rmax, double* dmax) {
@@ -34,22 +60,7 @@ __device__ void finish_tile(const DevProblem& P, const float* __restrict__ X, in
         const float* x = X + s * sx;
         const float m0 = x[3 * a], m1 = x[3 * a + 1], m2 = x[3 * a + 2];
         float H0 = hd0, H1 = hd1, H2 = hd2;
-        const int32_t j0 = P.nbr_ptr[a], j1 = P.nbr_ptr[a + 1];
-        for (int32_t j = j0; j < j1; ++j) {
-            const int32_t b = P.nbr_idx[j];
-            const float w = P.nbr_w[j];
-            H0 += w * (x[3 * b] - m0);
-            H1 += w * (x[3 * b + 1] - m1);
-            H2 += w * (x[3 * b + 2] - m2);
-        }
-        if (P.ku) {
-            const float e0 = P.easy[3 * a], e1 = P.easy[3 * a + 1], e2 = P.easy[3 * a + 2];
-            const float g = P.ku[a] * (m0 * e0 + m1 * e1 + m2 * e2);
-            H0 += g * e0; H1 += g * e1; H2 += g * e2;
-        }
-        if (E.Ha) {
-            H0 += E.Ha[3 * s]; H1 += E.Ha[3 * s + 1]; H2 += E.Ha[3 * s + 2];
-        }
+        if constexpr (LOCAL) add_local_field(P, x, E.Ha, s, a, m0, m1, m2, H0, H1, H2);
         if constexpr (MODE == Epi::HEFF) {
             float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
             out[0] = H0; out[1] = H1; out[2] = H2;

@@ -209,6 +209,7 @@ __global__ void k_control_rk4(int64_t B, const double* __restrict__ prm, double*
 // then forms the next attempt's stage-2 input y + h a21 k1.  No block
 // depends on another.
 constexpr int kCommitThreads = 1024;
+constexpr int kCommitCached = 4;  // tiles per thread whose data is loaded before the decision
 
 __global__ __launch_bounds__(kCommitThreads) void k_commit(
     int32_t n, int64_t np, float* __restrict__ y, float* __restrict__ k1,
@@ -221,6 +222,27 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(
     __shared__ double r0[NW], r1[NW];
     const int64_t s = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // everything the decision does not change is loaded first, so that its
+    // latency overlaps the reduction: the control values and, for the first
+    // kCommitCached * kCommitThreads tiles, both candidate states and slopes
+    const double h0 = h[s], t0 = t[s], dt0 = dt[s];
+    const int64_t st0 = steps[s], rj0 = rejected[s];
+    const int32_t f0 = flags[s];
+    float cy[kCommitCached][3], cy5[kCommitCached][3], ck1[kCommitCached][3], ck7[kCommitCached][3];
+#pragma unroll
+    for (int i = 0; i < kCommitCached; ++i) {
+        const int64_t a = threadIdx.x + static_cast<int64_t>(i) * kCommitThreads;
+        if (a < n) {
+            const int64_t o = s * 3 * np + 3 * a;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cy[i][c] = y[o + c];
+                cy5[i][c] = y5[o + c];
+                ck1[i][c] = k1[o + c];
+                ck7[i][c] = k7[o + c];
+            }
+        }
+    }
     double e = 0.0, dm = 0.0;
     for (int64_t i = threadIdx.x; i < nblk; i += kCommitThreads) {
         e = fmax(e, errp[s * pstride + i]);
@@ -235,7 +257,7 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(
         r0[wave] = e;
         r1[wave] = dm;
     }
-    __syncthreads();
+    __syncthreads();  // also: every thread has read the old control values
     e = r0[0];
     dm = r1[0];
 #pragma unroll
@@ -243,8 +265,7 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(
         e = fmax(e, r0[w]);
         dm = fmax(dm, r1[w]);
     }
-    const Decision d = dp_decide(prm, e, dm, h[s], t[s], dt[s], steps[s], rejected[s], flags[s]);
-    __syncthreads();  // every thread has read the old control values
+    const Decision d = dp_decide(prm, e, dm, h0, t0, dt0, st0, rj0, f0);
     if (threadIdx.x == 0) {
         t[s] = d.t;
         dt[s] = d.dt;
@@ -256,25 +277,37 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(
     }
     const bool renorm = prm[RP_RENORM] != 0.0;
     const float hh = static_cast<float>(d.h) * (1.0f / 5.0f);
-    for (int64_t a = threadIdx.x; a < n; a += kCommitThreads) {
+    auto apply = [&](int64_t a, const float* vy, const float* vy5, const float* vk1, const float* vk7) {
         const int64_t o = s * 3 * np + 3 * a;
         float v0, v1, v2, g0, g1, g2;
         if (d.acc) {
-            v0 = y5[o]; v1 = y5[o + 1]; v2 = y5[o + 2];
+            v0 = vy5[0]; v1 = vy5[1]; v2 = vy5[2];
             if (renorm) {
                 const float r = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
                 v0 *= r; v1 *= r; v2 *= r;
             }
-            g0 = k7[o]; g1 = k7[o + 1]; g2 = k7[o + 2];
+            g0 = vk7[0]; g1 = vk7[1]; g2 = vk7[2];
             y[o] = v0; y[o + 1] = v1; y[o + 2] = v2;
             k1[o] = g0; k1[o + 1] = g1; k1[o + 2] = g2;
         } else {
-            v0 = y[o]; v1 = y[o + 1]; v2 = y[o + 2];
-            g0 = k1[o]; g1 = k1[o + 1]; g2 = k1[o + 2];
+            v0 = vy[0]; v1 = vy[1]; v2 = vy[2];
+            g0 = vk1[0]; g1 = vk1[1]; g2 = vk1[2];
         }
         ya[o] = v0 + hh * g0;
         ya[o + 1] = v1 + hh * g1;
         ya[o + 2] = v2 + hh * g2;
+    };
+#pragma unroll
+    for (int i = 0; i < kCommitCached; ++i) {
+        const int64_t a = threadIdx.x + static_cast<int64_t>(i) * kCommitThreads;
+        if (a < n) apply(a, cy[i], cy5[i], ck1[i], ck7[i]);
+    }
+    for (int64_t a = threadIdx.x + static_cast<int64_t>(kCommitCached) * kCommitThreads; a < n;
+         a += kCommitThreads) {
+        const int64_t o = s * 3 * np + 3 * a;
+        const float vy[3] = {y[o], y[o + 1], y[o + 2]}, vy5[3] = {y5[o], y5[o + 1], y5[o + 2]};
+        const float vk1[3] = {k1[o], k1[o + 1], k1[o + 2]}, vk7[3] = {k7[o], k7[o + 1], k7[o + 2]};
+        apply(a, vy, vy5, vk1, vk7);
     }
 }
 

@@ -376,7 +376,7 @@ tm_status time_field(Problem* p, int64_t B, int mode, int32_t iters, hipStream_t
     // launch (the pair-symmetric tile pass); otherwise the whole evaluation
     const bool tiles_only = mode == 3 && p->T->layout == TM_LAYOUT_PSYM6;
     auto one = [&]() {
-        return tiles_only ? launch_psym_tiles(p, B, X, w->h, s) : launch_field(p, ep, B, X, e, s);
+        return tiles_only ? launch_psym_tiles(p, B, X, w->h, w->Ha, s) : launch_field(p, ep, B, X, e, s);
     };
     tm_status st = one();  // untimed first launch
     if (st == TM_OK && hipEventRecord(e0, s) != hipSuccess) st = TM_EDEVICE;

@@ -4,21 +4,23 @@
 // tile a depends only on the centre offset and is even in it, so
 // N^{ab} = N^{ba}; with the symmetry of each 3x3 block this is the symmetry
 // the paper invokes to store roughly half of the operator (Sec. 3.2).  The
-// operator is cut into 64 x 64-block tiles and only the tile pairs I <= J are
-// stored ([pairs][6][64][64] float32, a diagonal tile in full).
+// operator is cut into TS x TS-block tiles (TS = kPsTile) and only the tile
+// pairs I <= J are stored ([pairs][6][TS][TS] float32, a diagonal tile in
+// full).
 //
 // Product, two launches per field evaluation:
 //  * k_psym_tiles: one workgroup per (tile pair, state) reads its tile once
 //    and forms both uses of it: the row sums  sum_b N^{ab} (Ms m)_b  for the
 //    targets a of tile I, and for I < J the column sums
 //    sum_a N^{ab} (Ms m)_a = sum_a N^{ba} (Ms m)_a  for the targets b of
-//    tile J.  Each lands in its own slot part[s][K][j][64][3] (K = the target
+//    tile J.  Each lands in its own slot part[s][K][j][TS][3] (K = the target
 //    tile, j = the other tile), so every slot has exactly one writer.
 //  * k_psym_finish: one workgroup per (target tile K, state) adds the nt
-//    slots of K in ascending j (a fixed order: results do not depend on
-//    scheduling or on the batch) and runs the fused epilogue for its 64
-//    tiles.
-// Streamed bytes: 24 B x 4096 per stored tile pair, i.e. about 12 N^2 + 12 N x 64
+//    slots of K (a fixed order: results do not depend on scheduling or on
+//    the batch) and completes the right-hand side and the stage for its TS
+//    tiles; the local field terms were folded into the diagonal slot by the
+//    tile pass.
+// Streamed bytes: 24 B x TS^2 per stored tile pair, i.e. about 12 N^2 + 12 N TS
 // against 24 N^2 for SYM6.
 #include <hip/hip_runtime.h>
 
@@ -32,64 +34,100 @@ namespace {
 
 constexpr int TS = kPsTile;
 constexpr int TB = kPsTile * kPsTile;
-constexpr int kRowsPerWave = TS / 4;
+constexpr int RG = 256 / TS;       // row groups of a workgroup (one column per lane)
+constexpr int RPT = TS / RG;       // rows per thread
+static_assert(TS * RG == 256 && RPT * RG == TS, "tile size must divide the workgroup");
 
-// Index of tile pair (I, J), I <= J, in row-major upper-triangle order.
-inline int64_t pair_index(int64_t I, int64_t J, int64_t nt) { return I * nt - I * (I - 1) / 2 + (J - I); }
+// Index of tile pair (I, J), I <= J, in the pair table: the nt diagonal
+// pairs first, then the pairs I < J in row-major order.
+inline int64_t pair_index(int64_t I, int64_t J, int64_t nt) {
+    return I == J ? I : nt + I * (nt - 1) - I * (I - 1) / 2 + (J - I - 1);
+}
 
-template <bool STEPPING>
-__global__ __launch_bounds__(256) void k_psym_tiles(const float* __restrict__ tiles,
+// One workgroup per (tile pair, state).  Thread t takes column b = t % TS of
+// the tile and rows rg RPT .. rg RPT + RPT - 1 (rg = t / TS): each row's six
+// components are coalesced loads, the row sums go through LDS to a sum over
+// the TS columns, the column sums through LDS to a sum over the RG groups
+// (both in a fixed order).
+//
+// LOCALF: the workgroups of diagonal pairs (I == J) also evaluate the local
+// field terms (exchange, anisotropy, applied field) of their TS tiles --
+// issued before the tile is streamed, so that the dependent neighbour loads
+// overlap it, and dispatched first (diagonal pairs lead the pair table) --
+// and subtract them from their own slot, so that minus the slot sum is the
+// whole effective field and the finish kernel has no dependent loads left.
+template <bool STEPPING, bool LOCALF>
+__global__ __launch_bounds__(256) void k_psym_tiles(DevProblem P, const float* __restrict__ tiles,
                                                     const int32_t* __restrict__ pairs, int64_t nt,
                                                     const float* __restrict__ Ms, const float* __restrict__ X,
                                                     int64_t sx, const double* __restrict__ h,
-                                                    float* __restrict__ part) {
+                                                    const float* __restrict__ Ha, float* __restrict__ part) {
     const int64_t p = blockIdx.x;
     const int64_t s = blockIdx.y;
     if (STEPPING && h[s] == 0.0) return;  // frozen state: its slots are not read
     const int64_t I = pairs[2 * p], J = pairs[2 * p + 1];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __shared__ float rred[TS][3][TS + 1];  // row sums before the lane reduction
-    __shared__ float cred[4][TS][3];       // column sums per wave
+    const int t = threadIdx.x;
+    const int b = t % TS, rg = t / TS;
+    __shared__ float rred[TS][3][TS + 1];  // row sums before the column reduction
+    __shared__ float cred[RG][TS][3];      // column sums per row group
+    __shared__ float hl[TS][3];            // local field terms (diagonal pairs)
     const float* x = X + s * sx;
-    const int64_t bg = TS * J + lane;
+    if (LOCALF && I == J && t < TS) {
+        const int64_t a = TS * I + t;
+        float H0 = 0.0f, H1 = 0.0f, H2 = 0.0f;
+        if (a < P.n)
+            add_local_field(P, x, Ha, static_cast<int>(s), static_cast<int>(a), x[3 * a], x[3 * a + 1],
+                            x[3 * a + 2], H0, H1, H2);
+        hl[t][0] = H0;
+        hl[t][1] = H1;
+        hl[t][2] = H2;
+    }
+    const int64_t bg = TS * J + b;
     const float msb = Ms[bg];
     const float xb0 = x[3 * bg] * msb, xb1 = x[3 * bg + 1] * msb, xb2 = x[3 * bg + 2] * msb;
     const float* tile = tiles + p * 6 * TB;
     float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-#pragma unroll 4
-    for (int i = 0; i < kRowsPerWave; ++i) {
-        const int al = kRowsPerWave * w + i;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int al = RPT * rg + i;
         const int64_t ag = TS * I + al;
         const float msa = Ms[ag];
         const float xa0 = x[3 * ag] * msa, xa1 = x[3 * ag + 1] * msa, xa2 = x[3 * ag + 2] * msa;
-        const int off = al * TS + lane;
+        const int off = al * TS + b;
         const float v0 = tile[off], v1 = tile[TB + off], v2 = tile[2 * TB + off];
         const float v3 = tile[3 * TB + off], v4 = tile[4 * TB + off], v5 = tile[5 * TB + off];
-        rred[al][0][lane] = v0 * xb0 + v1 * xb1 + v2 * xb2;
-        rred[al][1][lane] = v1 * xb0 + v3 * xb1 + v4 * xb2;
-        rred[al][2][lane] = v2 * xb0 + v4 * xb1 + v5 * xb2;
+        rred[al][0][b] = v0 * xb0 + v1 * xb1 + v2 * xb2;
+        rred[al][1][b] = v1 * xb0 + v3 * xb1 + v4 * xb2;
+        rred[al][2][b] = v2 * xb0 + v4 * xb1 + v5 * xb2;
         c0 += v0 * xa0 + v1 * xa1 + v2 * xa2;
         c1 += v1 * xa0 + v3 * xa1 + v4 * xa2;
         c2 += v2 * xa0 + v4 * xa1 + v5 * xa2;
     }
-    cred[w][lane][0] = c0;
-    cred[w][lane][1] = c1;
-    cred[w][lane][2] = c2;
+    cred[rg][b][0] = c0;
+    cred[rg][b][1] = c1;
+    cred[rg][b][2] = c2;
     __syncthreads();
-    const int t = threadIdx.x;
     if (t < 3 * TS) {
         const int r = t / 3, c = t % 3;
         float acc = 0.0f;
 #pragma unroll 8
         for (int l = 0; l < TS; ++l) acc += rred[r][c][l];
+        if (LOCALF && I == J) acc -= hl[r][c];
         part[((s * nt + I) * nt + J) * (3 * TS) + t] = acc;
         if (I != J) {
-            const float cs = ((cred[0][r][c] + cred[1][r][c]) + cred[2][r][c]) + cred[3][r][c];
+            float cs = 0.0f;
+#pragma unroll
+            for (int q = 0; q < RG; ++q) cs += cred[q][r][c];
             part[((s * nt + J) * nt + I) * (3 * TS) + t] = cs;
         }
     }
 }
 
+// One workgroup per (target tile K, state): the nt slots of K are contiguous
+// ([nt][TS][3] floats); thread (g, q) = (t / TS, t % TS) adds the slots
+// j = g, g + RG, ... of tile q (independent coalesced loads), then the RG
+// group sums are added in order g = 0 .. RG-1 and the first TS lanes run the
+// epilogue of their tile.
 template <Epi MODE>
 __global__ __launch_bounds__(256) void k_psym_finish(DevProblem P, const float* __restrict__ part, int64_t nt,
                                                      const float* X, int64_t sx, EpiArgs E) {
@@ -102,20 +140,36 @@ __global__ __launch_bounds__(256) void k_psym_finish(DevProblem P, const float* 
     if constexpr (MODE == Epi::STAGE || MODE == Epi::RK4_FINAL) {
         if (frozen) return;
     }
-    __shared__ float hb[3 * TS];
-    const int t = threadIdx.x;
-    if (!frozen && t < 3 * TS) {
-        const float* src = part + (static_cast<int64_t>(s) * nt + K) * nt * (3 * TS) + t;
-        float acc = 0.0f;
-        for (int64_t j = 0; j < nt; ++j) acc += src[j * (3 * TS)];
-        hb[t] = -acc;
+    __shared__ float gs[RG][TS][3];
+    const int q = threadIdx.x % TS, grp = threadIdx.x / TS;
+    if (!frozen) {
+        const float* src = part + (static_cast<int64_t>(s) * nt + K) * nt * (3 * TS) + 3 * q;
+        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+#pragma unroll 4
+        for (int64_t j = grp; j < nt; j += RG) {
+            const float* v = src + j * (3 * TS);
+            a0 += v[0];
+            a1 += v[1];
+            a2 += v[2];
+        }
+        gs[grp][q][0] = a0;
+        gs[grp][q][1] = a1;
+        gs[grp][q][2] = a2;
     }
     __syncthreads();
     if (wave != 0) return;
     double rmax = 0.0, dmax = 0.0;
     const int64_t a = TS * K + lane;
-    if (!frozen && a < P.n)
-        finish_tile<MODE>(P, X, sx, E, s, a, hb[3 * lane], hb[3 * lane + 1], hb[3 * lane + 2], &rmax, &dmax);
+    if (!frozen && lane < TS && a < P.n) {
+        float hx = 0.0f, hy = 0.0f, hz = 0.0f;
+#pragma unroll
+        for (int g2 = 0; g2 < RG; ++g2) {
+            hx += gs[g2][lane][0];
+            hy += gs[g2][lane][1];
+            hz += gs[g2][lane][2];
+        }
+        finish_tile<MODE, false>(P, X, sx, E, s, a, -hx, -hy, -hz, &rmax, &dmax);
+    }
     if constexpr (MODE == Epi::DP_LAST) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -130,9 +184,10 @@ template <Epi MODE>
 void launch_psym_t(const DevProblem& P, const Tensor* T, const float* Ms, float* part, int64_t B,
                    const float* X, int64_t sx, const EpiArgs& e, hipStream_t s) {
     constexpr bool STEPPING = MODE == Epi::STAGE || MODE == Epi::RK4_FINAL || MODE == Epi::DP_LAST;
+    constexpr bool LOCALF = MODE != Epi::HD;
     const dim3 g1(static_cast<unsigned>(T->npairs), static_cast<unsigned>(B));
-    k_psym_tiles<STEPPING><<<g1, 256, 0, s>>>(static_cast<const float*>(T->data), T->pairs, T->nt, Ms, X, sx,
-                                              e.h, part);
+    k_psym_tiles<STEPPING, LOCALF><<<g1, 256, 0, s>>>(P, static_cast<const float*>(T->data), T->pairs, T->nt,
+                                                      Ms, X, sx, e.h, e.Ha, part);
     const dim3 g2(static_cast<unsigned>(T->nt), static_cast<unsigned>(B));
     k_psym_finish<MODE><<<g2, 256, 0, s>>>(P, part, T->nt, X, sx, e);
 }
@@ -141,14 +196,15 @@ void launch_psym_t(const DevProblem& P, const Tensor* T, const float* Ms, float*
 
 int64_t psym_partial_floats(const Tensor* T, int64_t B) { return B * T->nt * T->nt * 3 * TS; }
 
-tm_status launch_psym_tiles(const Problem* p, int64_t B, const float* X, const double* h, hipStream_t s) {
+tm_status launch_psym_tiles(const Problem* p, int64_t B, const float* X, const double* h, const float* Ha,
+                            hipStream_t s) {
     const Tensor* T = p->T;
     Workspace* w = p->ws.get();
     TM_REQUIRE(T->layout == TM_LAYOUT_PSYM6 && w && w->part && w->B >= B, TM_EINVAL,
                "pair-symmetric tile pass: not prepared");
     const dim3 g1(static_cast<unsigned>(T->npairs), static_cast<unsigned>(B));
-    k_psym_tiles<true><<<g1, 256, 0, s>>>(static_cast<const float*>(T->data), T->pairs, T->nt, p->Ms, X,
-                                          3 * p->np, h, w->part);
+    k_psym_tiles<true, true><<<g1, 256, 0, s>>>(p->dev(), static_cast<const float*>(T->data), T->pairs, T->nt,
+                                                p->Ms, X, 3 * p->np, h, Ha, w->part);
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
 }

@@ -99,7 +99,7 @@ def test_psym_film_full(tmg, ctx, orc):
     e2, emax = rel_errors(Hd, want)
     assert e2 <= 1e-5 and emax <= 1e-5, (e2, emax)
     # about half the bytes of the six-plane layout
-    assert T.nbytes < 0.56 * 24 * wl.n * wl.n
+    assert T.nbytes < 0.53 * 24 * wl.n * wl.n
     close(g, T, p)
 
 
