@@ -44,97 +44,133 @@ __device__ inline void add_local_field(const DevProblem& P, const float* __restr
     }
 }
 
-// LOCAL = false: (hd0, hd1, hd2) already holds the whole effective field
-// (the caller added the local terms), so only the right-hand side and the
-// stage remain.
+// Inputs of the epilogue that do not depend on the field: the tile's state
+// m and, for the stepping modes, the previous stage slopes and the step's
+// base state.  Loading them first lets a caller overlap their latency with
+// the field's own reduction.
+struct EpiIn {
+    float m[3];
+    float y[3];
+    float kp[6][3];
+};
+
+template <Epi MODE>
+__device__ inline void epi_load(const float* __restrict__ X, int64_t sx, const EpiArgs& E, int s, int a,
+                                EpiIn& in) {
+    const int64_t o = s * sx + 3 * static_cast<int64_t>(a);
+    if constexpr (MODE != Epi::HD) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) in.m[c] = X[o + c];
+    }
+    if constexpr (MODE == Epi::STAGE || MODE == Epi::RK4_FINAL || MODE == Epi::DP_LAST) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            if (MODE == Epi::DP_LAST || j < E.nprev) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) in.kp[j][c] = E.kprev[j][o + c];
+            }
+        }
+        const float* y = MODE == Epi::RK4_FINAL ? E.y_mut : E.y;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) in.y[c] = y[o + c];
+    }
+}
+
+// The epilogue proper from the whole effective field (H0, H1, H2) of tile a
+// in state s: HD / HEFF store it, DMDT the Landau-Lifshitz right-hand side,
+// the stepping modes complete their Runge-Kutta stage.
+template <Epi MODE>
+__device__ void epi_compute(const DevProblem& P, int64_t sx, const EpiArgs& E, int s, int a,
+                            const EpiIn& in, float H0, float H1, float H2, double* rmax, double* dmax) {
+    const int64_t o = s * sx + 3 * static_cast<int64_t>(a);
+    if constexpr (MODE == Epi::HD || MODE == Epi::HEFF) {
+        float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
+        out[0] = H0; out[1] = H1; out[2] = H2;
+        return;
+    } else {
+        const float m0 = in.m[0], m1 = in.m[1], m2 = in.m[2];
+        // m x H and m x (m x H)
+        const float p0 = m1 * H2 - m2 * H1, p1 = m2 * H0 - m0 * H2, p2 = m0 * H1 - m1 * H0;
+        const float q0 = m1 * p2 - m2 * p1, q1 = m2 * p0 - m0 * p2, q2 = m0 * p1 - m1 * p0;
+        const float k0 = -P.c1 * p0 - P.c2 * q0;
+        const float k1 = -P.c1 * p1 - P.c2 * q1;
+        const float k2 = -P.c1 * p2 - P.c2 * q2;
+        if constexpr (MODE == Epi::DMDT) {
+            float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
+            out[0] = k0; out[1] = k1; out[2] = k2;
+            return;
+        } else if constexpr (MODE == Epi::STAGE) {
+            float* out = E.out + o;
+            out[0] = k0; out[1] = k1; out[2] = k2;
+            const float h = static_cast<float>(E.h[s]);
+            float c0 = E.coef[E.nprev] * k0, c1 = E.coef[E.nprev] * k1, c2 = E.coef[E.nprev] * k2;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                if (j < E.nprev) {
+                    c0 += E.coef[j] * in.kp[j][0]; c1 += E.coef[j] * in.kp[j][1]; c2 += E.coef[j] * in.kp[j][2];
+                }
+            }
+            float* yn = E.ynext + o;
+            yn[0] = in.y[0] + h * c0; yn[1] = in.y[1] + h * c1; yn[2] = in.y[2] + h * c2;
+            return;
+        } else if constexpr (MODE == Epi::RK4_FINAL) {
+            const double hd = E.h[s];
+            if (hd == 0.0) return;
+            const float h = static_cast<float>(hd);
+            float c0 = E.coef[E.nprev] * k0, c1 = E.coef[E.nprev] * k1, c2 = E.coef[E.nprev] * k2;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                if (j < E.nprev) {
+                    c0 += E.coef[j] * in.kp[j][0]; c1 += E.coef[j] * in.kp[j][1]; c2 += E.coef[j] * in.kp[j][2];
+                }
+            }
+            float v0 = in.y[0] + h * c0, v1 = in.y[1] + h * c1, v2 = in.y[2] + h * c2;
+            if (E.renorm) {
+                const float r = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+                v0 *= r; v1 *= r; v2 *= r;
+            }
+            float* y = E.y_mut + o;
+            y[0] = v0; y[1] = v1; y[2] = v2;
+            return;
+        } else {  // DP_LAST: k7 at the fifth-order solution, float64 error estimate
+            float* out = E.out + o;
+            out[0] = k0; out[1] = k1; out[2] = k2;
+            const double h = E.h[s];
+            double e0 = (kDpB[6] - kDpBs[6]) * k0, e1 = (kDpB[6] - kDpBs[6]) * k1,
+                   e2 = (kDpB[6] - kDpBs[6]) * k2;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                const double w = kDpB[j] - kDpBs[j];
+                e0 += w * in.kp[j][0]; e1 += w * in.kp[j][1]; e2 += w * in.kp[j][2];
+            }
+            const double atol = E.params[RP_ATOL], rtol = E.params[RP_RTOL];
+            const double s0 = atol + rtol * fmax(fabs((double)in.y[0]), fabs((double)m0));
+            const double s1 = atol + rtol * fmax(fabs((double)in.y[1]), fabs((double)m1));
+            const double s2 = atol + rtol * fmax(fabs((double)in.y[2]), fabs((double)m2));
+            const double r0 = fabs(h * e0) / s0, r1 = fabs(h * e1) / s1, r2 = fabs(h * e2) / s2;
+            // a NaN anywhere must win the max: map it to +inf (fmax drops NaN)
+            const bool bad = !(r0 == r0) || !(r1 == r1) || !(r2 == r2);
+            *rmax = bad ? INFINITY : fmax(r0, fmax(r1, r2));
+            const double d = sqrt((double)k0 * k0 + (double)k1 * k1 + (double)k2 * k2);
+            *dmax = (d == d) ? d : INFINITY;
+            return;
+        }
+    }
+}
+
+// Whole epilogue from H_d of tile a in state s.  LOCAL = false: (hd0, hd1,
+// hd2) already holds the whole effective field (the caller added the local
+// terms).
 template <Epi MODE, bool LOCAL = true>
 __device__ void finish_tile(const DevProblem& P, const float* __restrict__ X, int64_t sx,
                             const EpiArgs& E, int s, int a, float hd0, float hd1, float hd2,
                             double* rmax, double* dmax) {
-    const int64_t o = s * sx + 3 * static_cast<int64_t>(a);
-    if constexpr (MODE == Epi::HD) {
-        float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
-        out[0] = hd0; out[1] = hd1; out[2] = hd2;
-        return;
-    } else {
-        const float* x = X + s * sx;
-        const float m0 = x[3 * a], m1 = x[3 * a + 1], m2 = x[3 * a + 2];
-        float H0 = hd0, H1 = hd1, H2 = hd2;
-        if constexpr (LOCAL) add_local_field(P, x, E.Ha, s, a, m0, m1, m2, H0, H1, H2);
-        if constexpr (MODE == Epi::HEFF) {
-            float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
-            out[0] = H0; out[1] = H1; out[2] = H2;
-            return;
-        } else {
-            // m x H and m x (m x H)
-            const float p0 = m1 * H2 - m2 * H1, p1 = m2 * H0 - m0 * H2, p2 = m0 * H1 - m1 * H0;
-            const float q0 = m1 * p2 - m2 * p1, q1 = m2 * p0 - m0 * p2, q2 = m0 * p1 - m1 * p0;
-            const float k0 = -P.c1 * p0 - P.c2 * q0;
-            const float k1 = -P.c1 * p1 - P.c2 * q1;
-            const float k2 = -P.c1 * p2 - P.c2 * q2;
-            if constexpr (MODE == Epi::DMDT) {
-                float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
-                out[0] = k0; out[1] = k1; out[2] = k2;
-                return;
-            } else if constexpr (MODE == Epi::STAGE) {
-                float* out = E.out + o;
-                out[0] = k0; out[1] = k1; out[2] = k2;
-                const float h = static_cast<float>(E.h[s]);
-                float c0 = E.coef[E.nprev] * k0, c1 = E.coef[E.nprev] * k1,
-                      c2 = E.coef[E.nprev] * k2;
-                for (int j = 0; j < E.nprev; ++j) {
-                    const float* kj = E.kprev[j] + o;
-                    c0 += E.coef[j] * kj[0]; c1 += E.coef[j] * kj[1]; c2 += E.coef[j] * kj[2];
-                }
-                const float* y = E.y + o;
-                float* yn = E.ynext + o;
-                yn[0] = y[0] + h * c0; yn[1] = y[1] + h * c1; yn[2] = y[2] + h * c2;
-                return;
-            } else if constexpr (MODE == Epi::RK4_FINAL) {
-                const double hd = E.h[s];
-                if (hd == 0.0) return;
-                const float h = static_cast<float>(hd);
-                float c0 = E.coef[E.nprev] * k0, c1 = E.coef[E.nprev] * k1,
-                      c2 = E.coef[E.nprev] * k2;
-                for (int j = 0; j < E.nprev; ++j) {
-                    const float* kj = E.kprev[j] + o;
-                    c0 += E.coef[j] * kj[0]; c1 += E.coef[j] * kj[1]; c2 += E.coef[j] * kj[2];
-                }
-                float* y = E.y_mut + o;
-                float v0 = y[0] + h * c0, v1 = y[1] + h * c1, v2 = y[2] + h * c2;
-                if (E.renorm) {
-                    const float r = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
-                    v0 *= r; v1 *= r; v2 *= r;
-                }
-                y[0] = v0; y[1] = v1; y[2] = v2;
-                return;
-            } else {  // DP_LAST: k7 at the fifth-order solution, float64 error estimate
-                float* out = E.out + o;
-                out[0] = k0; out[1] = k1; out[2] = k2;
-                const double h = E.h[s];
-                double e0 = (kDpB[6] - kDpBs[6]) * k0, e1 = (kDpB[6] - kDpBs[6]) * k1,
-                       e2 = (kDpB[6] - kDpBs[6]) * k2;
-#pragma unroll
-                for (int j = 0; j < 6; ++j) {
-                    const double w = kDpB[j] - kDpBs[j];
-                    const float* kj = E.kprev[j] + o;
-                    e0 += w * kj[0]; e1 += w * kj[1]; e2 += w * kj[2];
-                }
-                const double atol = E.params[RP_ATOL], rtol = E.params[RP_RTOL];
-                const float* y = E.y + o;
-                const double s0 = atol + rtol * fmax(fabs((double)y[0]), fabs((double)m0));
-                const double s1 = atol + rtol * fmax(fabs((double)y[1]), fabs((double)m1));
-                const double s2 = atol + rtol * fmax(fabs((double)y[2]), fabs((double)m2));
-                const double r0 = fabs(h * e0) / s0, r1 = fabs(h * e1) / s1, r2 = fabs(h * e2) / s2;
-                // a NaN anywhere must win the max: map it to +inf (fmax drops NaN)
-                const bool bad = !(r0 == r0) || !(r1 == r1) || !(r2 == r2);
-                *rmax = bad ? INFINITY : fmax(r0, fmax(r1, r2));
-                const double d = sqrt((double)k0 * k0 + (double)k1 * k1 + (double)k2 * k2);
-                *dmax = (d == d) ? d : INFINITY;
-                return;
-            }
-        }
-    }
+    EpiIn in;
+    epi_load<MODE>(X, sx, E, s, a, in);
+    float H0 = hd0, H1 = hd1, H2 = hd2;
+    if constexpr (LOCAL && MODE != Epi::HD)
+        add_local_field(P, X + s * sx, E.Ha, s, a, in.m[0], in.m[1], in.m[2], H0, H1, H2);
+    epi_compute<MODE>(P, sx, E, s, a, in, H0, H1, H2, rmax, dmax);
 }
 
 

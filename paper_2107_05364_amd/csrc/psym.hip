@@ -142,6 +142,11 @@ __global__ __launch_bounds__(256) void k_psym_finish(DevProblem P, const float* 
     }
     __shared__ float gs[RG][TS][3];
     const int q = threadIdx.x % TS, grp = threadIdx.x / TS;
+    // the epilogue's own inputs are loaded before the slots are summed
+    const int64_t a = TS * K + lane;
+    const bool mine = !frozen && wave == 0 && lane < TS && a < P.n;
+    EpiIn in;
+    if (mine) epi_load<MODE>(X, sx, E, s, static_cast<int>(a), in);
     if (!frozen) {
         const float* src = part + (static_cast<int64_t>(s) * nt + K) * nt * (3 * TS) + 3 * q;
         float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
@@ -159,8 +164,7 @@ __global__ __launch_bounds__(256) void k_psym_finish(DevProblem P, const float* 
     __syncthreads();
     if (wave != 0) return;
     double rmax = 0.0, dmax = 0.0;
-    const int64_t a = TS * K + lane;
-    if (!frozen && lane < TS && a < P.n) {
+    if (mine) {
         float hx = 0.0f, hy = 0.0f, hz = 0.0f;
 #pragma unroll
         for (int g2 = 0; g2 < RG; ++g2) {
@@ -168,7 +172,7 @@ __global__ __launch_bounds__(256) void k_psym_finish(DevProblem P, const float* 
             hy += gs[g2][lane][1];
             hz += gs[g2][lane][2];
         }
-        finish_tile<MODE, false>(P, X, sx, E, s, a, -hx, -hy, -hz, &rmax, &dmax);
+        epi_compute<MODE>(P, sx, E, s, static_cast<int>(a), in, -hx, -hy, -hz, &rmax, &dmax);
     }
     if constexpr (MODE == Epi::DP_LAST) {
 #pragma unroll
