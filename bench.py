@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-peaks", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-threshold", action="store_true")
+    ap.add_argument("--no-sp3", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="counter runs: one 1 GiB device copy (calibration) and the stage kernel "
                          "of the film workload only")
@@ -341,6 +342,84 @@ def threshold_section(tmg, W, torch, attempts=300, fracs=(0.2, 0.4, 0.7)):
     return out
 
 
+def sp3_section(tmg, W, torch, ns=(4, 6, 8, 10, 12, 16, 20)):
+    """Standard problem 3: for each resolution n (n^3 cubic tiles, pair-
+    symmetric operator), the edge L / l_ex at which the relaxed flower and
+    vortex states have equal energy -- a scan in steps of 0.2 l_ex, then
+    secant refinement of the sign change -- and the fit L(n) = a n^b + c whose
+    c extrapolates to an infinitely fine mesh (the paper quotes 8.477 +- 0.007
+    from its own runs, as context)."""
+    from scipy.optimize import curve_fit
+
+    out = {"workload": "cube with Ku = 0.1 Km (easy z), flower vs vortex (axis x) relaxed by pure damping "
+                       "to max|dm/dt| < 1e-4 gamma0 Ms, batch of 2 states", "resolutions": []}
+    t_all = time.perf_counter()
+    for n in ns:
+        t0 = time.perf_counter()
+        w0 = W.sp3_cube(n, 8.5)
+        ctx = tmg.Context(0)
+        geom = tmg.Geometry(ctx, w0.centers, w0.sizes)
+        T = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM6)
+        steps_total = 0
+
+        def diff(lam):
+            nonlocal steps_total
+            w = W.sp3_cube(n, lam)
+            ex = w.extra
+            p = tmg.Problem(ctx, geom, T, w.Ms, w.A, w.alpha, w.gamma0, ll_form=1, Ku=ex["Ku"], easy=ex["easy"])
+            m = torch.as_tensor(w.m0.astype(np.float32), device="cuda")
+            _, _, steps, _ = p.run(m, None, tmg.TM_DP45, dt=1e-14, max_steps=20000, dmdt_stop=ex["dmdt_stop"])
+            e = p.energy(m).sum(dim=1).cpu().numpy() / (ex["Km"] * ex["volume"])
+            steps_total += int(steps.sum().item())
+            p.close()
+            return float(e[0] - e[1]), float(e[0]), float(e[1])
+
+        lams = np.round(np.arange(7.4, 9.61, 0.2), 3)
+        prev = None
+        bracket = None
+        for lam in lams:
+            d = diff(lam)[0]
+            if prev is not None and prev[1] < 0 <= d:
+                bracket = (prev, (lam, d))
+                break
+            prev = (lam, d)
+        row = {"n": n, "tiles": n ** 3}
+        if bracket is None:
+            row["crossing"] = None
+        else:
+            (a, fa), (b, fb) = bracket
+            for _ in range(4):  # secant (regula falsi) on the energy difference
+                c = b - fb * (b - a) / (fb - fa)
+                fc = diff(c)[0]
+                if fc < 0:
+                    a, fa = c, fc
+                else:
+                    b, fb = c, fc
+            row["crossing"] = round(b - fb * (b - a) / (fb - fa), 4)
+        row["relax_steps"] = steps_total
+        row["seconds"] = round(time.perf_counter() - t0, 2)
+        out["resolutions"].append(row)
+        T.close()
+        geom.close()
+        ctx.close()
+    pts = [(r["n"], r["crossing"]) for r in out["resolutions"] if r["crossing"] is not None]
+    for key, nmin in (("fit", 0), ("fit_n_ge_8", 8)):
+        sel = [x for x in pts if x[0] >= nmin]
+        if len(sel) < 4:
+            continue
+        nn = np.array([x[0] for x in sel], float)
+        ll = np.array([x[1] for x in sel], float)
+        try:
+            (a, b, c), cov = curve_fit(lambda x, a, b, c: a * x ** b + c, nn, ll, p0=(-3.0, -1.0, 8.5), maxfev=20000)
+            out[key] = {"a": round(float(a), 4), "b": round(float(b), 4), "L_inf": round(float(c), 4),
+                        "L_inf_sd": round(float(np.sqrt(cov[2, 2])), 4)}
+        except Exception as exc:  # a failed fit is reported, not fatal
+            out[key] = {"error": str(exc)}
+    out["paper_L_inf"] = "8.477 +- 0.007 (paper's fit over its own resolutions; context only)"
+    out["seconds"] = round(time.perf_counter() - t_all, 1)
+    return out
+
+
 def peaks_section(torch):
     """Achievable rates on this device for context: a 4 GiB device copy
     (read + write bytes) and library GEMMs (torch.mm) in bf16 and fp32."""
@@ -562,6 +641,8 @@ def main():
         rec["sp4_sweep"] = sp4_sweep_section(tmg, W, torch)
     if not args.no_threshold:
         rec["threshold"] = threshold_section(tmg, W, torch)
+    if not args.no_sp3:
+        rec["sp3"] = sp3_section(tmg, W, torch)
     if not args.no_serving:
         rec["serving"] = serving_section(tmg, W, torch, count=args.serving_count)
     if not args.no_peaks:

@@ -26,7 +26,7 @@ import numpy as np
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
 _M2 = np.uint64(0x94D049BB133111EB)
-MU0 = 4.0e-7 * math.pi          # only for the mT -> A/m conversion of inputs
+MU0 = 4.0e-7 * math.pi          # only to state inputs: mT -> A/m, the energy density Km of problem 3
 GAMMA0 = 2.21e5                 # gyromagnetic constant of standard problem 4 [m/(A s)]
 NM = 1e-9
 
@@ -123,6 +123,29 @@ def thin_film(nx: int = 100, ny: int = 25, seed_m: int = 0, seed_h: int = 1) -> 
     Ha = np.array([[b * math.cos(ang), b * math.sin(ang), 0.0]])
     return Workload("thin_film_%dx%dx1" % (nx, ny), c, s, m0, Ha, alpha=0.02,
                     extra={"steps": 20000, "dt0": 1e-14, "atol": 1e-6, "rtol": 1e-6})
+
+
+def sp3_cube(n: int, lam: float, Ms: float = 8.0e5, edge: float = 20 * NM) -> Workload:
+    """Standard problem 3 (paper Sec. 4.2): a cube of edge L = lam * l_ex cut
+    into n^3 cubic tiles, with l_ex = sqrt(A / Km), Km = mu0 Ms^2 / 2 and a
+    uniaxial anisotropy Ku = 0.1 Km along z.  The edge is held at `edge` and
+    A = Km (edge / lam)^2 sets L / l_ex = lam (the demag tensor depends only on
+    shape, so one geometry serves every lam).  Two starting states:
+    m0[0] flower start, uniform along the easy axis; m0[1] vortex start,
+    circulating in the y-z planes about the x axis through the cube's centre
+    (the vortex axis perpendicular to the easy axis), tilting toward +x near
+    the axis.  Relaxation is pure damping (LL with c1 = 0, c2 = gamma0)."""
+    Km = 0.5 * MU0 * Ms * Ms
+    A = Km * (edge / lam) ** 2
+    c, s = grid(n, n, n, edge / n, edge / n, edge / n)
+    flower = np.tile([0.0, 0.0, 1.0], (c.shape[0], 1))
+    y, z = c[:, 1] - 0.5 * edge, c[:, 2] - 0.5 * edge
+    v = np.stack([np.full_like(y, 0.1 * edge), -z, y], axis=1)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return Workload("sp3_cube_n%d_L%.3f" % (n, lam), c, s, np.stack([flower, v]), np.zeros((2, 3)),
+                    Ms=Ms, A=A, alpha=GAMMA0, gamma0=0.0,
+                    extra={"Ku": 0.1 * Km, "easy": np.array([0.0, 0.0, 1.0]), "Km": Km, "lam": lam,
+                           "ll_form": 1, "volume": edge ** 3, "dmdt_stop": 1e-4 * GAMMA0 * Ms})
 
 
 def hysteresis_batch(B: int = 128, nx: int = 100, ny: int = 25, seed_axis: int = 2) -> Workload:
