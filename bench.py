@@ -265,24 +265,35 @@ def sp4_sweep_section(tmg, W, torch, attempts=300):
         p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
         shape, _ = tmg.tm_problem_tune(p.handle, 1, 10)
         ms, nb = tmg.tm_profile_field(p.handle, 1, 50)
-        m = torch.as_tensor(wl.m0.astype(np.float32), device="cuda")
         Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
-        dt = torch.full((1,), 1e-14, dtype=torch.float64, device="cuda")
-        p.run(m, Ha, tmg.TM_DP45, dt=dt, max_steps=1 << 40, max_attempts=20)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        p.run(m, Ha, tmg.TM_DP45, dt=dt, max_steps=1 << 40, max_attempts=attempts)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        rows.append({"n": nn, "tiles": wl.n, "assembly_ms": round(asm * 1e3, 2), "shape": shape,
-                     "stage_kernel_us": round(ms * 1e3, 2),
-                     "stage_kernel_gbs": round(nb / (ms * 1e-3) / 1e9, 1),
-                     "steps_per_s": round(attempts / el, 1)})
+
+        def steps_per_s(prob):
+            m = torch.as_tensor(wl.m0.astype(np.float32), device="cuda")
+            dt = torch.full((1,), 1e-14, dtype=torch.float64, device="cuda")
+            prob.run(m, Ha, tmg.TM_DP45, dt=dt, max_steps=1 << 40, max_attempts=20)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            prob.run(m, Ha, tmg.TM_DP45, dt=dt, max_steps=1 << 40, max_attempts=attempts)
+            torch.cuda.synchronize()
+            return attempts / (time.perf_counter() - t0)
+
+        row = {"n": nn, "tiles": wl.n, "assembly_ms": round(asm * 1e3, 2), "shape": shape,
+               "stage_kernel_us": round(ms * 1e3, 2),
+               "stage_kernel_gbs": round(nb / (ms * 1e-3) / 1e9, 1),
+               "steps_per_s": round(steps_per_s(p), 1)}
         p.close()
         T.close()
+        # the same film with the pair-symmetric operator (identical tiles)
+        Tp = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM6)
+        pp = tmg.Problem(ctx, geom, Tp, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+        msp, nbp = tmg.tm_profile_field(pp.handle, 1, 50)
+        row.update({"psym6_field_us": round(msp * 1e3, 2), "psym6_steps_per_s": round(steps_per_s(pp), 1)})
+        rows.append(row)
+        pp.close()
+        Tp.close()
         geom.close()
         ctx.close()
-    return {"workload": "SP4 film [20n,5n,1] tiles, n=1..9, one state, DP45, fp32 SYM6", "sizes": rows}
+    return {"workload": "SP4 film [20n,5n,1] tiles, n=1..9, one state, DP45, fp32 SYM6 (and PSYM6)", "sizes": rows}
 
 
 def threshold_section(tmg, W, torch, attempts=300, fracs=(0.2, 0.4, 0.7)):
