@@ -19,9 +19,11 @@
 // source order, so the structure is unique.
 //
 // Product.  k_field_bsr: one 256-thread workgroup per target tile streams
-// that row's column indices and component planes (coalesced) and gathers the
-// source states (12 bytes each, served from cache), then runs the same
-// fused epilogue as the dense kernel.
+// that row's column indices and component planes (coalesced, four blocks per
+// thread in flight) and gathers the source states (12 bytes each, served from
+// cache), then runs the same fused epilogue as the dense kernel.  (A layout
+// with per-segment masks of kept blocks and lane-owned columns, which reads
+// the states contiguously, measured slower: idle lanes on dropped columns.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -136,13 +138,18 @@ __global__ __launch_bounds__(256) void k_bsr_fill(const float* __restrict__ T, i
 }
 
 // Field kernel over a BSR6 operator: one workgroup per (target tile, state).
-template <Epi MODE>
+// Each thread takes four of the row's blocks per round (q, q + 256, ...):
+// their column indices and the 24 component loads are issued together, then
+// the four gathered source states.  UNI: uniform Ms, applied once to the sum
+// instead of per source tile.
+template <Epi MODE, bool UNI>
 __global__ __launch_bounds__(256) void k_field_bsr(DevProblem P, const int64_t* __restrict__ row_ptr,
                                                    const int32_t* __restrict__ col,
                                                    const float* __restrict__ vals, int64_t nnzb,
-                                                   const float* __restrict__ Ms, const float* X,
+                                                   const float* __restrict__ Ms, float ms_uni, const float* X,
                                                    int64_t sx, EpiArgs E) {
     constexpr int NW = 4;
+    constexpr int U = 4;
     constexpr bool STEPPING = MODE == Epi::STAGE || MODE == Epi::RK4_FINAL || MODE == Epi::DP_LAST;
     const int s = blockIdx.y;
     const int a = blockIdx.x;
@@ -156,16 +163,29 @@ __global__ __launch_bounds__(256) void k_field_bsr(DevProblem P, const int64_t* 
     if (!frozen) {
         const float* x = X + s * sx;
         float hx = 0.0f, hy = 0.0f, hz = 0.0f;
-        const int64_t q1 = row_ptr[a + 1];
-        for (int64_t q = row_ptr[a] + threadIdx.x; q < q1; q += 256) {
-            const int32_t b = col[q];
-            const float ms = Ms[b];
+        const int64_t q0 = row_ptr[a], q1 = row_ptr[a + 1];
+        auto block = [&](int64_t q, int32_t b) {
+            const float ms = UNI ? 1.0f : Ms[b];
             const float mx = x[3 * b] * ms, my = x[3 * b + 1] * ms, mz = x[3 * b + 2] * ms;
             const float xx = vals[q], xy = vals[nnzb + q], xz = vals[2 * nnzb + q];
             const float yy = vals[3 * nnzb + q], yz = vals[4 * nnzb + q], zz = vals[5 * nnzb + q];
             hx += xx * mx + xy * my + xz * mz;
             hy += xy * mx + yy * my + yz * mz;
             hz += xz * mx + yz * my + zz * mz;
+        };
+        int64_t q = q0 + threadIdx.x;
+        for (; q + (U - 1) * 256 < q1; q += U * 256) {
+            int32_t b[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) b[u] = col[q + u * 256];
+#pragma unroll
+            for (int u = 0; u < U; ++u) block(q + u * 256, b[u]);
+        }
+        for (; q < q1; q += 256) block(q, col[q]);
+        if (UNI) {
+            hx *= ms_uni;
+            hy *= ms_uni;
+            hz *= ms_uni;
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -257,11 +277,15 @@ tm_status count_nonzero(const Tensor* S, unsigned long long* hist, hipStream_t s
 }
 
 template <Epi MODE>
-void launch_bsr_t(const DevProblem& P, const Tensor* T, const float* Ms, int64_t B, const float* X,
-                  int64_t sx, const EpiArgs& e, hipStream_t s) {
+void launch_bsr_t(const DevProblem& P, const Tensor* T, const float* Ms, bool uni, float ms_uni, int64_t B,
+                  const float* X, int64_t sx, const EpiArgs& e, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(T->n), static_cast<unsigned>(B));
-    k_field_bsr<MODE><<<grid, 256, 0, s>>>(P, T->row_ptr, T->col, static_cast<const float*>(T->data), T->nnzb,
-                                           Ms, X, sx, e);
+    if (uni)
+        k_field_bsr<MODE, true><<<grid, 256, 0, s>>>(P, T->row_ptr, T->col, static_cast<const float*>(T->data),
+                                                     T->nnzb, Ms, ms_uni, X, sx, e);
+    else
+        k_field_bsr<MODE, false><<<grid, 256, 0, s>>>(P, T->row_ptr, T->col, static_cast<const float*>(T->data),
+                                                      T->nnzb, Ms, ms_uni, X, sx, e);
 }
 
 }  // namespace
@@ -275,13 +299,15 @@ tm_status launch_field_bsr(const Problem* p, Epi mode, int64_t B, const float* X
                static_cast<long long>(B));
     const DevProblem P = p->dev();
     const int64_t sx = 3 * p->np;
+    const bool uni = p->uniform_ms;
+    const float msu = static_cast<float>(p->ms_ref);
     switch (mode) {
-        case Epi::HD: launch_bsr_t<Epi::HD>(P, T, p->Ms, B, X, sx, e, s); break;
-        case Epi::HEFF: launch_bsr_t<Epi::HEFF>(P, T, p->Ms, B, X, sx, e, s); break;
-        case Epi::DMDT: launch_bsr_t<Epi::DMDT>(P, T, p->Ms, B, X, sx, e, s); break;
-        case Epi::STAGE: launch_bsr_t<Epi::STAGE>(P, T, p->Ms, B, X, sx, e, s); break;
-        case Epi::RK4_FINAL: launch_bsr_t<Epi::RK4_FINAL>(P, T, p->Ms, B, X, sx, e, s); break;
-        case Epi::DP_LAST: launch_bsr_t<Epi::DP_LAST>(P, T, p->Ms, B, X, sx, e, s); break;
+        case Epi::HD: launch_bsr_t<Epi::HD>(P, T, p->Ms, uni, msu, B, X, sx, e, s); break;
+        case Epi::HEFF: launch_bsr_t<Epi::HEFF>(P, T, p->Ms, uni, msu, B, X, sx, e, s); break;
+        case Epi::DMDT: launch_bsr_t<Epi::DMDT>(P, T, p->Ms, uni, msu, B, X, sx, e, s); break;
+        case Epi::STAGE: launch_bsr_t<Epi::STAGE>(P, T, p->Ms, uni, msu, B, X, sx, e, s); break;
+        case Epi::RK4_FINAL: launch_bsr_t<Epi::RK4_FINAL>(P, T, p->Ms, uni, msu, B, X, sx, e, s); break;
+        case Epi::DP_LAST: launch_bsr_t<Epi::DP_LAST>(P, T, p->Ms, uni, msu, B, X, sx, e, s); break;
     }
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
