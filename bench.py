@@ -502,7 +502,10 @@ def serving_section(tmg, W, torch, count=24, n_max=4000, max_steps=3000, slots=8
         key = (r.centers.shape[0], r.centers.tobytes())
         if key not in cache:
             g = tmg.Geometry(ctx, r.centers, r.sizes)
-            T = tmg.Tensor(ctx, g)
+            # the same operator layout the server picks: pair-symmetric for
+            # identical tiles
+            same = bool(np.all(r.sizes == r.sizes[0]))
+            T = tmg.Tensor(ctx, g, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM6 if same else tmg.TM_LAYOUT_SYM6)
             cache[key] = (g, T)
         g, T = cache[key]
         p = tmg.Problem(ctx, g, T, Ms, A, alpha)

@@ -115,9 +115,30 @@ struct tm_server {
 
 namespace {
 
-int64_t workspace_bytes(int64_t n, int64_t B) {
+// Meshes of identical tiles are served with the pair-symmetric operator
+// (about half the bytes streamed per step), others with the six planes.
+bool identical_tiles(const std::vector<double>& sizes) {
+    for (size_t i = 3; i < sizes.size(); i += 3)
+        if (sizes[i] != sizes[0] || sizes[i + 1] != sizes[1] || sizes[i + 2] != sizes[2]) return false;
+    return true;
+}
+
+int64_t operator_bytes(int64_t n, tm_layout layout) {
+    if (layout == TM_LAYOUT_PSYM6) {
+        const int64_t nt = (n + kPsTile - 1) / kPsTile;
+        return nt * (nt + 1) / 2 * (6 * kPsTile * kPsTile * 4 + 8);
+    }
+    return 6 * n * round_up(n, 4) * 4;
+}
+
+int64_t workspace_bytes(int64_t n, int64_t B, tm_layout layout) {
     const int64_t np = padded_tiles(n);
-    return 12 * B * 3 * np * 4 + B * 128 + 16 * B * n + 4096 + ((n + 255) / 256) * B * 32;
+    int64_t b = 12 * B * 3 * np * 4 + B * 128 + 16 * B * n + 4096 + ((n + 255) / 256) * B * 32;
+    if (layout == TM_LAYOUT_PSYM6) {
+        const int64_t nt = (n + kPsTile - 1) / kPsTile;
+        b += B * nt * nt * 3 * kPsTile * 4;
+    }
+    return b;
 }
 
 }  // namespace
@@ -173,15 +194,16 @@ bool tm_server::try_place(Req* r) {
         if (static_cast<int>(groups.size()) >= cfg.max_groups) return false;
         // bytes a new group needs: the operator unless cached, plus the slots
         bool cached = false;
-        int64_t tbytes = 6 * r->n * round_up(r->n, 4) * 4;
+        const tm_layout layout = identical_tiles(r->sizes) ? TM_LAYOUT_PSYM6 : TM_LAYOUT_SYM6;
+        const int64_t tbytes = operator_bytes(r->n, layout);
         {
             std::lock_guard<std::mutex> lk(ctx->mu);
             for (Tensor* T : ctx->cache)
-                if (T->hash == r->ghash && T->n == r->n && T->prec == TM_PREC_FP32 &&
-                    T->layout == TM_LAYOUT_SYM6 && T->centers == r->centers && T->sizes == r->sizes)
+                if (T->hash == r->ghash && T->n == r->n && T->prec == TM_PREC_FP32 && T->layout == layout &&
+                    T->centers == r->centers && T->sizes == r->sizes)
                     cached = true;
         }
-        const int64_t need = (cached ? 0 : tbytes) + workspace_bytes(r->n, B);
+        const int64_t need = (cached ? 0 : tbytes) + workspace_bytes(r->n, B, layout);
         if (used + need > budget) {
             if (groups.empty()) {  // nothing will ever free up: refuse
                 std::lock_guard<std::mutex> lk(mu);
@@ -204,8 +226,8 @@ bool tm_server::try_place(Req* r) {
                                     r->sizes.data(), &g->geom);
         int64_t hits0 = ctx->cache_hits;
         if (st == TM_OK)
-            st = tm_tensor_assemble(reinterpret_cast<tm_ctx*>(ctx), g->geom, TM_PREC_FP32,
-                                    TM_LAYOUT_SYM6, g->stream, &g->tensor);
+            st = tm_tensor_assemble(reinterpret_cast<tm_ctx*>(ctx), g->geom, TM_PREC_FP32, layout, g->stream,
+                                    &g->tensor);
         r->cache_hit = ctx->cache_hits > hits0 ? 1 : 0;
         tm_material mat{r->Ms.data(), r->A, r->Ku.empty() ? nullptr : r->Ku.data(),
                         r->easy.empty() ? nullptr : r->easy.data(), r->alpha, r->gamma0, r->ll_form};
