@@ -97,3 +97,15 @@ def test_init_without_gpu_fails_cleanly(tmg):
     st = tmg.load().tm_init(0, C.byref(out))
     assert st in (tmg.TM_EDEVICE, tmg.TM_EINVAL)
     assert tmg.last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; a request for more exits with a message
+    (before touching any device)."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
