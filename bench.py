@@ -103,14 +103,24 @@ def cpu_baseline(wl, nsteps):
     Ha = wl.Ha[0].astype(np.float32).astype(np.float64)
     k1 = P.rhs(y, Ha)
     dt, t = 1e-14, 0.0
+    cores = oracle.num_threads()
     t0 = time.perf_counter()
     for _ in range(nsteps):
         _, dt, t, _, _ = P.dp45_attempt(y, k1, Ha, dt, t)
     el = time.perf_counter() - t0
-    return {"value": nsteps / el, "unit": "steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+    # single thread, on a tenth of the sample
+    oracle.set_num_threads(1)
+    n1 = max(1, nsteps // 10)
+    t0 = time.perf_counter()
+    for _ in range(n1):
+        _, dt, t, _, _ = P.dp45_attempt(y, k1, Ha, dt, t)
+    el1 = time.perf_counter() - t0
+    oracle.set_num_threads(cores)
+    return {"value": nsteps / el, "unit": "steps/s", "cores": cores, "kind": "oracle",
             "sample": "%d attempted DP45 steps of the same film workload after one FP64 operator "
-                      "assembly (%.1f s, not included)" % (nsteps, t_asm),
-            "assembly_s": round(t_asm, 3)}
+                      "assembly (%.1f s, not included); single-thread rate from %d further steps"
+                      % (nsteps, t_asm, n1),
+            "single_thread_steps_per_s": round(n1 / el1, 2), "assembly_s": round(t_asm, 3)}
 
 
 def batched_section(tmg, W, torch, attempts=60, profile_iters=20):
@@ -165,7 +175,7 @@ def batched_section(tmg, W, torch, attempts=60, profile_iters=20):
     return out
 
 
-def large_section(tmg, W, torch, attempts=20, profile_iters=10):
+def large_section(tmg, W, torch, attempts=20, profile_iters=10, with_oracle=True):
     """The 20000-tile refined slab (edges 2.5-20 nm, 1000 x 250 x 20 nm): FP64
     operator assembly on the GPU, the stage kernel streaming a 9.6 GB SYM6
     operator (no cache can hold it: the HBM roofline proper), a few single-state
@@ -182,6 +192,16 @@ def large_section(tmg, W, torch, attempts=20, profile_iters=10):
     asm = time.perf_counter() - t0
     out["assembly_ms"] = round(asm * 1e3, 1)
     out["assembly_gpairs_s"] = round(n * n / asm / 1e9, 2)
+    if with_oracle:
+        import oracle
+
+        rows = np.arange(0, n, n // 64)[:64]
+        t0 = time.perf_counter()
+        oracle.demag_rows(wl.centers, wl.sizes, wl.Ms, wl.m0[0].astype(np.float64), rows)
+        el = time.perf_counter() - t0
+        out["oracle_tensor_gpairs_s"] = round(len(rows) * n / el / 1e9, 4)
+        out["oracle_sample"] = "%d target rows x %d sources evaluated on the fly (%d threads)" % (
+            len(rows), n, oracle.num_threads())
     p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
     shape, _ = tmg.tm_problem_tune(p.handle, 1, 3)
     out["stage_kernel_shape"] = shape
@@ -217,7 +237,7 @@ def large_section(tmg, W, torch, attempts=20, profile_iters=10):
     return out
 
 
-def cube_section(tmg, W, torch, reps=5):
+def cube_section(tmg, W, torch, reps=5, with_oracle=True):
     """The 8 x 8 x 8 grid of 5 nm cubes (N = 512), RK4 at dt = 1e-13 s for
     200 steps with the float32 SYM6 operator (3 MB, cache-resident): a
     launch- and latency-bound case."""
@@ -243,9 +263,21 @@ def cube_section(tmg, W, torch, reps=5):
     T.close()
     geom.close()
     ctx.close()
-    return {"workload": "8x8x8 cubes of 5 nm (N=512), alpha=0.5, RK4 dt=1e-13 s x %d steps, fp32 SYM6" % nsteps,
-            "steps_per_s": round(nsteps / best, 1), "us_per_step": round(best / nsteps * 1e6, 2),
-            "stage_kernel_us": round(ms * 1e3, 2)}
+    out = {"workload": "8x8x8 cubes of 5 nm (N=512), alpha=0.5, RK4 dt=1e-13 s x %d steps, fp32 SYM6" % nsteps,
+           "steps_per_s": round(nsteps / best, 1), "us_per_step": round(best / nsteps * 1e6, 2),
+           "stage_kernel_us": round(ms * 1e3, 2)}
+    if with_oracle:
+        import oracle
+
+        t0 = time.perf_counter()
+        P = oracle.Problem(wl.centers, wl.sizes, wl.Ms, wl.A, wl.alpha)
+        t_asm = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        P.rk4(wl.m0[0].astype(np.float32).astype(np.float64), [0, 0, 0], wl.extra["dt"], nsteps)
+        el = time.perf_counter() - t0
+        out["oracle"] = {"steps_per_s": round(nsteps / el, 1), "assembly_s": round(t_asm, 3),
+                         "cores": oracle.num_threads(), "sample": "the full run (assembly + %d RK4 steps)" % nsteps}
+    return out
 
 
 def sp4_sweep_section(tmg, W, torch, attempts=300):
@@ -648,9 +680,9 @@ def main():
         bat["vs_single_fp32_solve"] = round(best / rec["value"], 2)
         rec["batched"] = bat
     if not args.no_large:
-        rec["large"] = large_section(tmg, W, torch)
+        rec["large"] = large_section(tmg, W, torch, with_oracle=not args.no_cpu_baseline)
     if not args.no_cube:
-        rec["cube"] = cube_section(tmg, W, torch)
+        rec["cube"] = cube_section(tmg, W, torch, with_oracle=not args.no_cpu_baseline)
     if not args.no_sweep:
         rec["sp4_sweep"] = sp4_sweep_section(tmg, W, torch)
     if not args.no_threshold:

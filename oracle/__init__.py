@@ -54,6 +54,7 @@ def lib():
         L.orc_faces.argtypes = [i64, d, d, i64, C.POINTER(i64), C.POINTER(i64), d, d]
         L.orc_faces.restype = i64
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         P = C.POINTER(_Problem)
         L.orc_heff.argtypes = [P, d, d, d]
         L.orc_ll_rhs.argtypes = [P, d, d, d, d]
@@ -91,6 +92,11 @@ def _f64(x) -> np.ndarray:
 
 def _p(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's outer loops from now on (for timing)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def num_threads() -> int:

@@ -36,6 +36,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads the outer loops use from now on (timing runs only). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Analytical demagnetisation tensor of a uniformly magnetised cuboid        */
 /* (paper Sec. 3; the cuboid formula itself is only cited there, so it is    */
