@@ -535,8 +535,8 @@ def serving_section(tmg, W, torch, count=24, n_max=4000, max_steps=3000, slots=8
         if key not in cache:
             g = tmg.Geometry(ctx, r.centers, r.sizes)
             # the same operator layout the server picks: pair-symmetric for
-            # identical tiles
-            same = bool(np.all(r.sizes == r.sizes[0]))
+            # identical tiles above 1200 tiles
+            same = bool(np.all(r.sizes == r.sizes[0])) and r.centers.shape[0] > 1200
             T = tmg.Tensor(ctx, g, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM6 if same else tmg.TM_LAYOUT_SYM6)
             cache[key] = (g, T)
         g, T = cache[key]
