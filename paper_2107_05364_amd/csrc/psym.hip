@@ -38,6 +38,12 @@ constexpr int RG = 256 / TS;       // row groups of a workgroup (one column per 
 constexpr int RPT = TS / RG;       // rows per thread
 static_assert(TS * RG == 256 && RPT * RG == TS, "tile size must divide the workgroup");
 
+template <bool NTL>
+__device__ inline float ldt(const float* p) {
+    if constexpr (NTL) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // Index of tile pair (I, J), I <= J, in the pair table: the nt diagonal
 // pairs first, then the pairs I < J in row-major order.
 inline int64_t pair_index(int64_t I, int64_t J, int64_t nt) {
@@ -56,7 +62,7 @@ inline int64_t pair_index(int64_t I, int64_t J, int64_t nt) {
 // overlap it, and dispatched first (diagonal pairs lead the pair table) --
 // and subtract them from their own slot, so that minus the slot sum is the
 // whole effective field and the finish kernel has no dependent loads left.
-template <bool STEPPING, bool LOCALF>
+template <bool STEPPING, bool LOCALF, bool NTL>
 __global__ __launch_bounds__(256) void k_psym_tiles(DevProblem P, const float* __restrict__ tiles,
                                                     const int32_t* __restrict__ pairs, int64_t nt,
                                                     const float* __restrict__ Ms, const float* __restrict__ X,
@@ -94,8 +100,9 @@ __global__ __launch_bounds__(256) void k_psym_tiles(DevProblem P, const float* _
         const float msa = Ms[ag];
         const float xa0 = x[3 * ag] * msa, xa1 = x[3 * ag + 1] * msa, xa2 = x[3 * ag + 2] * msa;
         const int off = al * TS + b;
-        const float v0 = tile[off], v1 = tile[TB + off], v2 = tile[2 * TB + off];
-        const float v3 = tile[3 * TB + off], v4 = tile[4 * TB + off], v5 = tile[5 * TB + off];
+        const float v0 = ldt<NTL>(tile + off), v1 = ldt<NTL>(tile + TB + off), v2 = ldt<NTL>(tile + 2 * TB + off);
+        const float v3 = ldt<NTL>(tile + 3 * TB + off), v4 = ldt<NTL>(tile + 4 * TB + off),
+                    v5 = ldt<NTL>(tile + 5 * TB + off);
         rred[al][0][b] = v0 * xb0 + v1 * xb1 + v2 * xb2;
         rred[al][1][b] = v1 * xb0 + v3 * xb1 + v4 * xb2;
         rred[al][2][b] = v2 * xb0 + v4 * xb1 + v5 * xb2;
@@ -121,6 +128,20 @@ __global__ __launch_bounds__(256) void k_psym_tiles(DevProblem P, const float* _
             part[((s * nt + J) * nt + I) * (3 * TS) + t] = cs;
         }
     }
+}
+
+// Operators larger than the Infinity Cache are streamed with nontemporal
+// loads (each tile is read once per evaluation and cannot stay cached anyway).
+constexpr int64_t kPsymStreamBytes = 192ll << 20;
+
+template <bool STEPPING, bool LOCALF>
+inline void launch_tiles(dim3 grid, hipStream_t st, bool nt_loads, const DevProblem& P, const float* tiles,
+                         const int32_t* pairs, int64_t nt, const float* Ms, const float* X, int64_t sx,
+                         const double* h, const float* Ha, float* part) {
+    if (nt_loads)
+        k_psym_tiles<STEPPING, LOCALF, true><<<grid, 256, 0, st>>>(P, tiles, pairs, nt, Ms, X, sx, h, Ha, part);
+    else
+        k_psym_tiles<STEPPING, LOCALF, false><<<grid, 256, 0, st>>>(P, tiles, pairs, nt, Ms, X, sx, h, Ha, part);
 }
 
 // One workgroup per (target tile K, state): the nt slots of K are contiguous
@@ -190,8 +211,8 @@ void launch_psym_t(const DevProblem& P, const Tensor* T, const float* Ms, float*
     constexpr bool STEPPING = MODE == Epi::STAGE || MODE == Epi::RK4_FINAL || MODE == Epi::DP_LAST;
     constexpr bool LOCALF = MODE != Epi::HD;
     const dim3 g1(static_cast<unsigned>(T->npairs), static_cast<unsigned>(B));
-    k_psym_tiles<STEPPING, LOCALF><<<g1, 256, 0, s>>>(P, static_cast<const float*>(T->data), T->pairs, T->nt,
-                                                      Ms, X, sx, e.h, e.Ha, part);
+    launch_tiles<STEPPING, LOCALF>(g1, s, T->bytes > kPsymStreamBytes, P, static_cast<const float*>(T->data),
+                                   T->pairs, T->nt, Ms, X, sx, e.h, e.Ha, part);
     const dim3 g2(static_cast<unsigned>(T->nt), static_cast<unsigned>(B));
     k_psym_finish<MODE><<<g2, 256, 0, s>>>(P, part, T->nt, X, sx, e);
 }
@@ -207,8 +228,8 @@ tm_status launch_psym_tiles(const Problem* p, int64_t B, const float* X, const d
     TM_REQUIRE(T->layout == TM_LAYOUT_PSYM6 && w && w->part && w->B >= B, TM_EINVAL,
                "pair-symmetric tile pass: not prepared");
     const dim3 g1(static_cast<unsigned>(T->npairs), static_cast<unsigned>(B));
-    k_psym_tiles<true, true><<<g1, 256, 0, s>>>(p->dev(), static_cast<const float*>(T->data), T->pairs, T->nt,
-                                                p->Ms, X, 3 * p->np, h, Ha, w->part);
+    launch_tiles<true, true>(g1, s, T->bytes > kPsymStreamBytes, p->dev(), static_cast<const float*>(T->data),
+                             T->pairs, T->nt, p->Ms, X, 3 * p->np, h, Ha, w->part);
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
 }

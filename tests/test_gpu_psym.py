@@ -182,3 +182,19 @@ def test_psym_rejects_unlike_tiles(tmg, ctx):
     with pytest.raises(tmg.TilemagError):
         tmg.Tensor(ctx, g2, tmg.TM_PREC_FP64, tmg.TM_LAYOUT_PSYM6)
     close(g, g2)
+
+
+def test_psym_streamed_size_rows(tmg, ctx, orc):
+    """The SP4 film at [160, 40, 1] (N = 6400): the pair-symmetric operator
+    (494 MB) exceeds the Infinity Cache and is streamed with nontemporal
+    loads; sampled rows of H_d and H_eff against the oracle's rows."""
+    wl = W.thin_film(nx=160, ny=40)
+    g, T, p = _psym(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha)
+    assert T.nbytes > 192 * 2**20
+    m = wl.m0.astype(np.float32)
+    Hd = p.demag(device_state(m)).cpu().numpy()[0]
+    rows = np.array([0, 1, 31, 32, 33, 159, 160, 3199, 3200, 6367, 6398, 6399])
+    want = orc.demag_rows(wl.centers, wl.sizes, wl.Ms, m[0].astype(np.float64), rows)
+    e2, emax = rel_errors(Hd[rows], want)
+    assert e2 <= 1e-5 and emax <= 1e-5, (e2, emax)
+    close(g, T, p)
