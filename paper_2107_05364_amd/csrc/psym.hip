@@ -37,6 +37,8 @@ constexpr int TB = kPsTile * kPsTile;
 constexpr int RG = 256 / TS;       // row groups of a workgroup (one column per lane)
 constexpr int RPT = TS / RG;       // rows per thread
 static_assert(TS * RG == 256 && RPT * RG == TS, "tile size must divide the workgroup");
+constexpr int kFinishThreads = 1024;      // reduction + epilogue workgroup
+constexpr int FG = kFinishThreads / TS;   // slot groups of the reduction
 
 template <bool NTL>
 __device__ inline float ldt(const float* p) {
@@ -146,12 +148,12 @@ inline void launch_tiles(dim3 grid, hipStream_t st, bool nt_loads, const DevProb
 
 // One workgroup per (target tile K, state): the nt slots of K are contiguous
 // ([nt][TS][3] floats); thread (g, q) = (t / TS, t % TS) adds the slots
-// j = g, g + RG, ... of tile q (independent coalesced loads), then the RG
-// group sums are added in order g = 0 .. RG-1 and the first TS lanes run the
-// epilogue of their tile.
+// j = g, g + FG, ... of tile q (independent coalesced loads, four in flight),
+// then the FG group sums are added in order g = 0 .. FG-1 and the first TS
+// lanes run the epilogue of their tile.
 template <Epi MODE>
-__global__ __launch_bounds__(256) void k_psym_finish(DevProblem P, const float* __restrict__ part, int64_t nt,
-                                                     const float* X, int64_t sx, EpiArgs E) {
+__global__ __launch_bounds__(kFinishThreads) void k_psym_finish(DevProblem P, const float* __restrict__ part,
+                                                                int64_t nt, const float* X, int64_t sx, EpiArgs E) {
     constexpr bool STEPPING = MODE == Epi::STAGE || MODE == Epi::RK4_FINAL || MODE == Epi::DP_LAST;
     const int64_t K = blockIdx.x;
     const int s = blockIdx.y;
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(256) void k_psym_finish(DevProblem P, const float* 
     if constexpr (MODE == Epi::STAGE || MODE == Epi::RK4_FINAL) {
         if (frozen) return;
     }
-    __shared__ float gs[RG][TS][3];
+    __shared__ float gs[FG][TS][3];
     const int q = threadIdx.x % TS, grp = threadIdx.x / TS;
     // the epilogue's own inputs are loaded before the slots are summed
     const int64_t a = TS * K + lane;
@@ -171,8 +173,22 @@ __global__ __launch_bounds__(256) void k_psym_finish(DevProblem P, const float* 
     if (!frozen) {
         const float* src = part + (static_cast<int64_t>(s) * nt + K) * nt * (3 * TS) + 3 * q;
         float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-#pragma unroll 4
-        for (int64_t j = grp; j < nt; j += RG) {
+        // four slots per round, all loads issued before the adds
+        int64_t j = grp;
+        for (; j + 3 * FG < nt; j += 4 * FG) {
+            float v[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[u][c] = src[(j + u * FG) * (3 * TS) + c];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a0 += v[u][0];
+                a1 += v[u][1];
+                a2 += v[u][2];
+            }
+        }
+        for (; j < nt; j += FG) {
             const float* v = src + j * (3 * TS);
             a0 += v[0];
             a1 += v[1];
@@ -188,7 +204,7 @@ __global__ __launch_bounds__(256) void k_psym_finish(DevProblem P, const float* 
     if (mine) {
         float hx = 0.0f, hy = 0.0f, hz = 0.0f;
 #pragma unroll
-        for (int g2 = 0; g2 < RG; ++g2) {
+        for (int g2 = 0; g2 < FG; ++g2) {
             hx += gs[g2][lane][0];
             hy += gs[g2][lane][1];
             hz += gs[g2][lane][2];
@@ -214,7 +230,7 @@ void launch_psym_t(const DevProblem& P, const Tensor* T, const float* Ms, float*
     launch_tiles<STEPPING, LOCALF>(g1, s, T->bytes > kPsymStreamBytes, P, static_cast<const float*>(T->data),
                                    T->pairs, T->nt, Ms, X, sx, e.h, e.Ha, part);
     const dim3 g2(static_cast<unsigned>(T->nt), static_cast<unsigned>(B));
-    k_psym_finish<MODE><<<g2, 256, 0, s>>>(P, part, T->nt, X, sx, e);
+    k_psym_finish<MODE><<<g2, kFinishThreads, 0, s>>>(P, part, T->nt, X, sx, e);
 }
 
 }  // namespace
