@@ -222,6 +222,18 @@ tm_status tm_dmdt(tm_problem* p, int64_t B, const float* m, const float* Ha, flo
 tm_status tm_energy(tm_problem* p, int64_t B, const float* m, const float* Ha, double* E,
                     hipStream_t stream);
 
+/* Diagnostics per state, accumulated in float64 in a fixed order:
+ *   D[b][0..3] the energy terms as tm_energy [J];
+ *   D[b][4..6] the mean magnetisation <m> = sum_a V_a Ms_a m_a / sum_a V_a Ms_a
+ *              (the normalised total moment; the volume average when Ms is
+ *              uniform);
+ *   D[b][7]    max_a |dm/dt|_a [1/s] (paper Sec. 2.1: zero at equilibrium);
+ *   D[b][8]    1 if any component of m, H_d or dm/dt of the state is not
+ *              finite, else 0.
+ *   D : device [B][9] float64.  Stream-ordered. */
+tm_status tm_diagnostics(tm_problem* p, int64_t B, const float* m, const float* Ha, double* D,
+                         hipStream_t stream);
+
 /* Integration controls. */
 typedef struct {
     int64_t max_steps;     /* accepted steps per state (RK4: steps) */

@@ -262,6 +262,24 @@ class Problem:
                 break
         return y, t, dt, att
 
+    def diagnostics(self, m, Ha=(0.0, 0.0, 0.0)) -> np.ndarray:
+        """[E_demag, E_ex, E_anis, E_Z, <m>_x, <m>_y, <m>_z, max_a |dm/dt|_a,
+        non-finite flag]: the energy terms, the moment-weighted mean
+        magnetisation sum V Ms m / sum V Ms, and the largest LL right-hand
+        side (Sec. 2.1-2.3)."""
+        m = _f64(m)
+        bad = not np.isfinite(m).all()
+        out = np.zeros(9)
+        with np.errstate(all="ignore"):
+            out[:4] = self.energy(m, Ha)
+            w = self.vol * self.Ms
+            out[4:7] = (w[:, None] * m).sum(axis=0) / w.sum()
+            k = self.rhs(m, Ha)
+            bad = bad or not np.isfinite(k).all()
+            out[7] = 0.0 if bad else np.sqrt((k * k).sum(axis=1)).max()
+        out[8] = 1.0 if bad else 0.0
+        return out
+
     def energy(self, m, Ha=(0.0, 0.0, 0.0)) -> np.ndarray:
         """[demag, exchange, anisotropy, Zeeman] energies in J."""
         m, Ha = _f64(m), _f64(Ha)

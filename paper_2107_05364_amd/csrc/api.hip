@@ -69,7 +69,7 @@ Workspace::~Workspace() {
     float* fl[] = {y, ya, yb, y5, k[0], k[1], k[2], k[3], k[4], k[5], k[6], Ha, hd, part};
     for (float* p : fl)
         if (p) (void)hipFree(p);
-    void* vp[] = {xh, xl, t, h, dt, errp, dmxp, steps, rejected, flags, acc, params, esum};
+    void* vp[] = {xh, xl, t, h, dt, errp, dmxp, steps, rejected, flags, acc, params, esum, diag};
     for (void* p : vp)
         if (p) (void)hipFree(p);
     if (host_params) (void)hipHostFree(host_params);
@@ -610,8 +610,9 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
     }
     const bool psym = T->layout == TM_LAYOUT_PSYM6;
     if (psym) pbytes = psym_partial_floats(T, bcap) * 4;
+    const int64_t dbytes = bcap * (nblk * 6 + 4) * 8;  // diagnostics partials + energies
     int64_t bytes = 12 * sb + bcap * 12 + bcap * (8 * 7 + 8 * 2 + 4 * 2) + 16 * bcap * n + 64 +
-                    RP_COUNT * 8 + nblk * bcap * 32 + xbytes + pbytes;
+                    RP_COUNT * 8 + nblk * bcap * 32 + xbytes + pbytes + dbytes;
     {
         std::lock_guard<std::mutex> lk(p->ctx->mu);
         const int64_t old = p->ws ? p->ws->bytes : 0;
@@ -654,6 +655,7 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->acc), bcap * 4);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->params), RP_COUNT * 8);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->esum), nblk * bcap * 32);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->diag), dbytes);
     w->esum_blocks = nblk * bcap;
     if (dense && xbytes && e == hipSuccess) {
         const int64_t half = T->prec == TM_PREC_FP32 ? xbytes : xbytes / 2;
@@ -727,6 +729,33 @@ tm_status tm_energy(tm_problem* p, int64_t B, const float* m, const float* Ha, d
     st = launch_field(p, Epi::HD, B, w->ya, e, s);
     if (st != TM_OK) return st;
     return launch_energy(p, B, w->ya, Ha, w->hd, E, s);
+}
+
+tm_status tm_diagnostics(tm_problem* p, int64_t B, const float* m, const float* Ha, double* D,
+                         hipStream_t s) {
+    TM_REQUIRE(p && m && D && B >= 1, TM_EINVAL, "tm_diagnostics: bad arguments");
+    TM_TRY_HIP(hipSetDevice(p->ctx->device));
+    tm_status st = ensure_workspace(p, B);
+    if (st != TM_OK) return st;
+    Workspace* w = p->ws.get();
+    st = launch_pack(m, B, p->n, p->np, w->ya, s);
+    if (st != TM_OK) return st;
+    EpiArgs e{};
+    e.out = w->hd;
+    e.out_stride = 3 * p->np;
+    st = launch_field(p, Epi::HD, B, w->ya, e, s);
+    if (st != TM_OK) return st;
+    const int64_t nblk = (p->n + 255) / 256;
+    double* E4 = w->diag + B * nblk * 6;
+    st = launch_energy(p, B, w->ya, Ha, w->hd, E4, s);
+    if (st != TM_OK) return st;
+    EpiArgs k{};
+    k.out = w->k[6];
+    k.out_stride = 3 * p->np;
+    k.Ha = Ha;
+    st = launch_field(p, Epi::DMDT, B, w->ya, k, s);
+    if (st != TM_OK) return st;
+    return launch_diagnostics(p, B, w->ya, w->hd, w->k[6], E4, D, s);
 }
 
 }  // extern "C"

@@ -178,6 +178,7 @@ struct Workspace {
     int32_t* acc = nullptr;
     double* params = nullptr; // RunParams on device
     double* esum = nullptr;   // energy partial sums
+    double* diag = nullptr;   // diagnostics: [B][nblk][6] partials, then [B][4] energies
     int64_t esum_blocks = 0;
     // pinned host mirrors (run parameters, polling)
     double* host_params = nullptr;
@@ -274,6 +275,10 @@ tm_status launch_commit(const Problem* p, Workspace* w, int64_t B, hipStream_t s
 int64_t last_stage_blocks(const Problem* p);
 tm_status launch_energy(const Problem* p, int64_t B, const float* X, const float* Ha,
                         const float* Hd, double* E, hipStream_t s);
+// Mean moment, max |dm/dt| and non-finite flag of each state; D [B][9] gets
+// the energies E4 [B][4] in 0..3 (fieldstep.hip).
+tm_status launch_diagnostics(const Problem* p, int64_t B, const float* X, const float* Hd,
+                             const float* dmdt, const double* E4, double* D, hipStream_t s);
 
 // Integrator pieces shared with the server (integrate.hip).
 tm_status enqueue_attempts(const Problem* p, Workspace* w, int integ, int64_t B, int renorm,

@@ -366,7 +366,78 @@ __global__ void k_energy_final(int64_t B, int64_t nblk, const double* __restrict
     E[i] = v;
 }
 
+// Diagnostics partials per block of 256 tiles and state, in float64:
+// sum V Ms m (3), sum V Ms, max |dm/dt|, count of non-finite values.
+__global__ __launch_bounds__(256) void k_diag_part(int32_t n, int64_t np, const float* __restrict__ X,
+                                                   const float* __restrict__ Hd, const float* __restrict__ K,
+                                                   const double* __restrict__ vms, double* __restrict__ part) {
+    const int s = blockIdx.y;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (a < n) {
+        const int64_t o = static_cast<int64_t>(s) * 3 * np + 3 * a;
+        const double w = vms[a];
+        bool ok = true;
+        double k2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const float m = X[o + c], h = Hd[o + c], k = K[o + c];
+            ok = ok && isfinite(m) && isfinite(h) && isfinite(k);
+            v[c] = w * m;
+            k2 += static_cast<double>(k) * k;
+        }
+        v[3] = w;
+        v[4] = ok ? sqrt(k2) : 0.0;
+        v[5] = ok ? 0.0 : 1.0;
+    }
+    __shared__ double red[6][256];
+    for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+            red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + st]);
+            red[5][threadIdx.x] += red[5][threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[(static_cast<int64_t>(s) * gridDim.x + blockIdx.x) * 6 + threadIdx.x] =
+        red[threadIdx.x][0];
+}
+
+__global__ void k_diag_final(int64_t B, int64_t nblk, const double* __restrict__ part,
+                             const double* __restrict__ E4, double* __restrict__ D) {
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= B) return;
+    double m0 = 0, m1 = 0, m2 = 0, w = 0, dm = 0, bad = 0;
+    for (int64_t b = 0; b < nblk; ++b) {
+        const double* q = part + (s * nblk + b) * 6;
+        m0 += q[0]; m1 += q[1]; m2 += q[2]; w += q[3];
+        dm = fmax(dm, q[4]);
+        bad += q[5];
+    }
+    double* d = D + s * 9;
+    for (int c = 0; c < 4; ++c) d[c] = E4[s * 4 + c];
+    d[4] = m0 / w;
+    d[5] = m1 / w;
+    d[6] = m2 / w;
+    d[7] = dm;
+    d[8] = bad > 0.0 ? 1.0 : 0.0;
+}
+
 }  // namespace
+
+tm_status launch_diagnostics(const Problem* p, int64_t B, const float* X, const float* Hd,
+                             const float* dmdt, const double* E4, double* D, hipStream_t s) {
+    Workspace* w = p->ws.get();
+    const int64_t nblk = (p->n + 255) / 256;
+    TM_REQUIRE(w && w->diag && w->B >= B, TM_EINVAL, "diagnostics workspace missing");
+    k_diag_part<<<dim3(static_cast<unsigned>(nblk), static_cast<unsigned>(B)), 256, 0, s>>>(
+        static_cast<int32_t>(p->n), p->np, X, Hd, dmdt, p->e_w, w->diag);
+    TM_TRY_HIP(hipGetLastError());
+    k_diag_final<<<static_cast<unsigned>((B + 255) / 256), 256, 0, s>>>(B, nblk, w->diag, E4, D);
+    TM_TRY_HIP(hipGetLastError());
+    return TM_OK;
+}
 
 DevProblem Problem::dev() const {
     DevProblem d;

@@ -35,6 +35,7 @@ EXPORTS = [
     "tm_tensor_assemble", "tm_tensor_threshold", "tm_tensor_sparse_info", "tm_tensor_sparse_get",
     "tm_tensor_get", "tm_tensor_rows", "tm_tensor_bytes", "tm_tensor_release",
     "tm_problem_create", "tm_problem_destroy", "tm_demag", "tm_heff", "tm_dmdt", "tm_energy",
+    "tm_diagnostics",
     "tm_run", "tm_profile_field", "tm_profile_field_mode", "tm_num_shapes", "tm_shape_info",
     "tm_problem_shape", "tm_problem_set_shape",
     "tm_problem_tune", "tm_server_create", "tm_server_submit", "tm_server_poll", "tm_server_destroy",
@@ -130,6 +131,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "tm_heff": (i32, [vp, i64, vp, vp, vp, vp]),
         "tm_dmdt": (i32, [vp, i64, vp, vp, vp, vp]),
         "tm_energy": (i32, [vp, i64, vp, vp, vp, vp]),
+        "tm_diagnostics": (i32, [vp, i64, vp, vp, vp, vp]),
         "tm_run": (i32, [vp, i32, i64, vp, vp, vp, vp, vp, P(tm_run_cfg), P(tm_run_stats), vp]),
         "tm_profile_field": (i32, [vp, i64, i32, vp, P(d), P(i64)]),
         "tm_profile_field_mode": (i32, [vp, i64, i32, i32, vp, P(d), P(i64)]),
@@ -374,6 +376,16 @@ def tm_energy(p, n, m, Ha, E) -> None:
                             _dev(E, torch.float64, "E"), _stream()))
 
 
+def tm_diagnostics(p, n, m, Ha, D) -> None:
+    import torch
+
+    B = _batch(m, n)
+    _shape(Ha, (B, 3), "Ha")
+    _shape(D, (B, 9), "D")
+    _check(load().tm_diagnostics(p, B, _dev(m, torch.float32, "m"), _dev(Ha, torch.float32, "Ha"),
+                                 _dev(D, torch.float64, "D"), _stream()))
+
+
 def tm_run(p, n, integ, m, Ha, t, dt, steps_out, cfg: tm_run_cfg, check=True) -> tm_run_stats:
     import torch
 
@@ -556,6 +568,14 @@ class Problem:
         E = torch.empty((m.shape[0], 4), dtype=torch.float64, device=m.device)
         tm_energy(self.handle, self.n, m, Ha, E)
         return E
+
+    def diagnostics(self, m, Ha=None):
+        """[B, 9] float64: energy terms, <m>, max |dm/dt|, non-finite flag."""
+        import torch
+
+        D = torch.empty((m.shape[0], 9), dtype=torch.float64, device=m.device)
+        tm_diagnostics(self.handle, self.n, m, Ha, D)
+        return D
 
     def run(self, m, Ha=None, integ=TM_DP45, dt=1e-14, t=None, max_steps=1, max_attempts=0,
             atol=1e-6, rtol=1e-6, t_end=0.0, dt_min=0.0, dmdt_stop=0.0, renorm=True,

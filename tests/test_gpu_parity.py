@@ -384,3 +384,34 @@ def test_errors_are_reported(tmg, ctx):
     with pytest.raises(tmg.TilemagError):
         tmg.Tensor(ctx, g, tmg.TM_PREC_BF16X3, tmg.TM_LAYOUT_SYM6)
     close(g)
+
+
+@pytest.mark.parametrize("layout", ["sym6", "psym6", "dense9"])
+def test_diagnostics_vs_oracle(tmg, ctx, orc, layout):
+    """tm_diagnostics against the oracle: energy terms (relative 1e-5),
+    moment-weighted <m> (1e-6), max |dm/dt| (relative 1e-5), and a state
+    holding a NaN flagged alone."""
+    import torch
+
+    c, s = W.grid(9, 5, 2, 5e-9, 4e-9, 3e-9)
+    n = c.shape[0]
+    # pair symmetry needs identical tiles and a uniform Ms; the other layouts
+    # get per-tile Ms to exercise the moment weights
+    Ms = 8.0e5 if layout == "psym6" else np.linspace(6e5, 9e5, n)
+    store, lay = {"sym6": (tmg.TM_PREC_FP32, tmg.TM_LAYOUT_SYM6), "psym6": (tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM6),
+                  "dense9": (tmg.TM_PREC_FP32, tmg.TM_LAYOUT_DENSE9)}[layout]
+    g, T, p = build(tmg, ctx, c, s, Ms=Ms, alpha=0.3, store=store, layout=lay, Ku=2e4,
+                    easy=W.random_unit_vectors(9, n))
+    m = np.stack([W.random_unit_vectors(70 + k, n) for k in range(3)]).astype(np.float32)
+    m[2, 5, 1] = np.nan
+    Ha = np.array([[1e4, 2e4, -5e3], [0.0, 0.0, 3e4], [1e4, 0, 0]], np.float32)
+    D = p.diagnostics(device_state(m), torch.as_tensor(Ha, device="cuda")).cpu().numpy()
+    P = orc.Problem(c, s, Ms, 1.3e-11, 0.3, Ku=2e4, easy=W.random_unit_vectors(9, n))
+    for k in range(2):
+        want = P.diagnostics(m[k].astype(np.float64), Ha[k].astype(np.float64))
+        np.testing.assert_allclose(D[k, :4], want[:4], rtol=1e-5, atol=1e-12 * np.abs(want[:4]).max())
+        np.testing.assert_allclose(D[k, 4:7], want[4:7], rtol=0, atol=1e-6)
+        assert abs(D[k, 7] - want[7]) <= 1e-5 * want[7]
+        assert D[k, 8] == 0.0
+    assert D[2, 8] == 1.0
+    close(g, T, p)

@@ -200,3 +200,29 @@ def test_oracle_regression_fixture():
             np.testing.assert_allclose(got[key][b], want[key][b], rtol=1e-13, atol=1e-17)
     for key in ("demag_first_tiles", "energy", "rk4_10_steps_first_tiles"):
         np.testing.assert_allclose(got[key], want[key], rtol=1e-12, atol=1e-30)
+
+
+def test_diagnostics_definitions(orc):
+    """Mean magnetisation of a uniform state is that state; weights are the
+    tile moments V Ms; max |dm/dt| is zero for a single tile magnetised along
+    its field and positive otherwise; a NaN is flagged."""
+    c, s = W.grid(3, 2, 2, 5e-9, 4e-9, 3e-9)
+    n = c.shape[0]
+    Ms = np.linspace(6e5, 9e5, n)
+    P = orc.Problem(c, s, Ms, 1.3e-11, 0.5)
+    u = np.array([0.28, -0.48, 0.83])
+    u /= np.linalg.norm(u)
+    D = P.diagnostics(np.tile(u, (n, 1)))
+    np.testing.assert_allclose(D[4:7], u, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(D[:4], P.energy(np.tile(u, (n, 1))), rtol=1e-15)
+    m = W.random_unit_vectors(4, n)
+    D = P.diagnostics(m)
+    w = P.vol * Ms
+    np.testing.assert_allclose(D[4:7], (w[:, None] * m).sum(0) / w.sum(), rtol=1e-14)
+    assert D[7] > 0 and D[8] == 0
+    P1 = orc.Problem(np.zeros((1, 3)), np.full((1, 3), 5e-9), 8e5, 1.3e-11, 0.3)
+    mm = np.array([[0.0, 0.6, 0.8]])
+    assert P1.diagnostics(mm, 5e4 * mm[0])[7] < 1e-6
+    bad = m.copy()
+    bad[3, 1] = np.nan
+    assert P.diagnostics(bad)[8] == 1.0
