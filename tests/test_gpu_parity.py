@@ -415,3 +415,39 @@ def test_diagnostics_vs_oracle(tmg, ctx, orc, layout):
         assert D[k, 8] == 0.0
     assert D[2, 8] == 1.0
     close(g, T, p)
+
+
+def test_step_underflow_fails_the_state(tmg, ctx):
+    """A tolerance the float32 state cannot meet drives the proposed step
+    below dt_min: the state stops with TM_ESTEP (forced from the host; every
+    kernel still completes)."""
+    import torch
+
+    wl = W.thin_film(nx=40, ny=10)
+    g, T, p = build(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha)
+    md = device_state(wl.m0)
+    Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
+    t, dt, steps, st = p.run(md, Ha, tmg.TM_DP45, dt=1e-14, max_steps=1000, atol=1e-13, rtol=1e-13,
+                             dt_min=1e-15, check=False)
+    assert st.status == tmg.TM_ESTEP and st.states_failed == 1
+    assert torch.isfinite(md).all()
+    close(g, T, p)
+
+
+def test_context_budget_refuses_operator(tmg):
+    """Admission by bytes at the context level: an operator larger than the
+    budget is refused with TM_ENOMEM, and admitted once the budget allows."""
+    c, s = W.grid(30, 20, 1, 5e-9, 5e-9, 3e-9)
+    ctx2 = tmg.Context(0)
+    try:
+        g = tmg.Geometry(ctx2, c, s)
+        ctx2.set_memory_budget(1 << 20)  # 1 MiB: the 600-tile operator needs 8.6 MB
+        with pytest.raises(tmg.TilemagError) as ei:
+            tmg.Tensor(ctx2, g)
+        assert ei.value.status == tmg.TM_ENOMEM
+        ctx2.set_memory_budget(1 << 30)
+        T = tmg.Tensor(ctx2, g)
+        assert T.nbytes == 24 * 600 * 600
+        close(g, T)
+    finally:
+        ctx2.close()
