@@ -39,7 +39,15 @@ typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 constexpr int kRowsPerBlock = 128;  // 4 waves x 2 tiles x 16 rows
-constexpr int kKC = 128;            // K elements per chunk (X double-buffered in LDS)
+constexpr int kKC = 128;            // largest K chunk (X double-buffered in LDS); ld is a multiple
+
+// K chunk per (precision, state tiles), measured on the film operator
+// (7680 x 7680): the split forms at 128 states and FP32 at 32-64 states run
+// faster with 64-element chunks (half the registers and LDS: two workgroups
+// per CU), the rest with 128.
+constexpr int chunk_for(int prec, int nst) {
+    return (prec != 0 && nst == 8) || (prec == 0 && (nst == 2 || nst == 4)) ? 64 : 128;
+}
 
 struct GemmArgs {
     int64_t ld;         // K extent (= 3 np) and operator row stride
@@ -51,7 +59,7 @@ struct GemmArgs {
     const void* Xlo;
     float* part;        // [splits][bpad][rows]
     int64_t rows;       // padded operator rows (multiple of 128)
-    int64_t kper;       // K elements per split (multiple of kKC)
+    int64_t kper;       // K elements per split (multiple of the chunk)
 };
 
 template <int PREC>
@@ -63,28 +71,28 @@ struct Elt<1> { using T = __bf16; static constexpr int kPerLane = 8; };
 template <>
 struct Elt<2> { using T = _Float16; static constexpr int kPerLane = 8; };
 
-// LDS row of one state's chunk: kKC elements + 16 bytes of padding
-template <int PREC>
-constexpr int lds_row_bytes() { return kKC * static_cast<int>(sizeof(typename Elt<PREC>::T)) + 16; }
+// LDS row of one state's chunk: KC elements + 16 bytes of padding
+template <int PREC, int KC>
+constexpr int lds_row_bytes() { return KC * static_cast<int>(sizeof(typename Elt<PREC>::T)) + 16; }
 
-// Software pipeline per K chunk c (kKC = 128): the operator rows and the X
+// Software pipeline per K chunk c (KC = 64 or 128): the operator rows and the X
 // tile of chunk c+1 are loaded into registers while the MFMAs of chunk c run
 // from LDS buffer c&1; the X tile then goes to buffer (c+1)&1, which no wave
 // reads any more (all passed the barrier after chunk c-1).  One barrier per
 // chunk.  A chunk carries enough MFMA work (split: 192 per wave) to cover
 // the latency of the next chunk's loads, and MFMAs are issued across
 // independent accumulators so that none waits for its predecessor.
-template <int PREC, int NST>
+template <int PREC, int NST, int KC>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
     using T = typename Elt<PREC>::T;
     constexpr bool SPLIT = PREC != 0;
-    constexpr int RB = lds_row_bytes<PREC>();
+    constexpr int RB = lds_row_bytes<PREC, KC>();
     constexpr int NS = NST * 16;
-    constexpr int CHUNK16 = kKC * static_cast<int>(sizeof(T)) / 16;  // 16-byte pieces per state row
+    constexpr int CHUNK16 = KC * static_cast<int>(sizeof(T)) / 16;  // 16-byte pieces per state row
     constexpr int XPIECES = NS * CHUNK16;
     constexpr int XPT = (XPIECES + 255) / 256;  // pieces per thread and array
     constexpr int BUF = NS * RB * (SPLIT ? 2 : 1);
-    constexpr int NSUB = PREC == 0 ? kKC / 16 : kKC / 32;
+    constexpr int NSUB = PREC == 0 ? KC / 16 : KC / 32;
     using AV = typename std::conditional<PREC == 0, float4,
                                          typename std::conditional<PREC == 1, v8bf, v8h>::type>::type;
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
@@ -94,7 +102,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
     const int64_t rowbase = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock + wave * 32;
     const int64_t kb = static_cast<int64_t>(blockIdx.y) * G.kper;
     const int64_t ke = min(kb + G.kper, G.ld);
-    const int nch = static_cast<int>((ke - kb) / kKC);
+    const int nch = static_cast<int>((ke - kb) / KC);
 
     const T* Ah = static_cast<const T*>(G.Ahi);
     const T* Al = static_cast<const T*>(G.Alo);
@@ -217,7 +225,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
         __syncthreads();
         for (int c = 0; c < nch; ++c) {
             const bool more = c + 1 < nch;
-            const int64_t k1 = kb + static_cast<int64_t>(c + 1) * kKC;
+            const int64_t k1 = kb + static_cast<int64_t>(c + 1) * KC;
             if (more) {
                 load_x(k1);
                 load_a_next(k1);
@@ -309,7 +317,8 @@ __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __res
 
 template <int PREC, int NST>
 tm_status launch_gemm_t(const GemmArgs& G, int64_t rowblocks, int64_t splits, hipStream_t s) {
-    k_gemm<PREC, NST><<<dim3(static_cast<unsigned>(rowblocks), static_cast<unsigned>(splits)), 256, 0, s>>>(G);
+    k_gemm<PREC, NST, chunk_for(PREC, NST)>
+        <<<dim3(static_cast<unsigned>(rowblocks), static_cast<unsigned>(splits)), 256, 0, s>>>(G);
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
 }
@@ -382,10 +391,10 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     G.part = w->part;
     G.rows = T->rows;
     const int64_t splits = w->part_splits;
-    G.kper = round_up((ld + splits - 1) / splits, kKC);
+    const int nst = gemm_state_tiles(B);
+    G.kper = round_up((ld + splits - 1) / splits, chunk_for(prec, nst));
     const int64_t used_splits = (ld + G.kper - 1) / G.kper;
     const int64_t rowblocks = T->rows / kRowsPerBlock;
-    const int nst = gemm_state_tiles(B);
     tm_status st = prec == 0   ? launch_gemm_p<0>(nst, G, rowblocks, used_splits, s)
                    : prec == 1 ? launch_gemm_p<1>(nst, G, rowblocks, used_splits, s)
                                : launch_gemm_p<2>(nst, G, rowblocks, used_splits, s);
