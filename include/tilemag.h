@@ -61,11 +61,13 @@ typedef enum {
 /* Layout of the stored operator. */
 typedef enum {
     TM_LAYOUT_SYM6 = 0,   /* 6 planes [6][N][ldN] of (xx,xy,xz,yy,yz,zz), each 3x3 block symmetric */
-    TM_LAYOUT_DENSE9 = 1, /* row-major [3N][ld3N] dense operator (MFMA GEMM operand) */
+    TM_LAYOUT_DENSE9 = 1, /* dense [3N][ld3N] operator, the MFMA GEMM operand: FP64 row-major;
+                             FP32 and the split forms in blocks of 128 rows x 64 columns
+                             ordered as the product loads them (read back row-major) */
     TM_LAYOUT_BSR6 = 2,   /* thresholded operator: block-sparse rows of 6-component blocks
                              (made by tm_tensor_threshold only) */
     TM_LAYOUT_PSYM6 = 3   /* pair-symmetric operator of a mesh of identical tiles: only the
-                             upper triangle of 64x64-block tiles, [pairs][6][64][64], since
+                             upper triangle of 32x32-block tiles, [pairs][6][32][32], since
                              N^{ab} = N^{ba} there (about half the SYM6 bytes) */
 } tm_layout;
 

@@ -319,41 +319,16 @@ tm_status tm_tensor_get(const tm_tensor* T, int64_t a, int64_t b, double out9[9]
         std::memcpy(out9, m, sizeof(m));
         return TM_OK;
     }
-    for (int i = 0; i < 3; ++i) {
-        const int64_t off = (3 * a + i) * T->ld + 3 * b;
-        if (T->prec == TM_PREC_FP64) {
-            TM_TRY_HIP(hipMemcpy(out9 + 3 * i, static_cast<const double*>(T->data) + off, 24,
-                                 hipMemcpyDeviceToHost));
-        } else if (T->prec == TM_PREC_FP32) {
-            float f[3];
-            TM_TRY_HIP(hipMemcpy(f, static_cast<const float*>(T->data) + off, 12, hipMemcpyDeviceToHost));
-            for (int j = 0; j < 3; ++j) out9[3 * i + j] = f[j];
-        } else {
-            uint16_t hi[3], lo[3];
-            TM_TRY_HIP(hipMemcpy(hi, static_cast<const uint16_t*>(T->data) + off, 6, hipMemcpyDeviceToHost));
-            TM_TRY_HIP(hipMemcpy(lo, static_cast<const uint16_t*>(T->lo) + off, 6, hipMemcpyDeviceToHost));
-            float rs = 1.0f;
-            if (T->prec == TM_PREC_FP16X3)
-                TM_TRY_HIP(hipMemcpy(&rs, T->rscale + 3 * a + i, 4, hipMemcpyDeviceToHost));
-            for (int j = 0; j < 3; ++j) {
-                double vh, vl;
-                if (T->prec == TM_PREC_BF16X3) {
-                    uint32_t bh = static_cast<uint32_t>(hi[j]) << 16, bl = static_cast<uint32_t>(lo[j]) << 16;
-                    float fh, fl;
-                    std::memcpy(&fh, &bh, 4);
-                    std::memcpy(&fl, &bl, 4);
-                    vh = fh; vl = fl;
-                } else {
-                    __half hh, hl;
-                    std::memcpy(&hh, &hi[j], 2);
-                    std::memcpy(&hl, &lo[j], 2);
-                    vh = __half2float(hh);
-                    vl = __half2float(hl);
-                }
-                out9[3 * i + j] = (vh + vl) * rs;
-            }
-        }
+    if (T->prec == TM_PREC_FP64) {  // row-major
+        for (int i = 0; i < 3; ++i)
+            TM_TRY_HIP(hipMemcpy(out9 + 3 * i, static_cast<const double*>(T->data) + (3 * a + i) * T->ld + 3 * b,
+                                 24, hipMemcpyDeviceToHost));
+        return TM_OK;
     }
+    std::vector<double> rows(3 * T->n * 3);
+    tm_status st = tm_tensor_rows(T, a, 1, rows.data());
+    if (st != TM_OK) return st;
+    std::memcpy(out9, rows.data() + b * 9, 9 * sizeof(double));
     return TM_OK;
 }
 
@@ -408,8 +383,13 @@ tm_status tm_tensor_rows(const tm_tensor* T, int64_t a0, int64_t count, double* 
     if (T->prec == TM_PREC_FP64 || T->prec == TM_PREC_FP32) {
         const size_t esz = T->prec == TM_PREC_FP64 ? 8 : 4;
         std::vector<unsigned char> buf(nrow * T->ld * esz);
-        TM_TRY_HIP(hipMemcpy(buf.data(), static_cast<const unsigned char*>(T->data) + r0 * T->ld * esz,
-                             buf.size(), hipMemcpyDeviceToHost));
+        if (T->prec == TM_PREC_FP64) {
+            TM_TRY_HIP(hipMemcpy(buf.data(), static_cast<const unsigned char*>(T->data) + r0 * T->ld * esz,
+                                 buf.size(), hipMemcpyDeviceToHost));
+        } else {
+            tm_status st = dense9_rows_rowmajor(T, T->data, r0, nrow, buf.data());
+            if (st != TM_OK) return st;
+        }
         for (int64_t r = 0; r < count; ++r)
             for (int64_t b = 0; b < n; ++b)
                 for (int i = 0; i < 3; ++i)
@@ -429,10 +409,9 @@ tm_status tm_tensor_rows(const tm_tensor* T, int64_t a0, int64_t count, double* 
     }
     std::vector<uint16_t> hi(nrow * T->ld), lo(nrow * T->ld);
     std::vector<float> rs(nrow, 1.0f);
-    TM_TRY_HIP(hipMemcpy(hi.data(), static_cast<const uint16_t*>(T->data) + r0 * T->ld, hi.size() * 2,
-                         hipMemcpyDeviceToHost));
-    TM_TRY_HIP(hipMemcpy(lo.data(), static_cast<const uint16_t*>(T->lo) + r0 * T->ld, lo.size() * 2,
-                         hipMemcpyDeviceToHost));
+    tm_status st = dense9_rows_rowmajor(T, T->data, r0, nrow, hi.data());
+    if (st == TM_OK) st = dense9_rows_rowmajor(T, T->lo, r0, nrow, lo.data());
+    if (st != TM_OK) return st;
     if (T->prec == TM_PREC_FP16X3)
         TM_TRY_HIP(hipMemcpy(rs.data(), T->rscale + r0, nrow * 4, hipMemcpyDeviceToHost));
     const bool bf = T->prec == TM_PREC_BF16X3;
@@ -603,8 +582,8 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
     int64_t xbytes = 0, pbytes = 0, splits = 0;
     if (dense) {
         const int64_t esz = T->prec == TM_PREC_FP32 ? 4 : 2;
-        const bool need_x = T->prec != TM_PREC_FP32 || !p->uniform_ms;
-        xbytes = need_x ? bcap * T->ld * esz * (T->prec == TM_PREC_FP32 ? 1 : 2) : 0;
+        // the right operand in the product's fragment order (hi + lo for the split forms)
+        xbytes = bcap * T->ld * esz * (T->prec == TM_PREC_FP32 ? 1 : 2);
         splits = gemm_splits(p);
         pbytes = splits * bcap * T->rows * 4;
     }

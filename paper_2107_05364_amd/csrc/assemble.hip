@@ -144,20 +144,31 @@ __global__ __launch_bounds__(256) void k_assemble_dense9(int32_t n, int64_t ld,
     r2[0] = cvt<OutT>(t6[2]); r2[1] = cvt<OutT>(t6[4]); r2[2] = cvt<OutT>(t6[5]);
 }
 
-// Split float32 entries into bf16 hi + lo (hi + lo carries 16 significant bits).
-__global__ __launch_bounds__(256) void k_split_bf16(int64_t count, const float* __restrict__ src,
+// Split float32 entries (row-major src, rows x ld) into bf16 hi + lo (hi + lo
+// carries 16 significant bits), written in the blocked product order.
+__global__ __launch_bounds__(256) void k_split_bf16(int64_t rows, int64_t ld, const float* __restrict__ src,
                                                     __hip_bfloat16* __restrict__ hi,
                                                     __hip_bfloat16* __restrict__ lo) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= count) return;
+    if (i >= rows * ld) return;
     const float v = src[i];
     const __hip_bfloat16 h = __float2bfloat16(v);
-    hi[i] = h;
-    lo[i] = __float2bfloat16(v - __bfloat162float(h));
+    const int64_t o = dense9_index(ld, 8, i / ld, i % ld);
+    hi[o] = h;
+    lo[o] = __float2bfloat16(v - __bfloat162float(h));
+}
+
+// Row-major float32 (rows x ld) to the blocked product order.
+__global__ __launch_bounds__(256) void k_block_fp32(int64_t rows, int64_t ld, const float* __restrict__ src,
+                                                    float* __restrict__ dst) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= rows * ld) return;
+    dst[dense9_index(ld, 4, i / ld, i % ld)] = src[i];
 }
 
 // Per-row power-of-two scale so that the row maximum maps to [2^13, 2^14),
-// then fp16 hi + lo of the scaled row.  One block per row.
+// then fp16 hi + lo of the scaled row in the blocked product order.  One
+// block per row.
 __global__ __launch_bounds__(256) void k_split_fp16_rows(int64_t ld, const float* __restrict__ src,
                                                          __half* __restrict__ hi,
                                                          __half* __restrict__ lo,
@@ -182,8 +193,9 @@ __global__ __launch_bounds__(256) void k_split_fp16_rows(int64_t ld, const float
     for (int64_t c = threadIdx.x; c < ld; c += blockDim.x) {
         const float v = r[c] * scale;
         const __half h = __float2half(v);
-        hi[row * ld + c] = h;
-        lo[row * ld + c] = __float2half(v - __half2float(h));
+        const int64_t o = dense9_index(ld, 8, row, c);
+        hi[o] = h;
+        lo[o] = __float2half(v - __half2float(h));
     }
 }
 
@@ -225,6 +237,46 @@ tm_status assemble_psym(Tensor* T, const double* d_centers, const double* d_size
     return TM_OK;
 }
 
+namespace {
+
+// Rows [r0, r0 + nrow) of a blocked DENSE9 array back in row-major order.
+template <typename E>
+__global__ __launch_bounds__(256) void k_gather_dense9(int64_t ld, int vec, int64_t r0, int64_t nrow,
+                                                       const E* __restrict__ src, E* __restrict__ dst) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= nrow * ld) return;
+    dst[i] = src[dense9_index(ld, vec, r0 + i / ld, i % ld)];
+}
+
+}  // namespace
+
+tm_status dense9_rows_rowmajor(const Tensor* T, const void* src, int64_t r0, int64_t nrow, void* host) {
+    TM_REQUIRE(T->layout == TM_LAYOUT_DENSE9 && T->prec != TM_PREC_FP64 && r0 >= 0 && nrow >= 0 &&
+                   r0 + nrow <= T->rows,
+               TM_EINVAL, "dense9 read-back: rows out of range");
+    if (nrow == 0) return TM_OK;
+    const int esz = T->prec == TM_PREC_FP32 ? 4 : 2;
+    const int vec = T->prec == TM_PREC_FP32 ? 4 : 8;
+    const int64_t count = nrow * T->ld;
+    void* d = nullptr;
+    TM_TRY_HIP(hipMalloc(&d, count * esz));
+    const unsigned g = static_cast<unsigned>((count + 255) / 256);
+    if (esz == 4)
+        k_gather_dense9<float><<<g, 256>>>(T->ld, vec, r0, nrow, static_cast<const float*>(src),
+                                           static_cast<float*>(d));
+    else
+        k_gather_dense9<uint16_t><<<g, 256>>>(T->ld, vec, r0, nrow, static_cast<const uint16_t*>(src),
+                                              static_cast<uint16_t*>(d));
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(host, d, count * esz, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) {
+        set_error("dense9 read-back: %s", hipGetErrorString(e));
+        return TM_EDEVICE;
+    }
+    return TM_OK;
+}
+
 tm_status assemble_device(Tensor* T, const double* d_centers, const double* d_sizes,
                           hipStream_t s) {
     const int32_t n = static_cast<int32_t>(T->n);
@@ -246,7 +298,7 @@ tm_status assemble_device(Tensor* T, const double* d_centers, const double* d_si
     const int64_t count = T->rows * T->ld;
     void* dst = T->data;
     float* tmp = nullptr;
-    if (T->prec == TM_PREC_BF16X3 || T->prec == TM_PREC_FP16X3) {
+    if (T->prec != TM_PREC_FP64) {  // assembled row-major, then stored blocked
         TM_TRY_HIP(hipMallocAsync(reinterpret_cast<void**>(&tmp), count * sizeof(float), s));
         dst = tmp;
     }
@@ -258,9 +310,13 @@ tm_status assemble_device(Tensor* T, const double* d_centers, const double* d_si
         k_assemble_dense9<float><<<grid, block, 0, s>>>(n, T->ld, d_centers, d_sizes,
                                                        static_cast<float*>(dst));
     TM_TRY_HIP(hipGetLastError());
-    if (T->prec == TM_PREC_BF16X3) {
+    if (T->prec == TM_PREC_FP32) {
         const unsigned g = static_cast<unsigned>((count + 255) / 256);
-        k_split_bf16<<<g, block, 0, s>>>(count, tmp, static_cast<__hip_bfloat16*>(T->data),
+        k_block_fp32<<<g, block, 0, s>>>(T->rows, T->ld, tmp, static_cast<float*>(T->data));
+        TM_TRY_HIP(hipGetLastError());
+    } else if (T->prec == TM_PREC_BF16X3) {
+        const unsigned g = static_cast<unsigned>((count + 255) / 256);
+        k_split_bf16<<<g, block, 0, s>>>(T->rows, T->ld, tmp, static_cast<__hip_bfloat16*>(T->data),
                                          static_cast<__hip_bfloat16*>(T->lo));
         TM_TRY_HIP(hipGetLastError());
     } else if (T->prec == TM_PREC_FP16X3) {

@@ -43,6 +43,28 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // batched product's 128-element chunks.
 inline int64_t padded_tiles(int64_t n) { return round_up(n, 128); }
 
+// Stored order of the DENSE9 operator in FP32 / BF16X3 / FP16X3 (the MFMA
+// operand of the batched product; FP64 stays row-major).  The padded
+// rows x ld matrix is cut into blocks of kGemmRows x kGemmKC elements, block
+// (rb, kc) at (rb * ld / kGemmKC + kc) * kGemmRows * kGemmKC.  Inside a block
+// the elements are in the order in which the product's lanes load them: row
+// rr = 32 w + 16 rt + j, column kk = 4 vec sub + vec g + e (vec = 4 for
+// float32, 8 for the 16-bit halves) sit at
+// ((((w * nsub + sub) * 2 + rt) * 64 + 16 g + j) * vec + e, nsub = kGemmKC / (4 vec),
+// so that every 16-byte load of a wave reads 1 KB in one piece and a block
+// (one workgroup's share of one K chunk) is a contiguous span of memory.
+constexpr int kGemmRows = 128;
+constexpr int kGemmKC = 64;
+__host__ __device__ inline int64_t dense9_index(int64_t ld, int vec, int64_t r, int64_t k) {
+    const int64_t rb = r / kGemmRows, kc = k / kGemmKC;
+    const int rr = static_cast<int>(r % kGemmRows), kk = static_cast<int>(k % kGemmKC);
+    const int w = rr / 32, rt = (rr % 32) / 16, j = rr % 16;
+    const int ksub = 4 * vec, nsub = kGemmKC / ksub;
+    const int sub = kk / ksub, g = (kk % ksub) / vec, e = kk % vec;
+    return (rb * (ld / kGemmKC) + kc) * (kGemmRows * kGemmKC) +
+           ((((w * nsub + sub) * 2 + rt) * 64 + 16 * g + j) * vec + e);
+}
+
 struct Tensor;
 
 // One device; owns the tensor cache and the admission ledger.
@@ -222,6 +244,9 @@ struct EpiArgs {
 tm_status launch_field(const Problem* p, Epi mode, int64_t B, const float* X, const EpiArgs& e,
                        hipStream_t s);
 // Batched (MFMA GEMM) path for DENSE9 operators (gemm.hip).
+// Host copy of rows [r0, r0 + nrow) of a blocked DENSE9 array (src = the
+// hi, lo or float32 data of T), row-major, nrow x ld elements.
+tm_status dense9_rows_rowmajor(const Tensor* T, const void* src, int64_t r0, int64_t nrow, void* host);
 int gemm_state_tiles(int64_t B);
 int64_t gemm_splits(const Problem* p);
 tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const float* X,

@@ -3,8 +3,8 @@
 // (paper Sec. 3.1: the demag operator is a dense 3N x 3N matrix applied to
 // the 3N-vector m; here to B such vectors at once).
 //
-//   C[r][s] = sum_k A[r][k] X[s][k],  A = stored operator (DENSE9, row-major,
-//   K contiguous), X[s][3b+j] = (Ms_b / Ms_ref) m_{s,b,j}, H_d = -Ms_ref C.
+//   C[r][s] = sum_k A[r][k] X[s][k],  A = stored operator (DENSE9),
+//   X[s][3b+j] = (Ms_b / Ms_ref) m_{s,b,j}, H_d = -Ms_ref C.
 //
 // Precisions (accumulation always float32):
 //   FP32   : v_mfma_f32_16x16x4_f32, A and X in float32;
@@ -16,16 +16,21 @@
 //            the scale is removed in the GEMM epilogue.
 //
 // Work split: a workgroup (4 waves) owns 128 operator rows x all states and
-// one K range (split-K); each wave owns two 16-row MFMA tiles.  The X chunk
-// of the K range is staged once per workgroup in LDS (row-padded so the
-// 16-byte reads of 16 lanes hit distinct banks) and reused by the 8 row
-// tiles; operator rows are read straight from memory, 16 bytes per lane,
-// each 128-byte line fully used.  Partial sums go to part[split][state][row]
-// and a fixed-order elementwise pass adds the splits, finishes the
-// effective field and the Runge-Kutta stage per tile.  The summation order
-// depends only on the problem size, never on the batch.
+// one K range (split-K); each wave owns two 16-row MFMA tiles.  K advances in
+// chunks of 64.  The operator is stored blocked (dense9_index): one
+// workgroup's rows of one chunk are a contiguous 16 KB (16-bit halves, each)
+// or 32 KB (float32) span, read straight into registers, 1 KB per wave load.
+// The right operand is written by k_prep in the same fragment order, one
+// contiguous span per chunk, staged once per workgroup in LDS (a plain copy:
+// every LDS access is a contiguous 1 KB per wave, free of bank conflicts)
+// and reused by the 8 row tiles.  Partial sums go to part[split][state][row]
+// and a fixed-order elementwise pass adds the splits, finishes the effective
+// field and the Runge-Kutta stage per tile.  The summation order depends only
+// on the problem size, never on the batch.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
+
+#include <type_traits>
 
 #include "common.h"
 #include "epilogue.h"
@@ -38,77 +43,72 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
-constexpr int kRowsPerBlock = 128;  // 4 waves x 2 tiles x 16 rows
-constexpr int kKC = 128;            // largest K chunk (X double-buffered in LDS); ld is a multiple
-
-// K chunk per (precision, state tiles), measured on the film operator
-// (7680 x 7680): the split forms at 128 states and FP32 at 32-64 states run
-// faster with 64-element chunks (half the registers and LDS: two workgroups
-// per CU), the rest with 128.
-constexpr int chunk_for(int prec, int nst) {
-    return (prec != 0 && nst == 8) || (prec == 0 && (nst == 2 || nst == 4)) ? 64 : 128;
-}
+constexpr int KC = kGemmKC;                          // K chunk
+constexpr int kBlockElems = kGemmRows * kGemmKC;     // elements of one operator block
 
 struct GemmArgs {
-    int64_t ld;         // K extent (= 3 np) and operator row stride
-    int64_t bpad;       // padded state count (multiple of 16)
-    const void* Ahi;    // FP32: the operator; split: hi part
-    const void* Alo;    // split: lo part
+    int64_t ld;         // K extent (= 3 np)
+    int64_t bpad;       // state stride of the partial sums (>= 16 NST)
+    const void* Ahi;    // FP32: the operator; split: hi part (blocked)
+    const void* Alo;    // split: lo part (blocked)
     const float* rscale;// FP16X3: 1/scale per row
-    const void* Xhi;    // [bpad][ld]
+    const void* Xhi;    // right operand, fragment order, [ld / KC][16 NST x KC]
     const void* Xlo;
     float* part;        // [splits][bpad][rows]
     int64_t rows;       // padded operator rows (multiple of 128)
-    int64_t kper;       // K elements per split (multiple of the chunk)
+    int64_t kper;       // K elements per split (multiple of KC)
 };
 
 template <int PREC>
 struct Elt;
 template <>
-struct Elt<0> { using T = float; static constexpr int kPerLane = 4; };
+struct Elt<0> { using T = float; using V = float4; static constexpr int kVec = 4; };
 template <>
-struct Elt<1> { using T = __bf16; static constexpr int kPerLane = 8; };
+struct Elt<1> { using T = __bf16; using V = v8bf; static constexpr int kVec = 8; };
 template <>
-struct Elt<2> { using T = _Float16; static constexpr int kPerLane = 8; };
+struct Elt<2> { using T = _Float16; using V = v8h; static constexpr int kVec = 8; };
 
-// LDS row of one state's chunk: KC elements + 16 bytes of padding
-template <int PREC, int KC>
-constexpr int lds_row_bytes() { return KC * static_cast<int>(sizeof(typename Elt<PREC>::T)) + 16; }
+template <int PREC, typename AV>
+__device__ inline v4f mfma_split(const AV& a, const AV& b, const v4f& c) {
+    if constexpr (PREC == 1) return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
 
-// Software pipeline per K chunk c (KC = 64 or 128): the operator rows and the X
+// Software pipeline per K chunk c: the operator rows of chunk c+2 and the X
 // tile of chunk c+1 are loaded into registers while the MFMAs of chunk c run
-// from LDS buffer c&1; the X tile then goes to buffer (c+1)&1, which no wave
-// reads any more (all passed the barrier after chunk c-1).  One barrier per
-// chunk.  A chunk carries enough MFMA work (split: 192 per wave) to cover
-// the latency of the next chunk's loads, and MFMAs are issued across
+// (operator rows from ring slot c % 3, X from LDS buffer c & 1); the X tile
+// then goes to buffer (c+1) & 1, which no wave reads any more (all passed the
+// barrier after chunk c-1).  One barrier per chunk.  One wave per SIMD (the
+// register file holds three chunks of operator rows); the MFMAs sweep the
 // independent accumulators so that none waits for its predecessor.
-template <int PREC, int NST, int KC>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
+template <int PREC, int NST>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_gemm(GemmArgs G) {
     using T = typename Elt<PREC>::T;
+    using AV = typename Elt<PREC>::V;
     constexpr bool SPLIT = PREC != 0;
-    constexpr int RB = lds_row_bytes<PREC, KC>();
+    constexpr int VEC = Elt<PREC>::kVec;
+    constexpr int NSUB = KC / (4 * VEC);                       // MFMA K steps per chunk
     constexpr int NS = NST * 16;
-    constexpr int CHUNK16 = KC * static_cast<int>(sizeof(T)) / 16;  // 16-byte pieces per state row
-    constexpr int XPIECES = NS * CHUNK16;
-    constexpr int XPT = (XPIECES + 255) / 256;  // pieces per thread and array
-    constexpr int BUF = NS * RB * (SPLIT ? 2 : 1);
-    constexpr int NSUB = PREC == 0 ? KC / 16 : KC / 32;
-    using AV = typename std::conditional<PREC == 0, float4,
-                                         typename std::conditional<PREC == 1, v8bf, v8h>::type>::type;
+    constexpr int XB = NS * KC * static_cast<int>(sizeof(T));  // bytes of one X array per chunk
+    constexpr int XPIECES = XB / 16;
+    constexpr int XPT = (XPIECES + 255) / 256;                 // 16-byte pieces per thread and array
+    constexpr int BUF = XB * (SPLIT ? 2 : 1);
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, j = lane & 15;
-    const int64_t rowbase = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock + wave * 32;
+    const int64_t rowbase = static_cast<int64_t>(blockIdx.x) * kGemmRows + wave * 32;
     const int64_t kb = static_cast<int64_t>(blockIdx.y) * G.kper;
     const int64_t ke = min(kb + G.kper, G.ld);
     const int nch = static_cast<int>((ke - kb) / KC);
+    const int64_t kc0 = kb / KC;
 
-    const T* Ah = static_cast<const T*>(G.Ahi);
-    const T* Al = static_cast<const T*>(G.Alo);
-    const unsigned char* Xh = static_cast<const unsigned char*>(G.Xhi);
-    const unsigned char* Xl = static_cast<const unsigned char*>(G.Xlo);
-    const int64_t xrow = G.ld * static_cast<int64_t>(sizeof(T));  // bytes per state row
+    // this workgroup's first operator block and this lane's place in a block
+    const int64_t ablk = (static_cast<int64_t>(blockIdx.x) * (G.ld / KC) + kc0) * kBlockElems;
+    const T* Ah = static_cast<const T*>(G.Ahi) + ablk;
+    const T* Al = SPLIT ? static_cast<const T*>(G.Alo) + ablk : nullptr;
+    const unsigned char* Xh = static_cast<const unsigned char*>(G.Xhi) + kc0 * XB;
+    const unsigned char* Xl = SPLIT ? static_cast<const unsigned char*>(G.Xlo) + kc0 * XB : nullptr;
 
     v4f acc[2][NST];
 #pragma unroll
@@ -117,15 +117,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
         for (int s = 0; s < NST; ++s) acc[r][s] = v4f{0.f, 0.f, 0.f, 0.f};
 
     v4u xh_r[XPT], xl_r[XPT];
-    AV ah_r[NSUB][2], al_r[NSUB][2], ah_n[NSUB][2], al_n[NSUB][2];
+    // operator rows of three chunks: the one being multiplied and the next two in flight
+    AV ah[3][NSUB][2], al[3][NSUB][2];
 
-    auto load_x = [&](int64_t k0) {
+    auto load_x = [&](int c) {
 #pragma unroll
         for (int q = 0; q < XPT; ++q) {
             const int idx = threadIdx.x + 256 * q;
             if (XPIECES % 256 == 0 || idx < XPIECES) {
-                const int st = idx / CHUNK16, pc = idx % CHUNK16;
-                const int64_t off = st * xrow + k0 * static_cast<int64_t>(sizeof(T)) + 16 * pc;
+                const int64_t off = static_cast<int64_t>(c) * XB + 16 * idx;
                 xh_r[q] = *reinterpret_cast<const v4u*>(Xh + off);
                 if constexpr (SPLIT) xl_r[q] = *reinterpret_cast<const v4u*>(Xl + off);
             }
@@ -137,41 +137,28 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
         for (int q = 0; q < XPT; ++q) {
             const int idx = threadIdx.x + 256 * q;
             if (XPIECES % 256 == 0 || idx < XPIECES) {
-                const int st = idx / CHUNK16, pc = idx % CHUNK16;
-                *reinterpret_cast<v4u*>(base + st * RB + 16 * pc) = xh_r[q];
-                if constexpr (SPLIT) *reinterpret_cast<v4u*>(base + NS * RB + st * RB + 16 * pc) = xl_r[q];
+                *reinterpret_cast<v4u*>(base + 16 * idx) = xh_r[q];
+                if constexpr (SPLIT) *reinterpret_cast<v4u*>(base + XB + 16 * idx) = xl_r[q];
             }
         }
     };
-    // the next chunk's operator rows always land in ah_n / al_n and the MFMAs
-    // always read ah_r / al_r (fixed arrays keep everything in registers)
-    auto load_a_next = [&](int64_t k0) {
+    // chunk rows go to ring slot S (a compile-time index, so the ring stays in registers)
+    auto load_a = [&](auto slot, int c) {
+        constexpr int S = decltype(slot)::value;
+        const int64_t cb = static_cast<int64_t>(c) * kBlockElems;
 #pragma unroll
         for (int sub = 0; sub < NSUB; ++sub)
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt) {
-                const int64_t row = rowbase + 16 * rt + j;
-                if constexpr (PREC == 0) {
-                    ah_n[sub][rt] = *reinterpret_cast<const float4*>(Ah + row * G.ld + k0 + 16 * sub + 4 * g);
-                } else {
-                    const int64_t off = row * G.ld + k0 + 32 * sub + 8 * g;
-                    ah_n[sub][rt] = *reinterpret_cast<const AV*>(Ah + off);
-                    al_n[sub][rt] = *reinterpret_cast<const AV*>(Al + off);
-                }
+                const int64_t off = cb + static_cast<int64_t>(((wave * NSUB + sub) * 2 + rt) * 64 + lane) * VEC;
+                ah[S][sub][rt] = *reinterpret_cast<const AV*>(Ah + off);
+                if constexpr (SPLIT) al[S][sub][rt] = *reinterpret_cast<const AV*>(Al + off);
             }
     };
-    auto rotate = [&]() {
-#pragma unroll
-        for (int sub = 0; sub < NSUB; ++sub)
-#pragma unroll
-            for (int rt = 0; rt < 2; ++rt) {
-                ah_r[sub][rt] = ah_n[sub][rt];
-                if constexpr (SPLIT) al_r[sub][rt] = al_n[sub][rt];
-            }
-    };
-    auto compute = [&](int buf) {
-        const auto& hi = ah_r;
-        const auto& lo = al_r;
+    auto compute = [&](auto slot, int buf) {
+        constexpr int S = decltype(slot)::value;
+        const auto& hi = ah[S];
+        const auto& lo = al[S];
         const unsigned char* xs = lds + buf * BUF;
 #pragma unroll
         for (int sub = 0; sub < NSUB; ++sub) {
@@ -179,7 +166,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
                 float4 b[NST];
 #pragma unroll
                 for (int st = 0; st < NST; ++st)
-                    b[st] = *reinterpret_cast<const float4*>(xs + (16 * st + j) * RB + 4 * (16 * sub + 4 * g));
+                    b[st] = *reinterpret_cast<const float4*>(xs + ((sub * NST + st) * 64 + lane) * 16);
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -191,52 +178,66 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
                             acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[rt][st], 0, 0, 0);
                         }
             } else {
-                const int kk = 32 * sub + 8 * g;
+                // all B fragments of this K step first (the LDS reads overlap
+                // the first products), then the three products as three sweeps
+                // over the 2 x NST accumulators, so that dependent MFMAs are
+                // 2 NST instructions apart
+                AV bh[NST], bl[NST];
 #pragma unroll
                 for (int st = 0; st < NST; ++st) {
-                    const AV bh = *reinterpret_cast<const AV*>(xs + (16 * st + j) * RB + 2 * kk);
-                    const AV bl = *reinterpret_cast<const AV*>(xs + NS * RB + (16 * st + j) * RB + 2 * kk);
-                    // three independent products over two accumulators
-                    if constexpr (PREC == 1) {
-                        acc[0][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[sub][0], bh, acc[0][st], 0, 0, 0);
-                        acc[1][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[sub][1], bh, acc[1][st], 0, 0, 0);
-                        acc[0][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[sub][0], bl, acc[0][st], 0, 0, 0);
-                        acc[1][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[sub][1], bl, acc[1][st], 0, 0, 0);
-                        acc[0][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[sub][0], bh, acc[0][st], 0, 0, 0);
-                        acc[1][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[sub][1], bh, acc[1][st], 0, 0, 0);
-                    } else {
-                        acc[0][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi[sub][0], bh, acc[0][st], 0, 0, 0);
-                        acc[1][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi[sub][1], bh, acc[1][st], 0, 0, 0);
-                        acc[0][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi[sub][0], bl, acc[0][st], 0, 0, 0);
-                        acc[1][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi[sub][1], bl, acc[1][st], 0, 0, 0);
-                        acc[0][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo[sub][0], bh, acc[0][st], 0, 0, 0);
-                        acc[1][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo[sub][1], bh, acc[1][st], 0, 0, 0);
-                    }
+                    const int o = ((sub * NST + st) * 64 + lane) * 16;
+                    bh[st] = *reinterpret_cast<const AV*>(xs + o);
+                    bl[st] = *reinterpret_cast<const AV*>(xs + XB + o);
                 }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int st = 0; st < NST; ++st)
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt) acc[rt][st] = mfma_split<PREC>(hi[sub][rt], bh[st], acc[rt][st]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int st = 0; st < NST; ++st)
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt) acc[rt][st] = mfma_split<PREC>(hi[sub][rt], bl[st], acc[rt][st]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int st = 0; st < NST; ++st)
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt) acc[rt][st] = mfma_split<PREC>(lo[sub][rt], bh[st], acc[rt][st]);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     };
 
+    // Near the end the loads repeat the last chunk instead of branching, so
+    // that the wait counts stay exact: each multiply waits for its own
+    // operator rows only.
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
+    using S2 = std::integral_constant<int, 2>;
+    const int last = nch - 1;
+    auto step = [&](auto slot, int c) {
+        constexpr int S = decltype(slot)::value;
+        load_x(min(c + 1, last));
+        load_a(std::integral_constant<int, (S + 2) % 3>{}, min(c + 2, last));
+        compute(slot, c & 1);
+        store_x((c + 1) & 1);
+        __syncthreads();
+    };
     if (nch > 0) {
-        load_x(kb);
-        load_a_next(kb);
-        rotate();
+        load_x(0);
+        load_a(S0{}, 0);
+        load_a(S1{}, min(1, last));
         store_x(0);
         __syncthreads();
-        for (int c = 0; c < nch; ++c) {
-            const bool more = c + 1 < nch;
-            const int64_t k1 = kb + static_cast<int64_t>(c + 1) * KC;
-            if (more) {
-                load_x(k1);
-                load_a_next(k1);
-            }
-            compute(c & 1);
-            if (more) {
-                store_x((c + 1) & 1);
-                rotate();
-            }
-            __syncthreads();
+        int c = 0;
+        for (; c + 3 <= nch; c += 3) {
+            step(S0{}, c);
+            step(S1{}, c + 1);
+            step(S2{}, c + 2);
         }
+        if (c < nch) step(S0{}, c);
+        if (c + 1 < nch) step(S1{}, c + 1);
     }
     // D[4 g + r][j] of tile (rt, st) -> part[split][state 16 st + j][row rowbase + 16 rt + 4 g + r]
     float* out = G.part + static_cast<int64_t>(blockIdx.y) * G.bpad * G.rows;
@@ -254,17 +255,30 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
     }
 }
 
-// Right operand from the (padded) stage input: (Ms_b / Ms_ref) m, as float32
-// or split into hi + lo.
+// Right operand from the (padded) stage input Y [B][ld]: (Ms_b / Ms_ref) m,
+// as float32 or split into hi + lo, written in the product's fragment order:
+// chunk kc holds 16 nst states x KC columns, state 16 st + j and column
+// kc KC + 4 vec sub + vec g + e at ((sub nst + st) 64 + 16 g + j) vec + e;
+// states B .. 16 nst - 1 are zero.  One thread per output element.
 template <int PREC>
-__global__ __launch_bounds__(256) void k_prep(int64_t B, int64_t ld, int32_t n, const float* __restrict__ Y,
+__global__ __launch_bounds__(256) void k_prep(int64_t B, int nst, int64_t ld, int32_t n, const float* __restrict__ Y,
                                               const float* __restrict__ Ms, float inv_ref,
                                               void* __restrict__ xh, void* __restrict__ xl) {
+    constexpr int VEC = Elt<PREC>::kVec;
+    const int64_t ns = 16 * static_cast<int64_t>(nst);
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= B * ld) return;
-    const int64_t k = i % ld;
+    if (i >= ns * ld) return;
+    const int64_t kc = i / (ns * KC);
+    const int64_t w = i % (ns * KC);
+    const int64_t piece = w / VEC;
+    const int e = static_cast<int>(w % VEC);
+    const int ln = static_cast<int>(piece % 64);
+    const int64_t q = piece / 64;
+    const int st = static_cast<int>(q % nst), sub = static_cast<int>(q / nst);
+    const int64_t s = 16 * st + (ln & 15);
+    const int64_t k = kc * KC + 4 * VEC * sub + VEC * (ln >> 4) + e;
     const int64_t b = k / 3;
-    const float v = (b < n) ? Y[i] * (Ms[b] * inv_ref) : 0.0f;
+    const float v = (s < B && b < n) ? Y[s * ld + k] * (Ms[b] * inv_ref) : 0.0f;
     if constexpr (PREC == 0) {
         static_cast<float*>(xh)[i] = v;
     } else if constexpr (PREC == 1) {
@@ -317,8 +331,7 @@ __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __res
 
 template <int PREC, int NST>
 tm_status launch_gemm_t(const GemmArgs& G, int64_t rowblocks, int64_t splits, hipStream_t s) {
-    k_gemm<PREC, NST, chunk_for(PREC, NST)>
-        <<<dim3(static_cast<unsigned>(rowblocks), static_cast<unsigned>(splits)), 256, 0, s>>>(G);
+    k_gemm<PREC, NST><<<dim3(static_cast<unsigned>(rowblocks), static_cast<unsigned>(splits)), 256, 0, s>>>(G);
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
 }
@@ -344,9 +357,9 @@ int gemm_state_tiles(int64_t B) {
 }
 
 int64_t gemm_splits(const Problem* p) {
-    const int64_t rowblocks = p->T->rows / kRowsPerBlock;
-    const int64_t kchunks = p->T->ld / kKC;
-    // about one workgroup per CU (the split-precision kernel holds ~139 KB of LDS)
+    const int64_t rowblocks = p->T->rows / kGemmRows;
+    const int64_t kchunks = p->T->ld / KC;
+    // about one workgroup per CU (one wave per SIMD)
     int64_t s = (256 + rowblocks - 1) / rowblocks;
     if (s > 1 && rowblocks * s > 256 + rowblocks / 2) s -= 1;
     return std::max<int64_t>(1, std::min<int64_t>(s, std::min<int64_t>(kchunks, 16)));
@@ -358,27 +371,27 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     Workspace* w = p->ws.get();
     TM_REQUIRE(w && w->part && B <= 128 && w->bpad >= 16 * gemm_state_tiles(B), TM_EINVAL,
                "batched product: workspace not prepared for %lld states", static_cast<long long>(B));
-    TM_REQUIRE(T->ld % kKC == 0 && T->rows % kRowsPerBlock == 0 && T->rows >= T->ld, TM_EINVAL,
-               "batched product: operator extent %lld x %lld is not a whole number of tiles",
+    TM_REQUIRE(T->ld % KC == 0 && T->rows % kGemmRows == 0 && T->rows >= T->ld, TM_EINVAL,
+               "batched product: operator extent %lld x %lld is not a whole number of blocks",
                static_cast<long long>(T->rows), static_cast<long long>(T->ld));
+    TM_REQUIRE(w->xh && (T->prec == TM_PREC_FP32 || w->xl), TM_EINVAL,
+               "batched product: workspace has no right-operand buffer");
     const int prec = T->prec == TM_PREC_FP32 ? 0 : T->prec == TM_PREC_BF16X3 ? 1 : 2;
     const int64_t ld = T->ld;
-    // right operand
-    const void* xh = X;
-    const void* xl = nullptr;
-    if (prec != 0 || !p->uniform_ms) {
-        const int64_t cnt = B * ld;
+    const int nst = gemm_state_tiles(B);
+    // right operand, in fragment order
+    {
+        const int64_t cnt = 16 * nst * ld;
         const unsigned grid = static_cast<unsigned>((cnt + 255) / 256);
         const float inv = static_cast<float>(1.0 / p->ms_ref);
+        const int32_t n32 = static_cast<int32_t>(p->n);
         if (prec == 0)
-            k_prep<0><<<grid, 256, 0, s>>>(B, ld, static_cast<int32_t>(p->n), X, p->Ms, inv, w->xh, nullptr);
+            k_prep<0><<<grid, 256, 0, s>>>(B, nst, ld, n32, X, p->Ms, inv, w->xh, nullptr);
         else if (prec == 1)
-            k_prep<1><<<grid, 256, 0, s>>>(B, ld, static_cast<int32_t>(p->n), X, p->Ms, inv, w->xh, w->xl);
+            k_prep<1><<<grid, 256, 0, s>>>(B, nst, ld, n32, X, p->Ms, inv, w->xh, w->xl);
         else
-            k_prep<2><<<grid, 256, 0, s>>>(B, ld, static_cast<int32_t>(p->n), X, p->Ms, inv, w->xh, w->xl);
+            k_prep<2><<<grid, 256, 0, s>>>(B, nst, ld, n32, X, p->Ms, inv, w->xh, w->xl);
         TM_TRY_HIP(hipGetLastError());
-        xh = w->xh;
-        xl = w->xl;
     }
     GemmArgs G;
     G.ld = ld;
@@ -386,15 +399,14 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     G.Ahi = T->data;
     G.Alo = T->lo;
     G.rscale = T->rscale;
-    G.Xhi = xh;
-    G.Xlo = xl;
+    G.Xhi = w->xh;
+    G.Xlo = w->xl;
     G.part = w->part;
     G.rows = T->rows;
     const int64_t splits = w->part_splits;
-    const int nst = gemm_state_tiles(B);
-    G.kper = round_up((ld + splits - 1) / splits, chunk_for(prec, nst));
+    G.kper = round_up((ld + splits - 1) / splits, KC);
     const int64_t used_splits = (ld + G.kper - 1) / G.kper;
-    const int64_t rowblocks = T->rows / kRowsPerBlock;
+    const int64_t rowblocks = T->rows / kGemmRows;
     tm_status st = prec == 0   ? launch_gemm_p<0>(nst, G, rowblocks, used_splits, s)
                    : prec == 1 ? launch_gemm_p<1>(nst, G, rowblocks, used_splits, s)
                                : launch_gemm_p<2>(nst, G, rowblocks, used_splits, s);
