@@ -386,6 +386,52 @@ def test_errors_are_reported(tmg, ctx):
     close(g)
 
 
+def test_edge_inputs_rejected(tmg, ctx):
+    """Empty, non-finite and degenerate inputs come back as TM_EINVAL from the
+    C ABI before anything is launched: a geometry without tiles, a non-finite
+    centre, a zero edge, a batch of no states (every field entry point and
+    tm_run), and a null device pointer."""
+    import ctypes
+
+    import torch
+
+    bad = [(np.zeros((0, 3)), np.zeros((0, 3))),
+           (np.array([[np.nan, 0.0, 0.0]]), np.full((1, 3), 1e-9)),
+           (np.zeros((1, 3)), np.array([[1e-9, 0.0, 1e-9]])),
+           (np.zeros((1, 3)), np.array([[1e-9, np.inf, 1e-9]]))]
+    for c, s in bad:
+        with pytest.raises(tmg.TilemagError) as ei:
+            tmg.Geometry(ctx, c, s)
+        assert ei.value.status == tmg.TM_EINVAL
+    c, s = _meshes()["grid13x5"]
+    n = c.shape[0]
+    for layout in (tmg.TM_LAYOUT_SYM6, tmg.TM_LAYOUT_PSYM6, tmg.TM_LAYOUT_DENSE9):
+        g, T, p = build(tmg, ctx, c, s, layout=layout)
+        m = device_state(W.random_unit_vectors(5, n)[None])
+        out = torch.full_like(m, 7.0)
+        L = tmg.load()
+        st = tmg._stream()
+        mp, op = ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(out.data_ptr())
+        assert L.tm_demag(p.handle, 0, mp, op, st) == tmg.TM_EINVAL
+        assert L.tm_heff(p.handle, 0, mp, None, op, st) == tmg.TM_EINVAL
+        assert L.tm_dmdt(p.handle, 0, mp, None, op, st) == tmg.TM_EINVAL
+        assert L.tm_demag(p.handle, 1, None, op, st) == tmg.TM_EINVAL
+        with pytest.raises(tmg.TilemagError) as ei:
+            p.demag(torch.empty((0, n, 3), device="cuda"))
+        assert ei.value.status == tmg.TM_EINVAL
+        with pytest.raises(tmg.TilemagError) as ei:
+            p.run(torch.empty((0, n, 3), device="cuda"), None, tmg.TM_DP45, dt=1e-14, max_steps=1)
+        assert ei.value.status == tmg.TM_EINVAL
+        if layout == tmg.TM_LAYOUT_DENSE9:  # the batched product takes at most 128 states a call
+            big = device_state(np.stack([W.random_unit_vectors(9 + k, n) for k in range(129)]))
+            with pytest.raises(tmg.TilemagError) as ei:
+                p.demag(big)
+            assert ei.value.status == tmg.TM_EINVAL
+        torch.cuda.synchronize()
+        assert bool((out == 7.0).all())  # nothing was written
+        close(g, T, p)
+
+
 @pytest.mark.parametrize("layout", ["sym6", "psym6", "dense9"])
 def test_diagnostics_vs_oracle(tmg, ctx, orc, layout):
     """tm_diagnostics against the oracle: energy terms (relative 1e-5),
