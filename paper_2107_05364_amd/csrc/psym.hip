@@ -65,17 +65,25 @@ inline int64_t pair_index(int64_t I, int64_t J, int64_t nt) {
 // and subtract them from their own slot, so that minus the slot sum is the
 // whole effective field and the finish kernel has no dependent loads left.
 template <bool STEPPING, bool LOCALF, bool NTL>
-__global__ __launch_bounds__(256) void k_psym_tiles(DevProblem P, const float* __restrict__ tiles,
+__global__ __launch_bounds__(256) void k_psym_tiles(DevProblem P, const float* tiles,
                                                     const int32_t* __restrict__ pairs, int64_t nt,
                                                     const float* __restrict__ Ms, const float* __restrict__ X,
                                                     int64_t sx, const double* __restrict__ h,
                                                     const float* __restrict__ Ha, float* __restrict__ part) {
     const int64_t p = blockIdx.x;
     const int64_t s = blockIdx.y;
-    if (STEPPING && h[s] == 0.0) return;  // frozen state: its slots are not read
-    const int64_t I = pairs[2 * p], J = pairs[2 * p + 1];
     const int t = threadIdx.x;
     const int b = t % TS, rg = t / TS;
+    // the tile is requested first: its loads depend on nothing else
+    const float* tile = tiles + p * 6 * TB;
+    float v[RPT][6];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[i][c] = ldt<NTL>(tile + c * TB + (RPT * rg + i) * TS + b);
+    asm volatile("" ::: "memory");  // keeps the loads above the early exit below
+    if (STEPPING && h[s] == 0.0) return;  // frozen state: its slots are not read
+    const int64_t I = pairs[2 * p], J = pairs[2 * p + 1];
     __shared__ float rred[TS][3][TS + 1];  // row sums before the column reduction
     __shared__ float cred[RG][TS][3];      // column sums per row group
     __shared__ float hl[TS][3];            // local field terms (diagonal pairs)
@@ -93,7 +101,6 @@ __global__ __launch_bounds__(256) void k_psym_tiles(DevProblem P, const float* _
     const int64_t bg = TS * J + b;
     const float msb = Ms[bg];
     const float xb0 = x[3 * bg] * msb, xb1 = x[3 * bg + 1] * msb, xb2 = x[3 * bg + 2] * msb;
-    const float* tile = tiles + p * 6 * TB;
     float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
@@ -101,10 +108,7 @@ __global__ __launch_bounds__(256) void k_psym_tiles(DevProblem P, const float* _
         const int64_t ag = TS * I + al;
         const float msa = Ms[ag];
         const float xa0 = x[3 * ag] * msa, xa1 = x[3 * ag + 1] * msa, xa2 = x[3 * ag + 2] * msa;
-        const int off = al * TS + b;
-        const float v0 = ldt<NTL>(tile + off), v1 = ldt<NTL>(tile + TB + off), v2 = ldt<NTL>(tile + 2 * TB + off);
-        const float v3 = ldt<NTL>(tile + 3 * TB + off), v4 = ldt<NTL>(tile + 4 * TB + off),
-                    v5 = ldt<NTL>(tile + 5 * TB + off);
+        const float v0 = v[i][0], v1 = v[i][1], v2 = v[i][2], v3 = v[i][3], v4 = v[i][4], v5 = v[i][5];
         rred[al][0][b] = v0 * xb0 + v1 * xb1 + v2 * xb2;
         rred[al][1][b] = v1 * xb0 + v3 * xb1 + v4 * xb2;
         rred[al][2][b] = v2 * xb0 + v4 * xb1 + v5 * xb2;
@@ -158,41 +162,60 @@ __global__ __launch_bounds__(kFinishThreads) void k_psym_finish(DevProblem P, co
     const int64_t K = blockIdx.x;
     const int s = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    bool frozen = false;
-    if constexpr (STEPPING) frozen = E.h[s] == 0.0;
-    if constexpr (MODE == Epi::STAGE || MODE == Epi::RK4_FINAL) {
-        if (frozen) return;
-    }
     __shared__ float gs[FG][TS][3];
     const int q = threadIdx.x % TS, grp = threadIdx.x / TS;
-    // the epilogue's own inputs are loaded before the slots are summed
+    // Thread (grp, q) adds the slots j = grp, grp + FG, ... of tile q in
+    // ascending j, four independent loads per round (past the last slot the
+    // load repeats it and the value is not added: no branches between the
+    // loads).  The slots are requested before anything else (they depend
+    // only on K and s), the epilogue's own inputs next; a frozen state then
+    // stops or skips.
+    const float* src = part + (static_cast<int64_t>(s) * nt + K) * nt * (3 * TS) + 3 * q;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+    int64_t j = grp;
     const int64_t a = TS * K + lane;
-    const bool mine = !frozen && wave == 0 && lane < TS && a < P.n;
     EpiIn in;
-    if (mine) epi_load<MODE>(X, sx, E, s, static_cast<int>(a), in);
-    if (!frozen) {
-        const float* src = part + (static_cast<int64_t>(s) * nt + K) * nt * (3 * TS) + 3 * q;
-        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-        // four slots per round, all loads issued before the adds
-        int64_t j = grp;
-        for (; j + 3 * FG < nt; j += 4 * FG) {
-            float v[4][3];
+    bool mine = false, skip = false;
+    {
+        float v[4][3];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) v[u][c] = src[(j + u * FG) * (3 * TS) + c];
+            for (int c = 0; c < 3; ++c) v[u][c] = src[min(j + u * FG, nt - 1) * (3 * TS) + c];
+        const bool mine0 = wave == 0 && lane < TS && a < P.n;
+        EpiIn in0;
+        if (mine0) epi_load<MODE>(X, sx, E, s, static_cast<int>(a), in0);
+        bool frozen = false;
+        if constexpr (STEPPING) frozen = E.h[s] == 0.0;
+        if constexpr (MODE == Epi::STAGE || MODE == Epi::RK4_FINAL) {
+            if (frozen) return;
+        }
+        in = in0;
+        mine = mine0 && !frozen;
+        skip = frozen;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 4; ++u)
+            if (j + u * FG < nt) {
                 a0 += v[u][0];
                 a1 += v[u][1];
                 a2 += v[u][2];
             }
-        }
-        for (; j < nt; j += FG) {
-            const float* v = src + j * (3 * TS);
-            a0 += v[0];
-            a1 += v[1];
-            a2 += v[2];
+        j += 4 * FG;
+    }
+    if (!skip) {
+        for (; j < nt; j += 4 * FG) {
+            float v[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[u][c] = src[min(j + u * FG, nt - 1) * (3 * TS) + c];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (j + u * FG < nt) {
+                    a0 += v[u][0];
+                    a1 += v[u][1];
+                    a2 += v[u][2];
+                }
         }
         gs[grp][q][0] = a0;
         gs[grp][q][1] = a1;
