@@ -64,7 +64,8 @@ KERNELS = {
     "sym6": (["paper_2107_05364_amd/csrc/fieldstep.hip", "paper_2107_05364_amd/csrc/epilogue.h",
               "paper_2107_05364_amd/csrc/common.h"],
              os.path.join(ROOT, "profiles", "k_field_stage_film_N2500_counters.md")),
-    "psym6": (["paper_2107_05364_amd/csrc/psym.hip", "paper_2107_05364_amd/csrc/common.h"],
+    "psym6": (["paper_2107_05364_amd/csrc/psym.hip", "paper_2107_05364_amd/csrc/epilogue.h",
+               "paper_2107_05364_amd/csrc/common.h"],
               os.path.join(ROOT, "profiles", "k_psym_tiles_film_N2500_counters.md")),
 }
 
@@ -637,8 +638,9 @@ def main():
     eval_ms, _ = tmg.tm_profile_field(p.handle, 1, args.profile_iters)
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9
     if psym:
-        kname = "k_psym_tiles<true,true>"
-        kdesc = " (pair-symmetric tile pass of the demag product; + reduction/epilogue launch)"
+        kname = "k_psym_tiles<true,true,%s>" % ("true" if T.nbytes > (192 << 20) else "false")
+        kdesc = (" (pair-symmetric tile pass of the demag product; the slot sum and epilogue run in "
+                 "a second launch, included in field_evaluation_us)")
     else:
         kname = "k_field<%d,%d,%d,%d,STAGE>" % tmg.tm_shape_info(shape)
         kdesc = " (fused demag matvec + H_eff + LL + stage update)"
