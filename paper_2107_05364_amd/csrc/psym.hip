@@ -65,7 +65,7 @@ inline int64_t pair_index(int64_t I, int64_t J, int64_t nt) {
 // and subtract them from their own slot, so that minus the slot sum is the
 // whole effective field and the finish kernel has no dependent loads left.
 template <bool STEPPING, bool LOCALF, bool NTL>
-__global__ __launch_bounds__(256) void k_psym_tiles(DevProblem P, const float* tiles,
+__global__ __launch_bounds__(256) void k_psym_tiles(DevProblem P, const float* __restrict__ tiles,
                                                     const int32_t* __restrict__ pairs, int64_t nt,
                                                     const float* __restrict__ Ms, const float* __restrict__ X,
                                                     int64_t sx, const double* __restrict__ h,
@@ -74,15 +74,14 @@ __global__ __launch_bounds__(256) void k_psym_tiles(DevProblem P, const float* t
     const int64_t s = blockIdx.y;
     const int t = threadIdx.x;
     const int b = t % TS, rg = t / TS;
-    // the tile is requested first: its loads depend on nothing else
+    // a frozen state reads no operator (a batch may hold many of them)
+    if (STEPPING && h[s] == 0.0) return;
     const float* tile = tiles + p * 6 * TB;
     float v[RPT][6];
 #pragma unroll
     for (int i = 0; i < RPT; ++i)
 #pragma unroll
         for (int c = 0; c < 6; ++c) v[i][c] = ldt<NTL>(tile + c * TB + (RPT * rg + i) * TS + b);
-    asm volatile("" ::: "memory");  // keeps the loads above the early exit below
-    if (STEPPING && h[s] == 0.0) return;  // frozen state: its slots are not read
     const int64_t I = pairs[2 * p], J = pairs[2 * p + 1];
     __shared__ float rred[TS][3][TS + 1];  // row sums before the column reduction
     __shared__ float cred[RG][TS][3];      // column sums per row group
