@@ -5,10 +5,11 @@
 // settings form a group.  A group owns one problem whose integration
 // workspace holds `max_slots` states; each request occupies one slot.  A
 // scheduler thread admits queued requests into free slots (or new groups,
-// when the tensor and workspace bytes fit the memory budget), advances every
-// active group by `steps_per_round` attempted DP45 steps from a captured
-// hipGraph on the group's own stream (groups overlap on the device), then
-// collects the slots whose state reached equilibrium
+// when the tensor and workspace bytes fit the memory budget) and advances
+// every active group in rounds of `steps_per_round` attempted DP45 steps
+// from a captured hipGraph on the group's own stream.  Groups overlap on the
+// device and progress independently: when a group's round ends (its event
+// completes) the scheduler collects the slots whose state reached equilibrium
 // (max_a |dm/dt|_a < threshold: Brown's first equation, paper Sec. 2.1) or
 // their step cap, and frees them for the next request.  A state's arithmetic
 // never depends on its slot or on the other states of the batch, so a result
@@ -190,6 +191,7 @@ bool tm_server::try_place(Req* r) {
         if (q->key == key) {
             auto it = std::find(q->slot.begin(), q->slot.end(), nullptr);
             if (it != q->slot.end()) {
+                if (q->launched) return false;  // mid-round: placed when the round ends
                 g = q;
                 break;
             }
@@ -309,49 +311,36 @@ bool tm_server::try_place(Req* r) {
 void tm_server::run() {
     (void)hipSetDevice(ctx->device);
     std::vector<Req*> waiting;
+    auto has_work = [](const Group* g) {
+        for (Req* r : g->slot)
+            if (r) return true;
+        return false;
+    };
     for (;;) {
+        bool inflight = false;
+        for (Group* g : groups) inflight = inflight || g->launched;
         {
             std::unique_lock<std::mutex> lk(mu);
-            bool busy = !waiting.empty();
-            for (Group* g : groups)
-                for (Req* r : g->slot) busy = busy || r;
-            if (!busy)
-                cv_work.wait(lk, [&] { return stopping || !queue.empty(); });
+            bool busy = !waiting.empty() || inflight;
+            for (Group* g : groups) busy = busy || has_work(g);
+            if (!busy) cv_work.wait(lk, [&] { return stopping || !queue.empty(); });
             while (!queue.empty()) {
                 waiting.push_back(queue.front());
                 queue.pop_front();
             }
-            bool active = !waiting.empty();
-            for (Group* g : groups)
-                for (Req* r : g->slot) active = active || r;
+            bool active = !waiting.empty() || inflight;
+            for (Group* g : groups) active = active || has_work(g);
             if (stopping && !active) break;
         }
-        // admission in arrival order; a request that does not fit waits
-        std::vector<Req*> still;
-        for (Req* r : waiting)
-            if (!try_place(r)) still.push_back(r);
-        waiting.swap(still);
-        // one round on every group with work, all groups enqueued first
-        for (Group* g : groups) {
-            g->launched = false;
-            bool any = false;
-            for (Req* r : g->slot) any = any || r;
-            if (!any) continue;
-            Workspace* w = g->P->ws.get();
-            const int rounds = std::max(1, cfg.steps_per_round / kGraphSteps);
-            bool ok = true;
-            for (int k = 0; k < rounds && ok; ++k) ok = hipGraphLaunch(w->graphK, g->stream) == hipSuccess;
-            ok = ok && hipMemcpyAsync(w->host_flags, w->flags, g->slot.size() * 4, hipMemcpyDeviceToHost,
-                                      g->stream) == hipSuccess;
-            ok = ok && hipEventRecord(g->ev, g->stream) == hipSuccess;
-            g->launched = ok;
-            if (!ok)
-                for (size_t i = 0; i < g->slot.size(); ++i)
-                    if (g->slot[i]) finish(g, i, TM_EDEVICE);
-        }
+        bool progressed = false;
+        // collect every group whose round has completed; the others keep running
         for (Group* g : groups) {
             if (!g->launched) continue;
-            if (hipEventSynchronize(g->ev) != hipSuccess) {
+            const hipError_t q = hipEventQuery(g->ev);
+            if (q == hipErrorNotReady) continue;
+            g->launched = false;
+            progressed = true;
+            if (q != hipSuccess) {
                 for (size_t i = 0; i < g->slot.size(); ++i)
                     if (g->slot[i]) finish(g, i, TM_EDEVICE);
                 continue;
@@ -370,18 +359,43 @@ void tm_server::run() {
                     finish(g, i, TM_OK);
             }
         }
-        // groups without work are closed when others wait for memory or
+        // admission in arrival order into idle groups or new ones; a request
+        // whose group is mid-round, or that does not fit, waits
+        std::vector<Req*> still;
+        for (Req* r : waiting) {
+            if (try_place(r))
+                progressed = true;
+            else
+                still.push_back(r);
+        }
+        waiting.swap(still);
+        // the next round of every idle group with work
+        for (Group* g : groups) {
+            if (g->launched || !has_work(g)) continue;
+            Workspace* w = g->P->ws.get();
+            const int rounds = std::max(1, cfg.steps_per_round / kGraphSteps);
+            bool ok = true;
+            for (int k = 0; k < rounds && ok; ++k) ok = hipGraphLaunch(w->graphK, g->stream) == hipSuccess;
+            ok = ok && hipMemcpyAsync(w->host_flags, w->flags, g->slot.size() * 4, hipMemcpyDeviceToHost,
+                                      g->stream) == hipSuccess;
+            ok = ok && hipEventRecord(g->ev, g->stream) == hipSuccess;
+            g->launched = ok;
+            progressed = true;
+            if (!ok)
+                for (size_t i = 0; i < g->slot.size(); ++i)
+                    if (g->slot[i]) finish(g, i, TM_EDEVICE);
+        }
+        // idle groups without work are closed when others wait for memory or
         // group room; their tensors stay cached
         std::vector<Group*> keep;
         for (Group* g : groups) {
-            bool any = false;
-            for (Req* r : g->slot) any = any || r;
-            if (!any && !waiting.empty())
+            if (!g->launched && !has_work(g) && !waiting.empty())
                 drop_group(g);
             else
                 keep.push_back(g);
         }
         groups.swap(keep);
+        if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
     for (Group* g : groups) drop_group(g);
     groups.clear();
