@@ -177,33 +177,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                             const float bv = q == 0 ? b[st].x : q == 1 ? b[st].y : q == 2 ? b[st].z : b[st].w;
                             acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[rt][st], 0, 0, 0);
                         }
-            } else {
-                // all B fragments of this K step first (the LDS reads overlap
-                // the first products), then the three products as three sweeps
-                // over the 2 x NST accumulators, so that dependent MFMAs are
-                // 2 NST instructions apart
-                AV bh[NST], bl[NST];
+            }
+        }
+        if constexpr (PREC != 0) {
+            // the B fragments of both K steps are requested first (the second
+            // step's reads overlap the first step's products), then per K step
+            // the three products as three sweeps over the 2 x NST accumulators,
+            // so that dependent MFMAs are 2 NST instructions apart
+            AV bh[NSUB][NST], bl[NSUB][NST];
+#pragma unroll
+            for (int sub = 0; sub < NSUB; ++sub) {
 #pragma unroll
                 for (int st = 0; st < NST; ++st) {
                     const int o = ((sub * NST + st) * 64 + lane) * 16;
-                    bh[st] = *reinterpret_cast<const AV*>(xs + o);
-                    bl[st] = *reinterpret_cast<const AV*>(xs + XB + o);
+                    bh[sub][st] = *reinterpret_cast<const AV*>(xs + o);
+                    bl[sub][st] = *reinterpret_cast<const AV*>(xs + XB + o);
                 }
                 __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int sub = 0; sub < NSUB; ++sub) {
 #pragma unroll
                 for (int st = 0; st < NST; ++st)
 #pragma unroll
-                    for (int rt = 0; rt < 2; ++rt) acc[rt][st] = mfma_split<PREC>(hi[sub][rt], bh[st], acc[rt][st]);
+                    for (int rt = 0; rt < 2; ++rt) acc[rt][st] = mfma_split<PREC>(hi[sub][rt], bh[sub][st], acc[rt][st]);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int st = 0; st < NST; ++st)
 #pragma unroll
-                    for (int rt = 0; rt < 2; ++rt) acc[rt][st] = mfma_split<PREC>(hi[sub][rt], bl[st], acc[rt][st]);
+                    for (int rt = 0; rt < 2; ++rt) acc[rt][st] = mfma_split<PREC>(hi[sub][rt], bl[sub][st], acc[rt][st]);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int st = 0; st < NST; ++st)
 #pragma unroll
-                    for (int rt = 0; rt < 2; ++rt) acc[rt][st] = mfma_split<PREC>(lo[sub][rt], bh[st], acc[rt][st]);
+                    for (int rt = 0; rt < 2; ++rt) acc[rt][st] = mfma_split<PREC>(lo[sub][rt], bh[sub][st], acc[rt][st]);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
