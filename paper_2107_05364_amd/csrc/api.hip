@@ -574,7 +574,7 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
                    "batched (DENSE9) path: at most %lld states per call",
                    static_cast<long long>(kMaxGemmStates));
     // the GEMM operand is read in tiles of 16 states: pad the batch
-    const int64_t bcap = dense ? 16 * gemm_state_tiles(B) : B;
+    const int64_t bcap = dense ? gemm_state_pad(T, B) : B;
     if (p->ws && p->ws->B >= bcap) return TM_OK;
     const int64_t np = p->np, n = p->n;
     const int64_t sb = bcap * 3 * np * 4;  // one state buffer

@@ -46,23 +46,28 @@ inline int64_t padded_tiles(int64_t n) { return round_up(n, 128); }
 // Stored order of the DENSE9 operator in FP32 / BF16X3 / FP16X3 (the MFMA
 // operand of the batched product; FP64 stays row-major).  The padded
 // rows x ld matrix is cut into blocks of kGemmRows x kGemmKC elements, block
-// (rb, kc) at (rb * ld / kGemmKC + kc) * kGemmRows * kGemmKC.  Inside a block
-// the elements are in the order in which the product's lanes load them: row
-// rr = 32 w + 16 rt + j, column kk = 4 vec sub + vec g + e (vec = 4 for
-// float32, 8 for the 16-bit halves) sit at
-// ((((w * nsub + sub) * 2 + rt) * 64 + 16 g + j) * vec + e, nsub = kGemmKC / (4 vec),
-// so that every 16-byte load of a wave reads 1 KB in one piece and a block
+// (rb, kc) at (rb * ld / kGemmKC + kc) * kGemmRows * kGemmKC, so that a block
 // (one workgroup's share of one K chunk) is a contiguous span of memory.
+// Inside a block the elements are in the order in which the product's lanes
+// load them, every 16-byte load of a wave reading 1 KB in one piece:
+//   vec = 4 (float32, 16x16x4 fragments): row 32 w + 16 rt + j, column
+//     16 sub + 4 g + e at ((((w * 4 + sub) * 2 + rt) * 64 + 16 g + j) * 4 + e;
+//   vec = 8 (16-bit halves, 32x32x16 fragments): row 32 w + i, column
+//     16 ks + 8 q + e at (((w * 4 + ks) * 64 + 32 q + i) * 8 + e.
 constexpr int kGemmRows = 128;
 constexpr int kGemmKC = 64;
 __host__ __device__ inline int64_t dense9_index(int64_t ld, int vec, int64_t r, int64_t k) {
     const int64_t rb = r / kGemmRows, kc = k / kGemmKC;
     const int rr = static_cast<int>(r % kGemmRows), kk = static_cast<int>(k % kGemmKC);
-    const int w = rr / 32, rt = (rr % 32) / 16, j = rr % 16;
-    const int ksub = 4 * vec, nsub = kGemmKC / ksub;
-    const int sub = kk / ksub, g = (kk % ksub) / vec, e = kk % vec;
-    return (rb * (ld / kGemmKC) + kc) * (kGemmRows * kGemmKC) +
-           ((((w * nsub + sub) * 2 + rt) * 64 + 16 * g + j) * vec + e);
+    const int64_t base = (rb * (ld / kGemmKC) + kc) * (kGemmRows * kGemmKC);
+    const int w = rr / 32;
+    if (vec == 8) {
+        const int i = rr % 32, ks = kk / 16, q = (kk % 16) / 8, e = kk % 8;
+        return base + (((w * 4 + ks) * 64 + 32 * q + i) * 8 + e);
+    }
+    const int rt = (rr % 32) / 16, j = rr % 16;
+    const int sub = kk / 16, g = (kk % 16) / 4, e = kk % 4;
+    return base + ((((w * 4 + sub) * 2 + rt) * 64 + 16 * g + j) * 4 + e);
 }
 
 struct Tensor;
@@ -248,6 +253,9 @@ tm_status launch_field(const Problem* p, Epi mode, int64_t B, const float* X, co
 // hi, lo or float32 data of T), row-major, nrow x ld elements.
 tm_status dense9_rows_rowmajor(const Tensor* T, const void* src, int64_t r0, int64_t nrow, void* host);
 int gemm_state_tiles(int64_t B);
+// States of a batched-product call padded to the product's state tiles
+// (float32: 16 x {1, 2, 4, 8}; the split forms: 32 x {1, 2, 4}).
+int64_t gemm_state_pad(const Tensor* T, int64_t B);
 int64_t gemm_splits(const Problem* p);
 tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const float* X,
                                const EpiArgs& e, hipStream_t s);

@@ -9,15 +9,15 @@
 // Precisions (accumulation always float32):
 //   FP32   : v_mfma_f32_16x16x4_f32, A and X in float32;
 //   BF16X3 : A = Ah + Al, X = Xh + Xl in bf16; C = Ah Xh + Ah Xl + Al Xh
-//            with v_mfma_f32_16x16x32_bf16 (the lo*lo term is below the
+//            with v_mfma_f32_32x32x16_bf16 (the lo*lo term is below the
 //            float32 rounding of the result);
 //   FP16X3 : as BF16X3 with fp16 and a power-of-two scale per operator row
 //            (the row maximum maps to 2^13..2^14, far entries stay normal);
 //            the scale is removed in the GEMM epilogue.
 //
 // Work split: a workgroup (4 waves) owns 128 operator rows x all states and
-// one K range (split-K); each wave owns two 16-row MFMA tiles.  K advances in
-// chunks of 64.  The operator is stored blocked (dense9_index): one
+// one K range (split-K); each wave owns 32 rows (two 16-row MFMA tiles in
+// FP32, one 32-row tile in the split forms).  K advances in chunks of 64.  The operator is stored blocked (dense9_index): one
 // workgroup's rows of one chunk are a contiguous 16 KB (16-bit halves, each)
 // or 32 KB (float32) span, read straight into registers, 1 KB per wave load.
 // The right operand is written by k_prep in the same fragment order, one
@@ -68,10 +68,16 @@ struct Elt<1> { using T = __bf16; using V = v8bf; static constexpr int kVec = 8;
 template <>
 struct Elt<2> { using T = _Float16; using V = v8h; static constexpr int kVec = 8; };
 
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// 32x32x16 products of the split forms: lane l holds A row l % 32 and B
+// column l % 32, each at K 8 (l / 32) .. +7; the result element 4 i + j of
+// lane l is row 8 i + 4 (l / 32) + j, column l % 32.  (On this part the
+// 32x32x16 form runs at about 1.8 times the rate of the 16x16x32 form.)
 template <int PREC, typename AV>
-__device__ inline v4f mfma_split(const AV& a, const AV& b, const v4f& c) {
-    if constexpr (PREC == 1) return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-    else return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+__device__ inline v16f mfma_split(const AV& a, const AV& b, const v16f& c) {
+    if constexpr (PREC == 1) return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
 // Software pipeline per K chunk c: the operator rows of chunk c+2 and the X
@@ -83,6 +89,7 @@ __device__ inline v4f mfma_split(const AV& a, const AV& b, const v4f& c) {
 // independent accumulators so that none waits for its predecessor.
 template <int PREC, int NST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_gemm(GemmArgs G) {
+    static_assert(PREC == 0, "the split forms use k_gemm_split");
     using T = typename Elt<PREC>::T;
     using AV = typename Elt<PREC>::V;
     constexpr bool SPLIT = PREC != 0;
@@ -179,41 +186,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                         }
             }
         }
-        if constexpr (PREC != 0) {
-            // the B fragments of both K steps are requested first (the second
-            // step's reads overlap the first step's products), then per K step
-            // the three products as three sweeps over the 2 x NST accumulators,
-            // so that dependent MFMAs are 2 NST instructions apart
-            AV bh[NSUB][NST], bl[NSUB][NST];
-#pragma unroll
-            for (int sub = 0; sub < NSUB; ++sub) {
-#pragma unroll
-                for (int st = 0; st < NST; ++st) {
-                    const int o = ((sub * NST + st) * 64 + lane) * 16;
-                    bh[sub][st] = *reinterpret_cast<const AV*>(xs + o);
-                    bl[sub][st] = *reinterpret_cast<const AV*>(xs + XB + o);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-#pragma unroll
-            for (int sub = 0; sub < NSUB; ++sub) {
-#pragma unroll
-                for (int st = 0; st < NST; ++st)
-#pragma unroll
-                    for (int rt = 0; rt < 2; ++rt) acc[rt][st] = mfma_split<PREC>(hi[sub][rt], bh[sub][st], acc[rt][st]);
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int st = 0; st < NST; ++st)
-#pragma unroll
-                    for (int rt = 0; rt < 2; ++rt) acc[rt][st] = mfma_split<PREC>(hi[sub][rt], bl[sub][st], acc[rt][st]);
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int st = 0; st < NST; ++st)
-#pragma unroll
-                    for (int rt = 0; rt < 2; ++rt) acc[rt][st] = mfma_split<PREC>(lo[sub][rt], bh[sub][st], acc[rt][st]);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
     };
 
     // Near the end the loads repeat the last chunk instead of branching, so
@@ -262,17 +234,170 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     }
 }
 
+// The split forms (BF16X3, FP16X3) on 32x32x16 MFMAs: a workgroup (4 waves)
+// owns 128 operator rows, wave w one 32-row tile, x all NSB 32-state tiles,
+// over one K range.  Per K chunk of 64 (four K steps of 16) a lane loads its
+// operator row's hi and lo halves for each step (16 bytes each, the blocked
+// order: 1 KB per wave load) and the B fragments from the LDS copy of the X
+// chunk.  Same pipeline as k_gemm: operator rows two chunks ahead in a
+// three-slot register ring, the X tile one chunk ahead through a
+// double-buffered LDS tile, one barrier per chunk; per K step three sweeps
+// (hi hi, hi lo, lo hi) over the NSB independent accumulators.
+template <int PREC, int NSB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_gemm_split(GemmArgs G) {
+    static_assert(PREC == 1 || PREC == 2, "split forms only");
+    using T = typename Elt<PREC>::T;
+    using AV = typename Elt<PREC>::V;
+    constexpr int KS = KC / 16;                                // K steps per chunk
+    constexpr int NS = NSB * 32;
+    constexpr int XB = NS * KC * static_cast<int>(sizeof(T));  // bytes of one X array per chunk
+    constexpr int XPIECES = XB / 16;
+    constexpr int XPT = (XPIECES + 255) / 256;
+    constexpr int BUF = 2 * XB;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t rowbase = static_cast<int64_t>(blockIdx.x) * kGemmRows + wave * 32;
+    const int64_t kb = static_cast<int64_t>(blockIdx.y) * G.kper;
+    const int64_t ke = min(kb + G.kper, G.ld);
+    const int nch = static_cast<int>((ke - kb) / KC);
+    const int64_t kc0 = kb / KC;
+
+    const int64_t ablk = (static_cast<int64_t>(blockIdx.x) * (G.ld / KC) + kc0) * kBlockElems;
+    const T* Ah = static_cast<const T*>(G.Ahi) + ablk;
+    const T* Al = static_cast<const T*>(G.Alo) + ablk;
+    const unsigned char* Xh = static_cast<const unsigned char*>(G.Xhi) + kc0 * XB;
+    const unsigned char* Xl = static_cast<const unsigned char*>(G.Xlo) + kc0 * XB;
+
+    v16f acc[NSB];
+#pragma unroll
+    for (int s = 0; s < NSB; ++s)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[s][e] = 0.0f;
+
+    v4u xh_r[XPT], xl_r[XPT];
+    AV ah[3][KS], al[3][KS];
+
+    auto load_x = [&](int c) {
+#pragma unroll
+        for (int q = 0; q < XPT; ++q) {
+            const int idx = threadIdx.x + 256 * q;
+            if (XPIECES % 256 == 0 || idx < XPIECES) {
+                const int64_t off = static_cast<int64_t>(c) * XB + 16 * idx;
+                xh_r[q] = *reinterpret_cast<const v4u*>(Xh + off);
+                xl_r[q] = *reinterpret_cast<const v4u*>(Xl + off);
+            }
+        }
+    };
+    auto store_x = [&](int buf) {
+        unsigned char* base = lds + buf * BUF;
+#pragma unroll
+        for (int q = 0; q < XPT; ++q) {
+            const int idx = threadIdx.x + 256 * q;
+            if (XPIECES % 256 == 0 || idx < XPIECES) {
+                *reinterpret_cast<v4u*>(base + 16 * idx) = xh_r[q];
+                *reinterpret_cast<v4u*>(base + XB + 16 * idx) = xl_r[q];
+            }
+        }
+    };
+    auto load_a = [&](auto slot, int c) {
+        constexpr int S = decltype(slot)::value;
+        const int64_t cb = static_cast<int64_t>(c) * kBlockElems;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int64_t off = cb + static_cast<int64_t>((wave * KS + ks) * 64 + lane) * 8;
+            ah[S][ks] = *reinterpret_cast<const AV*>(Ah + off);
+            al[S][ks] = *reinterpret_cast<const AV*>(Al + off);
+        }
+    };
+    auto compute = [&](auto slot, int buf) {
+        constexpr int S = decltype(slot)::value;
+        const unsigned char* xs = lds + buf * BUF;
+        // the B fragments of two K steps are requested ahead of their products
+#pragma unroll
+        for (int k2 = 0; k2 < KS; k2 += 2) {
+            AV bh[2][NSB], bl[2][NSB];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int st = 0; st < NSB; ++st) {
+                    const int o = (((k2 + u) * NSB + st) * 64 + lane) * 16;
+                    bh[u][st] = *reinterpret_cast<const AV*>(xs + o);
+                    bl[u][st] = *reinterpret_cast<const AV*>(xs + XB + o);
+                }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int ks = k2 + u;
+#pragma unroll
+                for (int st = 0; st < NSB; ++st) acc[st] = mfma_split<PREC>(ah[S][ks], bh[u][st], acc[st]);
+#pragma unroll
+                for (int st = 0; st < NSB; ++st) acc[st] = mfma_split<PREC>(ah[S][ks], bl[u][st], acc[st]);
+#pragma unroll
+                for (int st = 0; st < NSB; ++st) acc[st] = mfma_split<PREC>(al[S][ks], bh[u][st], acc[st]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
+    using S2 = std::integral_constant<int, 2>;
+    const int last = nch - 1;
+    auto step = [&](auto slot, int c) {
+        constexpr int S = decltype(slot)::value;
+        load_x(min(c + 1, last));
+        load_a(std::integral_constant<int, (S + 2) % 3>{}, min(c + 2, last));
+        compute(slot, c & 1);
+        store_x((c + 1) & 1);
+        __syncthreads();
+    };
+    if (nch > 0) {
+        load_x(0);
+        load_a(S0{}, 0);
+        load_a(S1{}, min(1, last));
+        store_x(0);
+        __syncthreads();
+        int c = 0;
+        for (; c + 3 <= nch; c += 3) {
+            step(S0{}, c);
+            step(S1{}, c + 1);
+            step(S2{}, c + 2);
+        }
+        if (c < nch) step(S0{}, c);
+        if (c + 1 < nch) step(S1{}, c + 1);
+    }
+    // element 4 i + j of tile st -> part[split][state 32 st + l % 32][row rowbase + 8 i + 4 (l / 32) + j]
+    float* out = G.part + static_cast<int64_t>(blockIdx.y) * G.bpad * G.rows;
+    const int col = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t r0 = rowbase + 8 * i + 4 * h;
+        float4 sc = make_float4(1.f, 1.f, 1.f, 1.f);
+        if constexpr (PREC == 2) sc = *reinterpret_cast<const float4*>(G.rscale + r0);
+#pragma unroll
+        for (int st = 0; st < NSB; ++st)
+            *reinterpret_cast<float4*>(out + (32 * st + col) * G.rows + r0) =
+                make_float4(acc[st][4 * i] * sc.x, acc[st][4 * i + 1] * sc.y, acc[st][4 * i + 2] * sc.z,
+                            acc[st][4 * i + 3] * sc.w);
+    }
+}
+
 // Right operand from the (padded) stage input Y [B][ld]: (Ms_b / Ms_ref) m,
-// as float32 or split into hi + lo, written in the product's fragment order:
-// chunk kc holds 16 nst states x KC columns, state 16 st + j and column
-// kc KC + 4 vec sub + vec g + e at ((sub nst + st) 64 + 16 g + j) vec + e;
-// states B .. 16 nst - 1 are zero.  One thread per output element.
+// as float32 or split into hi + lo, written in the product's fragment order,
+// chunk kc (KC columns of ns states) after chunk kc - 1:
+//   float32 (16-state tiles, nt = ns / 16): state 16 st + j, column
+//     kc KC + 16 sub + 4 g + e at ((sub nt + st) 64 + 16 g + j) 4 + e;
+//   split forms (32-state tiles, nt = ns / 32): state 32 st + i, column
+//     kc KC + 16 ks + 8 q + e at ((ks nt + st) 64 + 32 q + i) 8 + e;
+// states B .. ns - 1 are zero.  One thread per output element.
 template <int PREC>
-__global__ __launch_bounds__(256) void k_prep(int64_t B, int nst, int64_t ld, int32_t n, const float* __restrict__ Y,
+__global__ __launch_bounds__(256) void k_prep(int64_t B, int64_t ns, int64_t ld, int32_t n, const float* __restrict__ Y,
                                               const float* __restrict__ Ms, float inv_ref,
                                               void* __restrict__ xh, void* __restrict__ xl) {
     constexpr int VEC = Elt<PREC>::kVec;
-    const int64_t ns = 16 * static_cast<int64_t>(nst);
+    constexpr int TW = PREC == 0 ? 16 : 32;  // states per tile
+    const int64_t nt = ns / TW;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= ns * ld) return;
     const int64_t kc = i / (ns * KC);
@@ -281,9 +406,15 @@ __global__ __launch_bounds__(256) void k_prep(int64_t B, int nst, int64_t ld, in
     const int e = static_cast<int>(w % VEC);
     const int ln = static_cast<int>(piece % 64);
     const int64_t q = piece / 64;
-    const int st = static_cast<int>(q % nst), sub = static_cast<int>(q / nst);
-    const int64_t s = 16 * st + (ln & 15);
-    const int64_t k = kc * KC + 4 * VEC * sub + VEC * (ln >> 4) + e;
+    const int64_t st = q % nt, sub = q / nt;
+    int64_t s, k;
+    if constexpr (PREC == 0) {
+        s = 16 * st + (ln & 15);
+        k = kc * KC + 16 * sub + 4 * (ln >> 4) + e;
+    } else {
+        s = 32 * st + (ln & 31);
+        k = kc * KC + 16 * sub + 8 * (ln >> 5) + e;
+    }
     const int64_t b = k / 3;
     const float v = (s < B && b < n) ? Y[s * ld + k] * (Ms[b] * inv_ref) : 0.0f;
     if constexpr (PREC == 0) {
@@ -344,6 +475,21 @@ tm_status launch_gemm_t(const GemmArgs& G, int64_t rowblocks, int64_t splits, hi
 }
 
 template <int PREC>
+tm_status launch_gemm_split(int nsb, const GemmArgs& G, int64_t rowblocks, int64_t splits, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(rowblocks), static_cast<unsigned>(splits));
+    switch (nsb) {
+        case 1: k_gemm_split<PREC, 1><<<grid, 256, 0, s>>>(G); break;
+        case 2: k_gemm_split<PREC, 2><<<grid, 256, 0, s>>>(G); break;
+        case 4: k_gemm_split<PREC, 4><<<grid, 256, 0, s>>>(G); break;
+        default:
+            set_error("batched product: unsupported 32-state tile count %d", nsb);
+            return TM_EINVAL;
+    }
+    TM_TRY_HIP(hipGetLastError());
+    return TM_OK;
+}
+
+template <int PREC>
 tm_status launch_gemm_p(int nst, const GemmArgs& G, int64_t rowblocks, int64_t splits, hipStream_t s) {
     switch (nst) {
         case 1: return launch_gemm_t<PREC, 1>(G, rowblocks, splits, s);
@@ -363,6 +509,12 @@ int gemm_state_tiles(int64_t B) {
     return t <= 1 ? 1 : t <= 2 ? 2 : t <= 4 ? 4 : 8;
 }
 
+int64_t gemm_state_pad(const Tensor* T, int64_t B) {
+    if (T->prec == TM_PREC_FP32) return 16 * gemm_state_tiles(B);
+    const int64_t t = (B + 31) / 32;
+    return 32 * (t <= 1 ? 1 : t <= 2 ? 2 : 4);
+}
+
 int64_t gemm_splits(const Problem* p) {
     const int64_t rowblocks = p->T->rows / kGemmRows;
     const int64_t kchunks = p->T->ld / KC;
@@ -376,7 +528,8 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
                                const EpiArgs& e, hipStream_t s) {
     const Tensor* T = p->T;
     Workspace* w = p->ws.get();
-    TM_REQUIRE(w && w->part && B <= 128 && w->bpad >= 16 * gemm_state_tiles(B), TM_EINVAL,
+    const int64_t ns = gemm_state_pad(T, B);
+    TM_REQUIRE(w && w->part && B <= 128 && w->bpad >= ns, TM_EINVAL,
                "batched product: workspace not prepared for %lld states", static_cast<long long>(B));
     TM_REQUIRE(T->ld % KC == 0 && T->rows % kGemmRows == 0 && T->rows >= T->ld, TM_EINVAL,
                "batched product: operator extent %lld x %lld is not a whole number of blocks",
@@ -385,19 +538,18 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
                "batched product: workspace has no right-operand buffer");
     const int prec = T->prec == TM_PREC_FP32 ? 0 : T->prec == TM_PREC_BF16X3 ? 1 : 2;
     const int64_t ld = T->ld;
-    const int nst = gemm_state_tiles(B);
     // right operand, in fragment order
     {
-        const int64_t cnt = 16 * nst * ld;
+        const int64_t cnt = ns * ld;
         const unsigned grid = static_cast<unsigned>((cnt + 255) / 256);
         const float inv = static_cast<float>(1.0 / p->ms_ref);
         const int32_t n32 = static_cast<int32_t>(p->n);
         if (prec == 0)
-            k_prep<0><<<grid, 256, 0, s>>>(B, nst, ld, n32, X, p->Ms, inv, w->xh, nullptr);
+            k_prep<0><<<grid, 256, 0, s>>>(B, ns, ld, n32, X, p->Ms, inv, w->xh, nullptr);
         else if (prec == 1)
-            k_prep<1><<<grid, 256, 0, s>>>(B, nst, ld, n32, X, p->Ms, inv, w->xh, w->xl);
+            k_prep<1><<<grid, 256, 0, s>>>(B, ns, ld, n32, X, p->Ms, inv, w->xh, w->xl);
         else
-            k_prep<2><<<grid, 256, 0, s>>>(B, nst, ld, n32, X, p->Ms, inv, w->xh, w->xl);
+            k_prep<2><<<grid, 256, 0, s>>>(B, ns, ld, n32, X, p->Ms, inv, w->xh, w->xl);
         TM_TRY_HIP(hipGetLastError());
     }
     GemmArgs G;
@@ -414,9 +566,9 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     G.kper = round_up((ld + splits - 1) / splits, KC);
     const int64_t used_splits = (ld + G.kper - 1) / G.kper;
     const int64_t rowblocks = T->rows / kGemmRows;
-    tm_status st = prec == 0   ? launch_gemm_p<0>(nst, G, rowblocks, used_splits, s)
-                   : prec == 1 ? launch_gemm_p<1>(nst, G, rowblocks, used_splits, s)
-                               : launch_gemm_p<2>(nst, G, rowblocks, used_splits, s);
+    tm_status st = prec == 0   ? launch_gemm_p<0>(static_cast<int>(ns / 16), G, rowblocks, used_splits, s)
+                   : prec == 1 ? launch_gemm_split<1>(static_cast<int>(ns / 32), G, rowblocks, used_splits, s)
+                               : launch_gemm_split<2>(static_cast<int>(ns / 32), G, rowblocks, used_splits, s);
     if (st != TM_OK) return st;
     // X holds (Ms_b / Ms_ref) m (or m itself when Ms is uniform): H_d = -Ms_ref C
     const float scale = static_cast<float>(p->ms_ref);
