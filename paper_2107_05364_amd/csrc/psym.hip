@@ -34,9 +34,10 @@ namespace {
 
 constexpr int TS = kPsTile;
 constexpr int TB = kPsTile * kPsTile;
-constexpr int RG = 256 / TS;       // row groups of a workgroup (one column per lane)
+constexpr int kTileThreads = 256;  // tile pass workgroup
+constexpr int RG = kTileThreads / TS;  // row groups of a workgroup (one column per lane)
 constexpr int RPT = TS / RG;       // rows per thread
-static_assert(TS * RG == 256 && RPT * RG == TS, "tile size must divide the workgroup");
+static_assert(TS * RG == kTileThreads && RPT * RG == TS, "tile size must divide the workgroup");
 constexpr int kFinishThreads = 1024;      // reduction + epilogue workgroup
 constexpr int FG = kFinishThreads / TS;   // slot groups of the reduction
 
@@ -65,7 +66,7 @@ inline int64_t pair_index(int64_t I, int64_t J, int64_t nt) {
 // and subtract them from their own slot, so that minus the slot sum is the
 // whole effective field and the finish kernel has no dependent loads left.
 template <bool STEPPING, bool LOCALF, bool NTL>
-__global__ __launch_bounds__(256) void k_psym_tiles(DevProblem P, const float* __restrict__ tiles,
+__global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const float* __restrict__ tiles,
                                                     const int32_t* __restrict__ pairs, int64_t nt,
                                                     const float* __restrict__ Ms, const float* __restrict__ X,
                                                     int64_t sx, const double* __restrict__ h,
@@ -144,9 +145,9 @@ inline void launch_tiles(dim3 grid, hipStream_t st, bool nt_loads, const DevProb
                          const int32_t* pairs, int64_t nt, const float* Ms, const float* X, int64_t sx,
                          const double* h, const float* Ha, float* part) {
     if (nt_loads)
-        k_psym_tiles<STEPPING, LOCALF, true><<<grid, 256, 0, st>>>(P, tiles, pairs, nt, Ms, X, sx, h, Ha, part);
+        k_psym_tiles<STEPPING, LOCALF, true><<<grid, kTileThreads, 0, st>>>(P, tiles, pairs, nt, Ms, X, sx, h, Ha, part);
     else
-        k_psym_tiles<STEPPING, LOCALF, false><<<grid, 256, 0, st>>>(P, tiles, pairs, nt, Ms, X, sx, h, Ha, part);
+        k_psym_tiles<STEPPING, LOCALF, false><<<grid, kTileThreads, 0, st>>>(P, tiles, pairs, nt, Ms, X, sx, h, Ha, part);
 }
 
 // One workgroup per (target tile K, state): the nt slots of K are contiguous
