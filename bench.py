@@ -147,6 +147,7 @@ def batched_section(tmg, W, torch, attempts=60, profile_iters=20):
                        (tmg.TM_PREC_FP16X3, "fp16x3")):
         T = tmg.Tensor(ctx, geom, prec, tmg.TM_LAYOUT_DENSE9)
         p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+        ksplits, _ = tmg.tm_problem_tune(p.handle, B, 5)  # K splits of the product
         m = torch.as_tensor(m32, device="cuda")
         hd = p.demag(m).cpu().numpy().reshape(B, -1).astype(np.float64)
         err2 = float(np.linalg.norm(hd - ref) / np.linalg.norm(ref))
@@ -167,7 +168,7 @@ def batched_section(tmg, W, torch, attempts=60, profile_iters=20):
                      "mfma_tflops": round(flops / (rhs_ms * 1e-3) / 1e12, 2),
                      "mfma_frac": round(flops / (rhs_ms * 1e-3) / 1e12 / peaks[name], 4),
                      "operator_gbs": round(op_bytes / (rhs_ms * 1e-3) / 1e9, 1),
-                     "hd_rel_err_2norm": err2, "hd_rel_err_max": errm,
+                     "hd_rel_err_2norm": err2, "hd_rel_err_max": errm, "k_splits_tuned": ksplits,
                      "accepted_min": int(st.accepted_min), "rejected": int(st.rejected)}
         p.close()
         T.close()
@@ -222,6 +223,7 @@ def large_section(tmg, W, torch, attempts=20, profile_iters=10, with_oracle=True
     T9 = tmg.Tensor(ctx, geom, tmg.TM_PREC_BF16X3, tmg.TM_LAYOUT_DENSE9)
     p9 = tmg.Problem(ctx, geom, T9, wl.Ms, wl.A, wl.alpha, wl.gamma0)
     m = torch.as_tensor(wl.m0.astype(np.float32), device="cuda")
+    out["batch32_k_splits_tuned"], _ = tmg.tm_problem_tune(p9.handle, 32, 2)
     ms, _ = tmg.tm_profile_field(p9.handle, 32, profile_iters)
     out["batch32_bf16x3_rhs_us"] = round(ms * 1e3, 1)
     out["batch32_bf16x3_operator_gbs"] = round(36.0 * n * n / (ms * 1e-3) / 1e9, 1)

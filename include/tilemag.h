@@ -312,9 +312,13 @@ tm_status tm_problem_shape(const tm_problem* p, int32_t* shape);
 tm_status tm_problem_set_shape(tm_problem* p, int32_t shape);
 
 /* Autotuner: times every shape (iters launches each, B states) and keeps the
- * fastest for p.  Blocking.  chosen / best_ms may be NULL.  For operators
- * other than SYM6 (one kernel shape each) it only times that kernel and
- * reports chosen = -1. */
+ * fastest for p.  Blocking.  chosen / best_ms may be NULL.  For a DENSE9
+ * operator in FP32 / BF16X3 / FP16X3 (the batched product) the candidates
+ * are the numbers of K splits (2, 3, 4, 5, 6, 8) and chosen is the split
+ * count kept; the split count sets the summation order, so results are
+ * bitwise reproducible for a fixed count and independent of the batch.
+ * For the other operators (one kernel shape each) it only times that
+ * kernel and reports chosen = -1. */
 tm_status tm_problem_tune(tm_problem* p, int64_t B, int32_t iters, hipStream_t stream,
                           int32_t* chosen, double* best_ms);
 

@@ -575,7 +575,7 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
                    static_cast<long long>(kMaxGemmStates));
     // the GEMM operand is read in tiles of 16 states: pad the batch
     const int64_t bcap = dense ? gemm_state_pad(T, B) : B;
-    if (p->ws && p->ws->B >= bcap) return TM_OK;
+    if (p->ws && p->ws->B >= bcap && (!dense || p->ws->part_splits >= gemm_splits(p))) return TM_OK;
     const int64_t np = p->np, n = p->n;
     const int64_t sb = bcap * 3 * np * 4;  // one state buffer
     const int64_t nblk = (n + 255) / 256;

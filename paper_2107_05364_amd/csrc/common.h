@@ -169,6 +169,7 @@ struct Problem {
     double* x_w = nullptr;      // per face A S/d (exchange energy), same CSR
     int64_t nnz = 0;
     int shape = -1;             // field-kernel launch shape (-1: default for n)
+    int gemm_splits = 0;        // batched product: K splits (0: default for the operator)
     int64_t bytes = 0;          // device bytes owned by the problem
     std::unique_ptr<Workspace> ws;
     DevProblem dev() const;

@@ -518,9 +518,10 @@ int64_t gemm_state_pad(const Tensor* T, int64_t B) {
 int64_t gemm_splits(const Problem* p) {
     const int64_t rowblocks = p->T->rows / kGemmRows;
     const int64_t kchunks = p->T->ld / KC;
-    // about one workgroup per CU (one wave per SIMD)
+    // about one workgroup per CU (one wave per SIMD), unless tuned
     int64_t s = (256 + rowblocks - 1) / rowblocks;
     if (s > 1 && rowblocks * s > 256 + rowblocks / 2) s -= 1;
+    if (p->gemm_splits > 0) s = p->gemm_splits;
     return std::max<int64_t>(1, std::min<int64_t>(s, std::min<int64_t>(kchunks, 16)));
 }
 
@@ -562,7 +563,9 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     G.Xlo = w->xl;
     G.part = w->part;
     G.rows = T->rows;
-    const int64_t splits = w->part_splits;
+    const int64_t splits = gemm_splits(p);
+    TM_REQUIRE(splits <= w->part_splits, TM_EINVAL, "batched product: workspace holds %lld K splits, %lld asked",
+               static_cast<long long>(w->part_splits), static_cast<long long>(splits));
     G.kper = round_up((ld + splits - 1) / splits, KC);
     const int64_t used_splits = (ld + G.kper - 1) / G.kper;
     const int64_t rowblocks = T->rows / kGemmRows;

@@ -468,6 +468,33 @@ extern "C" tm_status tm_problem_tune(tm_problem* pp, int64_t B, int32_t iters, h
     TM_TRY_HIP(hipSetDevice(p->ctx->device));
     tm_status st = ensure_workspace(p, B);
     if (st != TM_OK) return st;
+    if (p->T->layout == TM_LAYOUT_DENSE9 && p->T->prec != TM_PREC_FP64) {
+        // the batched product: the number of K splits (split-K workgroups
+        // against the partial-sum pass), each candidate timed, the fastest kept
+        static const int kCand[] = {2, 3, 4, 5, 6, 8};
+        const int keep = p->gemm_splits;
+        int best = 0;
+        double best_t = 1e30;
+        for (int c : kCand) {
+            if (c > p->T->ld / kGemmKC) continue;
+            p->gemm_splits = c;
+            double ms = 0.0;
+            st = ensure_workspace(p, B);
+            if (st == TM_OK) st = time_field(p, B, 0, iters, s, &ms);
+            if (st != TM_OK) {
+                p->gemm_splits = keep;
+                return st;
+            }
+            if (ms < best_t) {
+                best_t = ms;
+                best = c;
+            }
+        }
+        p->gemm_splits = best;
+        if (chosen) *chosen = best;
+        if (best_ms) *best_ms = best_t;
+        return TM_OK;
+    }
     if (p->T->layout != TM_LAYOUT_SYM6) {
         // launch shapes belong to the dense SYM6 kernel; other layouts have one
         double ms = 0.0;

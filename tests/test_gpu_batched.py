@@ -96,6 +96,29 @@ def test_batched_state_is_batch_invariant(tmg, ctx, prec):
     close(g, T, p)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tuned_split_count(tmg, ctx, orc, prec):
+    """tm_problem_tune on the batched product keeps one of its K-split
+    candidates; after tuning H_d still meets the oracle tolerance, a repeat
+    is bitwise identical, and a state is bit-identical alone and in the batch
+    (the split count fixes the summation order)."""
+    wl = W.thin_film(nx=40, ny=10)
+    g, T, p = build(tmg, ctx, wl.centers, wl.sizes, store=prec, layout=tmg.TM_LAYOUT_DENSE9)
+    m = np.stack([W.film_texture(wl.centers, 200e-9, k) for k in range(24)]).astype(np.float32)
+    chosen, ms = tmg.tm_problem_tune(p.handle, 24, 2)
+    _say("%s: %d K splits, %.1f us" % (NAMES[prec], chosen, ms * 1e3))
+    assert chosen in (2, 3, 4, 5, 6, 8) and ms > 0
+    H = p.demag(device_state(m)).cpu().numpy()
+    P = orc.Problem(wl.centers, wl.sizes, 8.0e5, 1.3e-11, 0.5)
+    for k in (0, 11, 23):
+        e2, emax = rel_errors(H[k], P.demag(m[k].astype(np.float64)))
+        assert e2 <= TOL[prec] and emax <= TOL[prec], (k, e2, emax)
+    assert np.array_equal(H, p.demag(device_state(m)).cpu().numpy())
+    one = p.demag(device_state(m[5:6])).cpu().numpy()
+    assert np.array_equal(H[5], one[0])
+    close(g, T, p)
+
+
 def test_batched_dp45_matches_matvec_path(tmg, ctx):
     """DP45 on 8 states to a common end time: the FP32 GEMM path and the FP32
     matvec path (different summation orders) agree within the float32
