@@ -325,7 +325,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                     bh[u][st] = *reinterpret_cast<const AV*>(xs + o);
                     bl[u][st] = *reinterpret_cast<const AV*>(xs + XB + o);
                 }
-            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int ks = k2 + u;
@@ -336,7 +335,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
                 for (int st = 0; st < NSB; ++st) acc[st] = mfma_split<PREC>(al[S][ks], bh[u][st], acc[st]);
             }
-            __builtin_amdgcn_sched_barrier(0);
+        }
+        // the next chunks' global loads (issued above in program order) are
+        // spread over the products so that they co-issue with the MFMAs
+#pragma unroll
+        for (int i = 0; i < 2 * KS * (XPT + 1); ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
         }
     };
 
