@@ -186,6 +186,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                         }
             }
         }
+        // the next chunks' global loads (issued above in program order) are
+        // spread over the products so that they co-issue with the MFMAs
+        constexpr int NMF = NSUB * 4 * NST * 2;    // MFMAs per chunk
+        constexpr int NVM = NSUB * 2 + XPT;        // global loads per chunk
+#pragma unroll
+        for (int i = 0; i < NVM; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, NMF / NVM, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);          // VMEM read
+        }
     };
 
     // Near the end the loads repeat the last chunk instead of branching, so
