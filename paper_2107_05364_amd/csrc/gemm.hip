@@ -347,10 +347,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         }
         // the next chunks' global loads (issued above in program order) are
         // spread over the products so that they co-issue with the MFMAs
+        constexpr int NMF = 3 * KS * NSB;      // MFMAs per chunk
+        constexpr int NVM = 2 * KS + 2 * XPT;  // global loads per chunk
 #pragma unroll
-        for (int i = 0; i < 2 * KS * (XPT + 1); ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
+        for (int i = 0; i < NVM; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, NMF / NVM > 0 ? NMF / NVM : 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);                            // VMEM read
         }
     };
 
