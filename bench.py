@@ -223,7 +223,7 @@ def large_section(tmg, W, torch, attempts=20, profile_iters=10, with_oracle=True
     T9 = tmg.Tensor(ctx, geom, tmg.TM_PREC_BF16X3, tmg.TM_LAYOUT_DENSE9)
     p9 = tmg.Problem(ctx, geom, T9, wl.Ms, wl.A, wl.alpha, wl.gamma0)
     m = torch.as_tensor(wl.m0.astype(np.float32), device="cuda")
-    out["batch32_k_splits_tuned"], _ = tmg.tm_problem_tune(p9.handle, 32, 2)
+    out["batch32_k_splits_tuned"], _ = tmg.tm_problem_tune(p9.handle, 32, 5)
     ms, _ = tmg.tm_profile_field(p9.handle, 32, profile_iters)
     out["batch32_bf16x3_rhs_us"] = round(ms * 1e3, 1)
     out["batch32_bf16x3_operator_gbs"] = round(36.0 * n * n / (ms * 1e-3) / 1e9, 1)
