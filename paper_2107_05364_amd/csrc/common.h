@@ -39,8 +39,8 @@ void set_error(const char* fmt, ...);
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // Padded tile count of state vectors and of the dense operator: a multiple of
-// 128, so that the dense operator's K extent 3 np is a whole number of the
-// batched product's 128-element chunks.
+// 128, so that the dense operator's rows and K extent 3 np are whole numbers
+// of the batched product's 128-row blocks and 64-element chunks.
 inline int64_t padded_tiles(int64_t n) { return round_up(n, 128); }
 
 // Stored order of the DENSE9 operator in FP32 / BF16X3 / FP16X3 (the MFMA
