@@ -62,6 +62,12 @@ def test_batched_demag_film_128_states(tmg, ctx, film_ref, prec):
     e2, emax = rel_errors(got, H)
     _say("  %s: rel2 %.3e relmax %.3e" % (NAMES[prec], e2, emax))
     assert e2 <= TOL[prec] and emax <= TOL[prec]
+    # and with the split count the benchmark tunes
+    splits, _ = tmg.tm_problem_tune(p.handle, 128, 3)
+    got = p.demag(device_state(m)).cpu().numpy()
+    e2, emax = rel_errors(got, H)
+    _say("  %s, %d K splits: rel2 %.3e relmax %.3e" % (NAMES[prec], splits, e2, emax))
+    assert e2 <= TOL[prec] and emax <= TOL[prec]
     close(g, T, p)
 
 

@@ -74,6 +74,8 @@ def test_large_slab_batched_bf16x3_rows(tmg, ctx, orc, slab):
     g = tmg.Geometry(ctx, wl.centers, wl.sizes)
     T = tmg.Tensor(ctx, g, tmg.TM_PREC_BF16X3, tmg.TM_LAYOUT_DENSE9)
     p = tmg.Problem(ctx, g, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+    splits, _ = tmg.tm_problem_tune(p.handle, 32, 5)  # as the benchmark does
+    _say("large slab bf16x3: %d K splits" % splits)
     m = wl.m0.astype(np.float32)
     Hd = p.demag(device_state(m)).cpu().numpy()
     for k in (0, 17, 31):
