@@ -466,10 +466,15 @@ def sp3_section(tmg, W, torch, ns=(4, 6, 8, 10, 12, 16, 20)):
     return out
 
 
-def peaks_section(torch):
-    """Achievable rates on this device for context: a 4 GiB device copy
-    (read + write bytes) and library GEMMs (torch.mm) in bf16 and fp32."""
+def peaks_section(torch, tmg):
+    """Achievable rates on this device for context: the library's own stream
+    read (2 GiB) and register-only MFMA loops, a 4 GiB device copy (read +
+    write bytes) and library GEMMs (torch.mm) in bf16 and fp32."""
     out = {}
+    rd, mb, mf = tmg.tm_measure_peaks(0, 2 << 30)
+    out["stream_read_gbs"] = round(rd, 1)
+    out["mfma_bf16_32x32x16_tflops"] = round(mb, 1)
+    out["mfma_fp32_16x16x4_tflops"] = round(mf, 1)
     src = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -696,7 +701,7 @@ def main():
     if not args.no_serving:
         rec["serving"] = serving_section(tmg, W, torch, count=args.serving_count)
     if not args.no_peaks:
-        rec["achievable_peaks"] = peaks_section(torch)
+        rec["achievable_peaks"] = peaks_section(torch, tmg)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(rec), flush=True)

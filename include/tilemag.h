@@ -86,6 +86,17 @@ const char* tm_last_error(void);
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t tm_version(void);
 
+/* Achievable rates of device `device`, measured with the library's own
+ * kernels (context for the roofline fractions, which use published peaks):
+ * a streaming read of a zero-filled read_bytes buffer (1 MiB .. 16 GiB,
+ * allocated and freed by the call) in GB/s, and register-only loops of the
+ * 32x32x16 bf16 and 16x16x4 float32 MFMA instructions the batched product
+ * issues, in TFLOP/s.  Output pointers may be NULL (that measurement is
+ * skipped).  Blocking; uses the device's null stream.  TM_EINVAL for a size
+ * out of range, TM_EDEVICE on a HIP error. */
+tm_status tm_measure_peaks(int32_t device, int64_t read_bytes, double* read_gbs, double* mfma_bf16_tflops,
+                           double* mfma_fp32_tflops);
+
 /* Opens device `device` (HIP ordinal) and creates a context that owns the
  * tensor cache and the admission budget (default: free device memory at
  * creation minus 4 GiB).  TM_EDEVICE if the device cannot be opened. */

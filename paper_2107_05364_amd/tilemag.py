@@ -30,7 +30,7 @@ _STATUS_NAMES = {0: "TM_OK", -1: "TM_EINVAL", -2: "TM_ENOMEM", -3: "TM_EDEVICE",
 
 # every symbol the header declares
 EXPORTS = [
-    "tm_last_error", "tm_version", "tm_init", "tm_finalize", "tm_set_memory_budget",
+    "tm_last_error", "tm_version", "tm_measure_peaks", "tm_init", "tm_finalize", "tm_set_memory_budget",
     "tm_geometry_create", "tm_geometry_hash", "tm_geometry_info", "tm_geometry_destroy",
     "tm_tensor_assemble", "tm_tensor_threshold", "tm_tensor_sparse_info", "tm_tensor_sparse_get",
     "tm_tensor_get", "tm_tensor_rows", "tm_tensor_bytes", "tm_tensor_release",
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     sig = {
         "tm_last_error": (C.c_char_p, []),
         "tm_version": (i32, []),
+        "tm_measure_peaks": (i32, [i32, i64, P(d), P(d), P(d)]),
         "tm_init": (i32, [i32, P(vp)]),
         "tm_finalize": (i32, [vp]),
         "tm_set_memory_budget": (i32, [vp, i64]),
@@ -167,6 +168,13 @@ def tm_last_error() -> str:
 
 def tm_version() -> int:
     return int(load().tm_version())
+
+
+def tm_measure_peaks(device: int = 0, read_bytes: int = 2 << 30):
+    """(stream read GB/s, bf16 32x32x16 MFMA TFLOP/s, fp32 16x16x4 MFMA TFLOP/s)."""
+    r, b, f = C.c_double(), C.c_double(), C.c_double()
+    _check(load().tm_measure_peaks(int(device), int(read_bytes), C.byref(r), C.byref(b), C.byref(f)))
+    return r.value, b.value, f.value
 
 
 last_error = tm_last_error
