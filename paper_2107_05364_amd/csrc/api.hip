@@ -69,7 +69,7 @@ Workspace::~Workspace() {
     float* fl[] = {y, ya, yb, y5, k[0], k[1], k[2], k[3], k[4], k[5], k[6], Ha, hd, part};
     for (float* p : fl)
         if (p) (void)hipFree(p);
-    void* vp[] = {xh, xl, t, h, dt, errp, dmxp, steps, rejected, flags, acc, params, esum, diag};
+    void* vp[] = {xh, xl, t, h, dt, errp, dmxp, snap, steps, rejected, flags, acc, params, esum, diag};
     for (void* p : vp)
         if (p) (void)hipFree(p);
     if (host_params) (void)hipHostFree(host_params);
@@ -590,7 +590,7 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
     const bool psym = T->layout == TM_LAYOUT_PSYM6;
     if (psym) pbytes = psym_partial_floats(T, bcap) * 4;
     const int64_t dbytes = bcap * (nblk * 6 + 4) * 8;  // diagnostics partials + energies
-    int64_t bytes = 12 * sb + bcap * 12 + bcap * (8 * 7 + 8 * 2 + 4 * 2) + 16 * bcap * n + 64 +
+    int64_t bytes = 12 * sb + bcap * 12 + bcap * (8 * 7 + 8 * 2 + 4 * 2 + 8 * kSnapStride) + 16 * bcap * n + 64 +
                     RP_COUNT * 8 + nblk * bcap * 32 + xbytes + pbytes + dbytes;
     {
         std::lock_guard<std::mutex> lk(p->ctx->mu);
@@ -627,6 +627,7 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
     w->pstride = n;  // at most one partial per target tile (one tile per block)
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->errp), bcap * n * 8);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->dmxp), bcap * n * 8);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->snap), bcap * kSnapStride * 8);
 
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->steps), bcap * 8);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->rejected), bcap * 8);

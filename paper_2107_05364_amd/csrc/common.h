@@ -199,6 +199,7 @@ struct Workspace {
     double* errp = nullptr;   // [B][pstride] per-block maxima of the scaled error
     double* dmxp = nullptr;   // [B][pstride] per-block maxima of |dm/dt|
     int64_t pstride = 0;
+    double* snap = nullptr;   // [B][kSnapStride] control values as the last stage saw them
 
     int64_t* steps = nullptr;
     int64_t* rejected = nullptr;
@@ -224,6 +225,10 @@ struct Workspace {
 
 tm_status ensure_workspace(Problem* p, int64_t B);
 constexpr int kGraphSteps = 16;
+// A state's control snapshot: h, t and dt, then the step counts and the
+// flags as 64-bit integer bit patterns.
+enum SnapSlot : int { SN_H = 0, SN_T = 1, SN_DT = 2, SN_STEPS = 3, SN_REJ = 4, SN_FLAGS = 5 };
+constexpr int kSnapStride = 8;
 
 // Kernel launchers (fieldstep.hip).
 enum class Epi : int { HD = 0, HEFF = 1, DMDT = 2, STAGE = 3, RK4_FINAL = 4, DP_LAST = 5 };
@@ -244,6 +249,15 @@ struct EpiArgs {
     double* dmxp;
     int64_t pstride;
     int32_t renorm;
+    // DP_LAST: the control values of each state (t, dt, step counts, flags;
+    // h above) and where the first block of the state copies them for the
+    // commit pass, [B][kSnapStride]
+    const double* t;
+    const double* dt;
+    const int64_t* steps;
+    const int64_t* rejected;
+    const int32_t* flags;
+    double* snap;
 };
 
 // H (or a stage) for B states whose inputs X are padded internal buffers.

@@ -219,11 +219,23 @@ __device__ Decision dp_decide(const double* __restrict__ prm, double e, double d
 }
 
 // Last stage: store the block's maxima (already reduced over the wave) for
-// the commit pass, which reduces them per state in fixed order.
+// the commit pass, which reduces them per state.  The first block of each
+// state also copies the state's control values, so that every block of the
+// commit decides from the same inputs while one of them rewrites them.
 __device__ inline void report_partials(const EpiArgs& E, double rmax, double dmax, int lane) {
     if (lane == 0) {
-        E.errp[blockIdx.y * E.pstride + blockIdx.x] = rmax;
-        E.dmxp[blockIdx.y * E.pstride + blockIdx.x] = dmax;
+        const int64_t s = blockIdx.y;
+        E.errp[s * E.pstride + blockIdx.x] = rmax;
+        E.dmxp[s * E.pstride + blockIdx.x] = dmax;
+        if (blockIdx.x == 0) {
+            double* c = E.snap + s * kSnapStride;
+            c[SN_H] = E.h[s];
+            c[SN_T] = E.t[s];
+            c[SN_DT] = E.dt[s];
+            c[SN_STEPS] = __longlong_as_double(static_cast<long long>(E.steps[s]));
+            c[SN_REJ] = __longlong_as_double(static_cast<long long>(E.rejected[s]));
+            c[SN_FLAGS] = __longlong_as_double(static_cast<long long>(E.flags[s]));
+        }
     }
 }
 

@@ -202,45 +202,46 @@ __global__ void k_control_rk4(int64_t B, const double* __restrict__ prm, double*
     h[s] = done ? 0.0 : (t_end > 0.0 ? fmin(dn, t_end - tn) : dn);
 }
 
-// Accept / reject of a Dormand-Prince attempt: one block per state reduces
-// the state's per-block error and |dm/dt| partials of the last stage (fixed
-// order), decides (dp_decide), writes the state's step control and applies
-// the step to every tile -- on acceptance y <- y5 (renormalised), k1 <- k7 --
+// Accept / reject of a Dormand-Prince attempt.  Block (x, s) takes tiles
+// [x kCommitTiles, (x + 1) kCommitTiles) of state s: it reduces the state's
+// per-block error and |dm/dt| partials of the last stage, decides
+// (dp_decide) from the control values the last stage copied (all blocks of a
+// state decide alike; block 0 writes the new control values), and applies
+// the step to its tiles -- on acceptance y <- y5 (renormalised), k1 <- k7 --
 // then forms the next attempt's stage-2 input y + h a21 k1.  No block
 // depends on another.
-constexpr int kCommitThreads = 1024;
-constexpr int kCommitCached = 4;  // tiles per thread whose data is loaded before the decision
+constexpr int kCommitThreads = 256;
+constexpr int kCommitTiles = kCommitThreads;  // one tile per thread
 
 __global__ __launch_bounds__(kCommitThreads) void k_commit(
     int32_t n, int64_t np, float* __restrict__ y, float* __restrict__ k1,
     const float* __restrict__ y5, const float* __restrict__ k7, float* __restrict__ ya,
     const double* __restrict__ errp, const double* __restrict__ dmxp, int64_t pstride, int64_t nblk,
-    double* __restrict__ t, double* __restrict__ h, double* __restrict__ dt,
-    int64_t* __restrict__ steps, int64_t* __restrict__ rejected, int32_t* __restrict__ flags,
-    int32_t* __restrict__ acc, const double* __restrict__ prm) {
+    const double* __restrict__ snap, double* __restrict__ t, double* __restrict__ h,
+    double* __restrict__ dt, int64_t* __restrict__ steps, int64_t* __restrict__ rejected,
+    int32_t* __restrict__ flags, int32_t* __restrict__ acc, const double* __restrict__ prm) {
     constexpr int NW = kCommitThreads / 64;
     __shared__ double r0[NW], r1[NW];
-    const int64_t s = blockIdx.x;
+    const int64_t s = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // everything the decision does not change is loaded first, so that its
-    // latency overlaps the reduction: the control values and, for the first
-    // kCommitCached * kCommitThreads tiles, both candidate states and slopes
-    const double h0 = h[s], t0 = t[s], dt0 = dt[s];
-    const int64_t st0 = steps[s], rj0 = rejected[s];
-    const int32_t f0 = flags[s];
-    float cy[kCommitCached][3], cy5[kCommitCached][3], ck1[kCommitCached][3], ck7[kCommitCached][3];
+    // latency overlaps the reduction: the control values and the tile's
+    // candidate states and slopes
+    const double* c = snap + s * kSnapStride;
+    const double h0 = c[SN_H], t0 = c[SN_T], dt0 = c[SN_DT];
+    const int64_t st0 = __double_as_longlong(c[SN_STEPS]), rj0 = __double_as_longlong(c[SN_REJ]);
+    const int32_t f0 = static_cast<int32_t>(__double_as_longlong(c[SN_FLAGS]));
+    const int64_t a = static_cast<int64_t>(blockIdx.x) * kCommitTiles + threadIdx.x;
+    const bool mine = a < n;
+    const int64_t o = s * 3 * np + 3 * a;
+    float vy[3] = {}, vy5[3] = {}, vk1[3] = {}, vk7[3] = {};
+    if (mine) {
 #pragma unroll
-    for (int i = 0; i < kCommitCached; ++i) {
-        const int64_t a = threadIdx.x + static_cast<int64_t>(i) * kCommitThreads;
-        if (a < n) {
-            const int64_t o = s * 3 * np + 3 * a;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                cy[i][c] = y[o + c];
-                cy5[i][c] = y5[o + c];
-                ck1[i][c] = k1[o + c];
-                ck7[i][c] = k7[o + c];
-            }
+        for (int q = 0; q < 3; ++q) {
+            vy[q] = y[o + q];
+            vy5[q] = y5[o + q];
+            vk1[q] = k1[o + q];
+            vk7[q] = k7[o + q];
         }
     }
     double e = 0.0, dm = 0.0;
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(
         r0[wave] = e;
         r1[wave] = dm;
     }
-    __syncthreads();  // also: every thread has read the old control values
+    __syncthreads();
     e = r0[0];
     dm = r1[0];
 #pragma unroll
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(
         dm = fmax(dm, r1[w]);
     }
     const Decision d = dp_decide(prm, e, dm, h0, t0, dt0, st0, rj0, f0);
-    if (threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         t[s] = d.t;
         dt[s] = d.dt;
         h[s] = d.h;
@@ -275,40 +276,26 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(
         flags[s] = d.flags;
         acc[s] = d.acc;
     }
+    if (!mine) return;
     const bool renorm = prm[RP_RENORM] != 0.0;
     const float hh = static_cast<float>(d.h) * (1.0f / 5.0f);
-    auto apply = [&](int64_t a, const float* vy, const float* vy5, const float* vk1, const float* vk7) {
-        const int64_t o = s * 3 * np + 3 * a;
-        float v0, v1, v2, g0, g1, g2;
-        if (d.acc) {
-            v0 = vy5[0]; v1 = vy5[1]; v2 = vy5[2];
-            if (renorm) {
-                const float r = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
-                v0 *= r; v1 *= r; v2 *= r;
-            }
-            g0 = vk7[0]; g1 = vk7[1]; g2 = vk7[2];
-            y[o] = v0; y[o + 1] = v1; y[o + 2] = v2;
-            k1[o] = g0; k1[o + 1] = g1; k1[o + 2] = g2;
-        } else {
-            v0 = vy[0]; v1 = vy[1]; v2 = vy[2];
-            g0 = vk1[0]; g1 = vk1[1]; g2 = vk1[2];
+    float v0, v1, v2, g0, g1, g2;
+    if (d.acc) {
+        v0 = vy5[0]; v1 = vy5[1]; v2 = vy5[2];
+        if (renorm) {
+            const float r = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+            v0 *= r; v1 *= r; v2 *= r;
         }
-        ya[o] = v0 + hh * g0;
-        ya[o + 1] = v1 + hh * g1;
-        ya[o + 2] = v2 + hh * g2;
-    };
-#pragma unroll
-    for (int i = 0; i < kCommitCached; ++i) {
-        const int64_t a = threadIdx.x + static_cast<int64_t>(i) * kCommitThreads;
-        if (a < n) apply(a, cy[i], cy5[i], ck1[i], ck7[i]);
+        g0 = vk7[0]; g1 = vk7[1]; g2 = vk7[2];
+        y[o] = v0; y[o + 1] = v1; y[o + 2] = v2;
+        k1[o] = g0; k1[o + 1] = g1; k1[o + 2] = g2;
+    } else {
+        v0 = vy[0]; v1 = vy[1]; v2 = vy[2];
+        g0 = vk1[0]; g1 = vk1[1]; g2 = vk1[2];
     }
-    for (int64_t a = threadIdx.x + static_cast<int64_t>(kCommitCached) * kCommitThreads; a < n;
-         a += kCommitThreads) {
-        const int64_t o = s * 3 * np + 3 * a;
-        const float vy[3] = {y[o], y[o + 1], y[o + 2]}, vy5[3] = {y5[o], y5[o + 1], y5[o + 2]};
-        const float vk1[3] = {k1[o], k1[o + 1], k1[o + 2]}, vk7[3] = {k7[o], k7[o + 1], k7[o + 2]};
-        apply(a, vy, vy5, vk1, vk7);
-    }
+    ya[o] = v0 + hh * g0;
+    ya[o + 1] = v1 + hh * g1;
+    ya[o + 2] = v2 + hh * g2;
 }
 
 // Energy terms per state in float64: block partial sums, then a fixed-order
@@ -527,10 +514,12 @@ int64_t last_stage_blocks(const Problem* p) {
 }
 
 tm_status launch_commit(const Problem* p, Workspace* w, int64_t B, hipStream_t s) {
-    k_commit<<<static_cast<unsigned>(B), kCommitThreads, 0, s>>>(
+    const dim3 grid(static_cast<unsigned>((p->n + kCommitTiles - 1) / kCommitTiles),
+                    static_cast<unsigned>(B));
+    k_commit<<<grid, kCommitThreads, 0, s>>>(
         static_cast<int32_t>(p->n), p->np, w->y, w->k[0], w->y5, w->k[6], w->ya, w->errp, w->dmxp,
-        w->pstride, last_stage_blocks(p), w->t, w->h, w->dt, w->steps, w->rejected, w->flags, w->acc,
-        w->params);
+        w->pstride, last_stage_blocks(p), w->snap, w->t, w->h, w->dt, w->steps, w->rejected,
+        w->flags, w->acc, w->params);
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
 }

@@ -76,6 +76,12 @@ EpiArgs stage_args(Workspace* w, float* kout, const float* const* kprev, int npr
     e.errp = w->errp;
     e.dmxp = w->dmxp;
     e.pstride = w->pstride;
+    e.t = w->t;
+    e.dt = w->dt;
+    e.steps = w->steps;
+    e.rejected = w->rejected;
+    e.flags = w->flags;
+    e.snap = w->snap;
     return e;
 }
 
