@@ -53,9 +53,10 @@ def parse():
                     help="counter runs: one 1 GiB device copy (calibration) and the stage kernel "
                          "of the film workload only")
     ap.add_argument("--serving-count", type=int, default=24)
-    ap.add_argument("--layout", choices=["psym6", "sym6"], default="psym6",
-                    help="operator layout of the headline run: pair-symmetric (the film's tiles "
-                         "are identical) or six planes")
+    ap.add_argument("--layout", choices=["psym4", "psym6", "sym6"], default="psym4",
+                    help="operator layout of the headline run: pair-symmetric with four planes "
+                         "(the film is one layer of identical tiles), pair-symmetric with six "
+                         "planes, or six planes")
     return ap.parse_args()
 
 
@@ -67,7 +68,11 @@ KERNELS = {
     "psym6": (["paper_2107_05364_amd/csrc/psym.hip", "paper_2107_05364_amd/csrc/epilogue.h",
                "paper_2107_05364_amd/csrc/common.h"],
               os.path.join(ROOT, "profiles", "k_psym_tiles_film_N2500_counters.md")),
+    "psym4": (["paper_2107_05364_amd/csrc/psym.hip", "paper_2107_05364_amd/csrc/epilogue.h",
+               "paper_2107_05364_amd/csrc/common.h"],
+              os.path.join(ROOT, "profiles", "k_psym_tiles_4planes_film_N2500_counters.md")),
 }
+LAYOUT_CODE = {"sym6": 0, "psym6": 3, "psym4": 4}  # tm_layout values
 
 
 def kernel_source_hash(layout):
@@ -323,12 +328,19 @@ def sp4_sweep_section(tmg, W, torch, attempts=300):
         pp = tmg.Problem(ctx, geom, Tp, wl.Ms, wl.A, wl.alpha, wl.gamma0)
         msp, nbp = tmg.tm_profile_field(pp.handle, 1, 50)
         row.update({"psym6_field_us": round(msp * 1e3, 2), "psym6_steps_per_s": round(steps_per_s(pp), 1)})
-        rows.append(row)
         pp.close()
         Tp.close()
+        # and with its four planes (one layer: xz = yz = 0)
+        T4 = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM4)
+        p4 = tmg.Problem(ctx, geom, T4, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+        ms4, _ = tmg.tm_profile_field(p4.handle, 1, 50)
+        row.update({"psym4_field_us": round(ms4 * 1e3, 2), "psym4_steps_per_s": round(steps_per_s(p4), 1)})
+        rows.append(row)
+        p4.close()
+        T4.close()
         geom.close()
         ctx.close()
-    return {"workload": "SP4 film [20n,5n,1] tiles, n=1..9, one state, DP45, fp32 SYM6 (and PSYM6)", "sizes": rows}
+    return {"workload": "SP4 film [20n,5n,1] tiles, n=1..9, one state, DP45, fp32 SYM6 (and PSYM6, PSYM4)", "sizes": rows}
 
 
 def threshold_section(tmg, W, torch, attempts=300, fracs=(0.2, 0.4, 0.7)):
@@ -543,9 +555,11 @@ def serving_section(tmg, W, torch, count=24, n_max=4000, max_steps=3000, slots=8
         if key not in cache:
             g = tmg.Geometry(ctx, r.centers, r.sizes)
             # the same operator layout the server picks: pair-symmetric for
-            # identical tiles above 1200 tiles
+            # identical tiles above 1200 tiles, with four planes for one layer
             same = bool(np.all(r.sizes == r.sizes[0])) and r.centers.shape[0] > 1200
-            T = tmg.Tensor(ctx, g, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM6 if same else tmg.TM_LAYOUT_SYM6)
+            layer = bool(np.all(r.centers[:, 2] == r.centers[0, 2]))
+            lay = (tmg.TM_LAYOUT_PSYM4 if layer else tmg.TM_LAYOUT_PSYM6) if same else tmg.TM_LAYOUT_SYM6
+            T = tmg.Tensor(ctx, g, tmg.TM_PREC_FP32, lay)
             cache[key] = (g, T)
         g, T = cache[key]
         p = tmg.Problem(ctx, g, T, Ms, A, alpha)
@@ -603,8 +617,8 @@ def main():
     geom = tmg.Geometry(ctx, wl.centers, wl.sizes)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    psym = args.layout == "psym6"
-    T = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM6 if psym else tmg.TM_LAYOUT_SYM6)
+    psym = args.layout in ("psym4", "psym6")
+    T = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, LAYOUT_CODE[args.layout])
     torch.cuda.synchronize()
     asm_ms = (time.perf_counter() - t0) * 1e3
     p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
@@ -645,7 +659,8 @@ def main():
     eval_ms, _ = tmg.tm_profile_field(p.handle, 1, args.profile_iters)
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9
     if psym:
-        kname = "k_psym_tiles<true,true,%s>" % ("true" if T.nbytes > (192 << 20) else "false")
+        kname = "k_psym_tiles<true,true,%s,%d>" % ("true" if T.nbytes > (192 << 20) else "false",
+                                                   4 if args.layout == "psym4" else 6)
         kdesc = (" (pair-symmetric tile pass of the demag product; the slot sum and epilogue run in "
                  "a second launch, included in field_evaluation_us)")
     else:

@@ -66,9 +66,12 @@ typedef enum {
                              ordered as the product loads them (read back row-major) */
     TM_LAYOUT_BSR6 = 2,   /* thresholded operator: block-sparse rows of 6-component blocks
                              (made by tm_tensor_threshold only) */
-    TM_LAYOUT_PSYM6 = 3   /* pair-symmetric operator of a mesh of identical tiles: only the
+    TM_LAYOUT_PSYM6 = 3,  /* pair-symmetric operator of a mesh of identical tiles: only the
                              upper triangle of 32x32-block tiles, [pairs][6][32][32], since
                              N^{ab} = N^{ba} there (about half the SYM6 bytes) */
+    TM_LAYOUT_PSYM4 = 4   /* PSYM6 for a single layer of identical tiles (one z for every
+                             centre): xz and yz vanish there, so the tiles hold the four
+                             planes (xx,xy,yy,zz), [pairs][4][32][32] (two thirds of PSYM6) */
 } tm_layout;
 
 typedef enum { TM_RK4 = 0, TM_DP45 = 1 } tm_integrator;
@@ -137,7 +140,10 @@ tm_status tm_geometry_destroy(tm_geom* g);
  * BF16X3 and FP16X3 require DENSE9.  PSYM6 (FP32 only) stores each
  * symmetric pair of blocks once, which the paper's symmetry remark
  * (Sec. 3.2) allows when all tiles are identical: it requires every tile to
- * have the same edges (TM_EINVAL otherwise).  The returned handle holds a reference;
+ * have the same edges (TM_EINVAL otherwise).  PSYM4 further requires every
+ * centre to have the same z: the tensor of a tile at a point of its own
+ * mid-plane is even in z, so its xz and yz components are zero for every
+ * pair and are not stored (tm_tensor_get returns them as 0).  The returned handle holds a reference;
  * release it with tm_tensor_release.  The call blocks until the operator is
  * ready.  TM_ENOMEM if it does not fit the admission budget after evicting
  * unreferenced cached tensors. */

@@ -175,17 +175,23 @@ tm_status tm_tensor_assemble(tm_ctx* c, const tm_geom* g, tm_prec store, tm_layo
     TM_REQUIRE(c && g && out, TM_EINVAL, "tm_tensor_assemble: null argument");
     TM_REQUIRE(store >= TM_PREC_FP32 && store <= TM_PREC_FP64, TM_EINVAL,
                "tm_tensor_assemble: unknown precision %d", static_cast<int>(store));
-    TM_REQUIRE(layout == TM_LAYOUT_SYM6 || layout == TM_LAYOUT_DENSE9 || layout == TM_LAYOUT_PSYM6,
+    TM_REQUIRE(layout == TM_LAYOUT_SYM6 || layout == TM_LAYOUT_DENSE9 || is_psym(layout),
                TM_EINVAL, "tm_tensor_assemble: layout %d cannot be assembled", static_cast<int>(layout));
     TM_REQUIRE(layout == TM_LAYOUT_DENSE9 || store == TM_PREC_FP32 || store == TM_PREC_FP64,
                TM_EINVAL, "tm_tensor_assemble: split precisions need the DENSE9 layout");
-    if (layout == TM_LAYOUT_PSYM6) {
-        TM_REQUIRE(store == TM_PREC_FP32, TM_EINVAL, "tm_tensor_assemble: PSYM6 is stored in FP32");
+    if (is_psym(layout)) {
+        const char* nm = layout == TM_LAYOUT_PSYM4 ? "PSYM4" : "PSYM6";
+        TM_REQUIRE(store == TM_PREC_FP32, TM_EINVAL, "tm_tensor_assemble: %s is stored in FP32", nm);
         for (int64_t a = 1; a < g->n; ++a)
             TM_REQUIRE(g->sizes[3 * a] == g->sizes[0] && g->sizes[3 * a + 1] == g->sizes[1] &&
                            g->sizes[3 * a + 2] == g->sizes[2],
-                       TM_EINVAL, "tm_tensor_assemble: PSYM6 needs identical tiles (tile %lld differs)",
+                       TM_EINVAL, "tm_tensor_assemble: %s needs identical tiles (tile %lld differs)", nm,
                        static_cast<long long>(a));
+        if (layout == TM_LAYOUT_PSYM4)
+            for (int64_t a = 1; a < g->n; ++a)
+                TM_REQUIRE(g->centers[3 * a + 2] == g->centers[2], TM_EINVAL,
+                           "tm_tensor_assemble: PSYM4 needs one layer of tiles (tile %lld has another z)",
+                           static_cast<long long>(a));
     }
     TM_TRY_HIP(hipSetDevice(c->device));
     std::unique_lock<std::mutex> lk(c->mu);
@@ -213,7 +219,7 @@ tm_status tm_tensor_assemble(tm_ctx* c, const tm_geom* g, tm_prec store, tm_layo
     size_t esz = store == TM_PREC_FP64 ? 8 : (store == TM_PREC_FP32 ? 4 : 2);
     int64_t main_bytes = 0, lo_bytes = 0, sc_bytes = 0;
     std::vector<int32_t> pairs;
-    if (layout == TM_LAYOUT_PSYM6) {
+    if (is_psym(layout)) {
         // pair table: the diagonal pairs first, then I < J row by row
         T->nt = (n + kPsTile - 1) / kPsTile;
         for (int64_t I = 0; I < T->nt; ++I) {
@@ -226,7 +232,7 @@ tm_status tm_tensor_assemble(tm_ctx* c, const tm_geom* g, tm_prec store, tm_layo
                 pairs.push_back(static_cast<int32_t>(J));
             }
         T->npairs = T->nt * (T->nt + 1) / 2;
-        main_bytes = T->npairs * 6 * kPsTile * kPsTile * 4;
+        main_bytes = T->npairs * psym_planes(layout) * kPsTile * kPsTile * 4;
         lo_bytes = 0;
     } else if (layout == TM_LAYOUT_SYM6) {
         T->ld = round_up(n, 4);
@@ -294,7 +300,7 @@ tm_status tm_tensor_get(const tm_tensor* T, int64_t a, int64_t b, double out9[9]
     TM_REQUIRE(T && out9, TM_EINVAL, "tm_tensor_get: null argument");
     TM_REQUIRE(a >= 0 && a < T->n && b >= 0 && b < T->n, TM_EINVAL, "tm_tensor_get: index out of range");
     TM_TRY_HIP(hipSetDevice(T->ctx->device));
-    if (T->layout == TM_LAYOUT_BSR6 || T->layout == TM_LAYOUT_PSYM6) {
+    if (T->layout == TM_LAYOUT_BSR6 || is_psym(T->layout)) {
         std::vector<double> row(T->n * 9);
         tm_status st = T->layout == TM_LAYOUT_BSR6 ? bsr_rows(T, a, 1, row.data()) : psym_rows(T, a, 1, row.data());
         if (st != TM_OK) return st;
@@ -351,7 +357,7 @@ tm_status tm_tensor_rows(const tm_tensor* T, int64_t a0, int64_t count, double* 
     TM_TRY_HIP(hipSetDevice(T->ctx->device));
     const int64_t n = T->n;
     if (T->layout == TM_LAYOUT_BSR6) return bsr_rows(T, a0, count, out);
-    if (T->layout == TM_LAYOUT_PSYM6) return psym_rows(T, a0, count, out);
+    if (is_psym(T->layout)) return psym_rows(T, a0, count, out);
     if (T->layout == TM_LAYOUT_SYM6) {
         const size_t esz = T->prec == TM_PREC_FP64 ? 8 : 4;
         std::vector<unsigned char> buf(6 * count * T->ld * esz);
@@ -587,7 +593,7 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
         splits = gemm_splits(p);
         pbytes = splits * bcap * T->rows * 4;
     }
-    const bool psym = T->layout == TM_LAYOUT_PSYM6;
+    const bool psym = is_psym(T->layout);
     if (psym) pbytes = psym_partial_floats(T, bcap) * 4;
     const int64_t dbytes = bcap * (nblk * 6 + 4) * 8;  // diagnostics partials + energies
     int64_t bytes = 12 * sb + bcap * 12 + bcap * (8 * 7 + 8 * 2 + 4 * 2 + 8 * kSnapStride) + 16 * bcap * n + 64 +

@@ -201,15 +201,19 @@ __global__ __launch_bounds__(256) void k_split_fp16_rows(int64_t ld, const float
 
 // PSYM6: tile pair p = (I, J), I <= J, holds block (al, bl) = tensor of tile
 // kPsTile J + bl at the centre of tile kPsTile I + al as planes [6][kPsTile][kPsTile]; blocks that
-// involve a padding index (>= n) are zero.
-__global__ __launch_bounds__(256) void k_assemble_psym6(int32_t n, const int32_t* __restrict__ pairs,
-                                                        const double* __restrict__ centers,
-                                                        const double* __restrict__ sizes,
-                                                        float* __restrict__ out) {
+// involve a padding index (>= n) are zero.  PSYM4 (NP = 4) keeps the planes
+// xx, xy, yy, zz: the xz and yz components are odd in the z offset, which is
+// zero for every pair of a single layer.
+template <int NP>
+__global__ __launch_bounds__(256) void k_assemble_psym(int32_t n, const int32_t* __restrict__ pairs,
+                                                       const double* __restrict__ centers,
+                                                       const double* __restrict__ sizes,
+                                                       float* __restrict__ out) {
     constexpr int TB = kPsTile * kPsTile;
+    static_assert(NP == 6 || NP == 4, "six or four planes");
     const int64_t p = blockIdx.x;
     const int64_t I = pairs[2 * p], J = pairs[2 * p + 1];
-    float* tile = out + p * 6 * TB;
+    float* tile = out + p * NP * TB;
     for (int e = threadIdx.x + 256 * blockIdx.y; e < TB; e += 256 * gridDim.y) {
         const int64_t a = kPsTile * I + e / kPsTile, b = kPsTile * J + e % kPsTile;
         double t6[6] = {0, 0, 0, 0, 0, 0};
@@ -220,19 +224,30 @@ __global__ __launch_bounds__(256) void k_assemble_psym6(int32_t n, const int32_t
             cuboid_tensor(dx, dy, dz, 0.5 * sizes[3 * b + 0], 0.5 * sizes[3 * b + 1],
                           0.5 * sizes[3 * b + 2], t6);
         }
+        if constexpr (NP == 6) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) tile[c * TB + e] = static_cast<float>(t6[c]);
+            for (int c = 0; c < 6; ++c) tile[c * TB + e] = static_cast<float>(t6[c]);
+        } else {
+            tile[0 * TB + e] = static_cast<float>(t6[0]);
+            tile[1 * TB + e] = static_cast<float>(t6[1]);
+            tile[2 * TB + e] = static_cast<float>(t6[3]);
+            tile[3 * TB + e] = static_cast<float>(t6[5]);
+        }
     }
 }
 
 }  // namespace
 
 tm_status assemble_psym(Tensor* T, const double* d_centers, const double* d_sizes, hipStream_t s) {
-    TM_REQUIRE(T->layout == TM_LAYOUT_PSYM6 && T->prec == TM_PREC_FP32 && T->pairs, TM_EINVAL,
+    TM_REQUIRE(is_psym(T->layout) && T->prec == TM_PREC_FP32 && T->pairs, TM_EINVAL,
                "pair-symmetric assembly: bad tensor");
     const dim3 grid(static_cast<unsigned>(T->npairs), 4);
-    k_assemble_psym6<<<grid, 256, 0, s>>>(static_cast<int32_t>(T->n), T->pairs, d_centers, d_sizes,
-                                          static_cast<float*>(T->data));
+    if (T->layout == TM_LAYOUT_PSYM4)
+        k_assemble_psym<4><<<grid, 256, 0, s>>>(static_cast<int32_t>(T->n), T->pairs, d_centers, d_sizes,
+                                                static_cast<float*>(T->data));
+    else
+        k_assemble_psym<6><<<grid, 256, 0, s>>>(static_cast<int32_t>(T->n), T->pairs, d_centers, d_sizes,
+                                                static_cast<float*>(T->data));
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
 }
@@ -281,7 +296,7 @@ tm_status assemble_device(Tensor* T, const double* d_centers, const double* d_si
                           hipStream_t s) {
     const int32_t n = static_cast<int32_t>(T->n);
     const dim3 block(256);
-    if (T->layout == TM_LAYOUT_PSYM6) return assemble_psym(T, d_centers, d_sizes, s);
+    if (is_psym(T->layout)) return assemble_psym(T, d_centers, d_sizes, s);
     if (T->layout == TM_LAYOUT_SYM6) {
         const dim3 grid(static_cast<unsigned>((T->ld + 255) / 256), static_cast<unsigned>(n));
         if (T->prec == TM_PREC_FP32)

@@ -123,7 +123,8 @@ struct Tensor {
     int32_t* col = nullptr;
     int64_t nnzb = 0;
     // PSYM6 (pair-symmetric): data = float [npairs][6][kPsTile][kPsTile] tiles of the
-    // upper triangle, pairs = int32 [npairs][2] (I, J), I <= J, nt tiles a side
+    // upper triangle, pairs = int32 [npairs][2] (I, J), I <= J, nt tiles a side;
+    // PSYM4 the same with the planes (xx, xy, yy, zz) of a single layer of tiles
     int32_t* pairs = nullptr;
     int64_t npairs = 0, nt = 0;
     double frac = -1.0;      // BSR6: removed fraction requested
@@ -131,6 +132,10 @@ struct Tensor {
     int64_t bytes = 0;
     int refs = 0;
 };
+
+// Pair-symmetric layouts and their stored planes.
+inline bool is_psym(int layout) { return layout == TM_LAYOUT_PSYM6 || layout == TM_LAYOUT_PSYM4; }
+inline int psym_planes(int layout) { return layout == TM_LAYOUT_PSYM4 ? 4 : 6; }
 
 // Frees a tensor's device memory and the tensor (the ledger is the caller's).
 void free_tensor(Tensor* T);

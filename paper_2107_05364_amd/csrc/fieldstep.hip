@@ -447,9 +447,9 @@ tm_status launch_field(const Problem* p, Epi mode, int64_t B, const float* X, co
     if (T->layout == TM_LAYOUT_DENSE9 && T->prec != TM_PREC_FP64)
         return launch_field_batched(p, mode, B, X, e, s);
     if (T->layout == TM_LAYOUT_BSR6) return launch_field_bsr(p, mode, B, X, e, s);
-    if (T->layout == TM_LAYOUT_PSYM6) return launch_field_psym(p, mode, B, X, e, s);
+    if (is_psym(T->layout)) return launch_field_psym(p, mode, B, X, e, s);
     TM_REQUIRE(T->layout == TM_LAYOUT_SYM6 && T->prec == TM_PREC_FP32, TM_EINVAL,
-               "field evaluation needs an FP32 SYM6, BSR6 or PSYM6 operator or a DENSE9 FP32 / BF16X3 / "
+               "field evaluation needs an FP32 SYM6, BSR6, PSYM6 or PSYM4 operator or a DENSE9 FP32 / BF16X3 / "
                "FP16X3 operator (FP64 operators are for verification)");
     MvArgs M;
     M.n = static_cast<int32_t>(p->n);
@@ -503,7 +503,7 @@ tm_status launch_control(Workspace* w, int64_t B, int integ, hipStream_t s) {
 int64_t last_stage_blocks(const Problem* p) {
     if (p->T->layout == TM_LAYOUT_DENSE9 && p->T->prec != TM_PREC_FP64) return (p->n + 255) / 256;
     if (p->T->layout == TM_LAYOUT_BSR6) return p->n;
-    if (p->T->layout == TM_LAYOUT_PSYM6) return p->T->nt;
+    if (is_psym(p->T->layout)) return p->T->nt;
     static const int tt_of_shape[kNumShapes] = {
 #define TM_SHAPE(i, BL, TT, NT, WPE) TT,
         TM_FIELD_SHAPES(TM_SHAPE)

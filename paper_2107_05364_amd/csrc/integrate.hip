@@ -380,7 +380,7 @@ tm_status time_field(Problem* p, int64_t B, int mode, int32_t iters, hipStream_t
     TM_TRY_HIP(hipEventCreate(&e1));
     // mode 3: the operator pass alone where the evaluation has more than one
     // launch (the pair-symmetric tile pass); otherwise the whole evaluation
-    const bool tiles_only = mode == 3 && p->T->layout == TM_LAYOUT_PSYM6;
+    const bool tiles_only = mode == 3 && is_psym(p->T->layout);
     auto one = [&]() {
         return tiles_only ? launch_psym_tiles(p, B, X, w->h, w->Ha, s) : launch_field(p, ep, B, X, e, s);
     };
@@ -414,10 +414,10 @@ extern "C" tm_status tm_profile_field_mode(tm_problem* pp, int64_t B, int32_t mo
     if (st != TM_OK) return st;
     if (bytes_out) {
         // operator bytes as stored (SYM6: 24 n^2; DENSE9: 36 n^2 algorithmic;
-        // BSR6: row pointers, columns and six planes; PSYM6: the stored tile
-        // pairs) + states in and out
+        // BSR6: row pointers, columns and six planes; PSYM6 / PSYM4: the
+        // stored tile pairs) + states in and out
         const Tensor* T = p->T;
-        const int64_t op = (T->layout == TM_LAYOUT_BSR6 || T->layout == TM_LAYOUT_PSYM6) ? T->bytes - (T->pairs ? T->npairs * 8 : 0)
+        const int64_t op = (T->layout == TM_LAYOUT_BSR6 || is_psym(T->layout)) ? T->bytes - (T->pairs ? T->npairs * 8 : 0)
                            : T->layout == TM_LAYOUT_DENSE9 ? 36 * p->n * p->n
                                                            : 24 * p->n * p->n;
         *bytes_out = op + 24 * p->n * B;

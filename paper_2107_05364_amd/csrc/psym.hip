@@ -1,4 +1,4 @@
-// Pair-symmetric demag operator (PSYM6) for meshes of identical tiles.
+// Pair-symmetric demag operator (PSYM6 / PSYM4) for meshes of identical tiles.
 //
 // When every tile has the same edges the tensor of tile b at the centre of
 // tile a depends only on the centre offset and is even in it, so
@@ -6,7 +6,8 @@
 // the paper invokes to store roughly half of the operator (Sec. 3.2).  The
 // operator is cut into TS x TS-block tiles (TS = kPsTile) and only the tile
 // pairs I <= J are stored ([pairs][6][TS][TS] float32, a diagonal tile in
-// full).
+// full).  PSYM4, for a single layer of tiles (one z for every centre), keeps
+// four planes: the xz and yz components are odd in the z offset and vanish.
 //
 // Product, two launches per field evaluation:
 //  * k_psym_tiles: one workgroup per (tile pair, state) reads its tile once
@@ -21,7 +22,7 @@
 //    tiles; the local field terms were folded into the diagonal slot by the
 //    tile pass.
 // Streamed bytes: 24 B x TS^2 per stored tile pair, i.e. about 12 N^2 + 12 N TS
-// against 24 N^2 for SYM6.
+// against 24 N^2 for SYM6 (PSYM4: 16 B x TS^2, about 8 N^2).
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -65,7 +66,9 @@ inline int64_t pair_index(int64_t I, int64_t J, int64_t nt) {
 // overlap it, and dispatched first (diagonal pairs lead the pair table) --
 // and subtract them from their own slot, so that minus the slot sum is the
 // whole effective field and the finish kernel has no dependent loads left.
-template <bool STEPPING, bool LOCALF, bool NTL>
+// NP = 6: planes (xx, xy, xz, yy, yz, zz); NP = 4 (a single layer): (xx, xy,
+// yy, zz), with xz = yz = 0.
+template <bool STEPPING, bool LOCALF, bool NTL, int NP>
 __global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const float* __restrict__ tiles,
                                                     const int32_t* __restrict__ pairs, int64_t nt,
                                                     const float* __restrict__ Ms, const float* __restrict__ X,
@@ -77,12 +80,12 @@ __global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const
     const int b = t % TS, rg = t / TS;
     // a frozen state reads no operator (a batch may hold many of them)
     if (STEPPING && h[s] == 0.0) return;
-    const float* tile = tiles + p * 6 * TB;
-    float v[RPT][6];
+    const float* tile = tiles + p * NP * TB;
+    float v[RPT][NP];
 #pragma unroll
     for (int i = 0; i < RPT; ++i)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) v[i][c] = ldt<NTL>(tile + c * TB + (RPT * rg + i) * TS + b);
+        for (int c = 0; c < NP; ++c) v[i][c] = ldt<NTL>(tile + c * TB + (RPT * rg + i) * TS + b);
     const int64_t I = pairs[2 * p], J = pairs[2 * p + 1];
     __shared__ float rred[TS][3][TS + 1];  // row sums before the column reduction
     __shared__ float cred[RG][TS][3];      // column sums per row group
@@ -108,7 +111,9 @@ __global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const
         const int64_t ag = TS * I + al;
         const float msa = Ms[ag];
         const float xa0 = x[3 * ag] * msa, xa1 = x[3 * ag + 1] * msa, xa2 = x[3 * ag + 2] * msa;
-        const float v0 = v[i][0], v1 = v[i][1], v2 = v[i][2], v3 = v[i][3], v4 = v[i][4], v5 = v[i][5];
+        const float v0 = v[i][0], v1 = v[i][1];
+        const float v2 = NP == 6 ? v[i][2] : 0.0f, v3 = v[i][NP == 6 ? 3 : 2];
+        const float v4 = NP == 6 ? v[i][4] : 0.0f, v5 = v[i][NP - 1];
         rred[al][0][b] = v0 * xb0 + v1 * xb1 + v2 * xb2;
         rred[al][1][b] = v1 * xb0 + v3 * xb1 + v4 * xb2;
         rred[al][2][b] = v2 * xb0 + v4 * xb1 + v5 * xb2;
@@ -140,14 +145,25 @@ __global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const
 // loads (each tile is read once per evaluation and cannot stay cached anyway).
 constexpr int64_t kPsymStreamBytes = 192ll << 20;
 
-template <bool STEPPING, bool LOCALF>
-inline void launch_tiles(dim3 grid, hipStream_t st, bool nt_loads, const DevProblem& P, const float* tiles,
-                         const int32_t* pairs, int64_t nt, const float* Ms, const float* X, int64_t sx,
-                         const double* h, const float* Ha, float* part) {
+template <bool STEPPING, bool LOCALF, int NP>
+inline void launch_tiles_np(dim3 grid, hipStream_t st, bool nt_loads, const DevProblem& P, const float* tiles,
+                            const int32_t* pairs, int64_t nt, const float* Ms, const float* X, int64_t sx,
+                            const double* h, const float* Ha, float* part) {
     if (nt_loads)
-        k_psym_tiles<STEPPING, LOCALF, true><<<grid, kTileThreads, 0, st>>>(P, tiles, pairs, nt, Ms, X, sx, h, Ha, part);
+        k_psym_tiles<STEPPING, LOCALF, true, NP><<<grid, kTileThreads, 0, st>>>(P, tiles, pairs, nt, Ms, X, sx, h, Ha, part);
     else
-        k_psym_tiles<STEPPING, LOCALF, false><<<grid, kTileThreads, 0, st>>>(P, tiles, pairs, nt, Ms, X, sx, h, Ha, part);
+        k_psym_tiles<STEPPING, LOCALF, false, NP><<<grid, kTileThreads, 0, st>>>(P, tiles, pairs, nt, Ms, X, sx, h, Ha, part);
+}
+
+template <bool STEPPING, bool LOCALF>
+inline void launch_tiles(const Tensor* T, dim3 grid, hipStream_t st, const DevProblem& P, const float* Ms,
+                         const float* X, int64_t sx, const double* h, const float* Ha, float* part) {
+    const bool nt_loads = T->bytes > kPsymStreamBytes;
+    const float* tiles = static_cast<const float*>(T->data);
+    if (T->layout == TM_LAYOUT_PSYM4)
+        launch_tiles_np<STEPPING, LOCALF, 4>(grid, st, nt_loads, P, tiles, T->pairs, T->nt, Ms, X, sx, h, Ha, part);
+    else
+        launch_tiles_np<STEPPING, LOCALF, 6>(grid, st, nt_loads, P, tiles, T->pairs, T->nt, Ms, X, sx, h, Ha, part);
 }
 
 // One workgroup per (target tile K, state): the nt slots of K are contiguous
@@ -250,8 +266,7 @@ void launch_psym_t(const DevProblem& P, const Tensor* T, const float* Ms, float*
     constexpr bool STEPPING = MODE == Epi::STAGE || MODE == Epi::RK4_FINAL || MODE == Epi::DP_LAST;
     constexpr bool LOCALF = MODE != Epi::HD;
     const dim3 g1(static_cast<unsigned>(T->npairs), static_cast<unsigned>(B));
-    launch_tiles<STEPPING, LOCALF>(g1, s, T->bytes > kPsymStreamBytes, P, static_cast<const float*>(T->data),
-                                   T->pairs, T->nt, Ms, X, sx, e.h, e.Ha, part);
+    launch_tiles<STEPPING, LOCALF>(T, g1, s, P, Ms, X, sx, e.h, e.Ha, part);
     const dim3 g2(static_cast<unsigned>(T->nt), static_cast<unsigned>(B));
     k_psym_finish<MODE><<<g2, kFinishThreads, 0, s>>>(P, part, T->nt, X, sx, e);
 }
@@ -264,11 +279,10 @@ tm_status launch_psym_tiles(const Problem* p, int64_t B, const float* X, const d
                             hipStream_t s) {
     const Tensor* T = p->T;
     Workspace* w = p->ws.get();
-    TM_REQUIRE(T->layout == TM_LAYOUT_PSYM6 && w && w->part && w->B >= B, TM_EINVAL,
+    TM_REQUIRE(is_psym(T->layout) && w && w->part && w->B >= B, TM_EINVAL,
                "pair-symmetric tile pass: not prepared");
     const dim3 g1(static_cast<unsigned>(T->npairs), static_cast<unsigned>(B));
-    launch_tiles<true, true>(g1, s, T->bytes > kPsymStreamBytes, p->dev(), static_cast<const float*>(T->data),
-                             T->pairs, T->nt, p->Ms, X, 3 * p->np, h, Ha, w->part);
+    launch_tiles<true, true>(T, g1, s, p->dev(), p->Ms, X, 3 * p->np, h, Ha, w->part);
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
 }
@@ -277,8 +291,8 @@ tm_status launch_field_psym(const Problem* p, Epi mode, int64_t B, const float* 
                             hipStream_t s) {
     const Tensor* T = p->T;
     Workspace* w = p->ws.get();
-    TM_REQUIRE(T->layout == TM_LAYOUT_PSYM6 && T->pairs && T->data, TM_EINVAL,
-               "pair-symmetric field evaluation needs a PSYM6 operator");
+    TM_REQUIRE(is_psym(T->layout) && T->pairs && T->data, TM_EINVAL,
+               "pair-symmetric field evaluation needs a PSYM6 or PSYM4 operator");
     TM_REQUIRE(w && w->part && w->B >= B && B >= 1 && B <= 65535, TM_EINVAL,
                "pair-symmetric field evaluation: workspace not prepared for %lld states",
                static_cast<long long>(B));
@@ -299,14 +313,18 @@ tm_status launch_field_psym(const Problem* p, Epi mode, int64_t B, const float* 
 
 tm_status psym_rows(const Tensor* T, int64_t a0, int64_t count, double* out) {
     const int64_t n = T->n, nt = T->nt;
-    std::vector<float> tile(6 * TB);
-    static const int comp[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+    const int NP = psym_planes(T->layout);
+    std::vector<float> tile(NP * TB);
+    // plane of each of the 9 components (-1: zero, not stored)
+    static const int comp6[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+    static const int comp4[9] = {0, 1, -1, 1, 2, -1, -1, -1, 3};
+    const int* comp = NP == 4 ? comp4 : comp6;
     for (int64_t ta = a0 / TS; ta <= (a0 + count - 1) / TS; ++ta) {
         for (int64_t tb = 0; tb < nt; ++tb) {
             const bool upper = ta <= tb;
             const int64_t pidx = upper ? pair_index(ta, tb, nt) : pair_index(tb, ta, nt);
-            TM_TRY_HIP(hipMemcpy(tile.data(), static_cast<const float*>(T->data) + pidx * 6 * TB,
-                                 6 * TB * sizeof(float), hipMemcpyDeviceToHost));
+            TM_TRY_HIP(hipMemcpy(tile.data(), static_cast<const float*>(T->data) + pidx * NP * TB,
+                                 NP * TB * sizeof(float), hipMemcpyDeviceToHost));
             for (int64_t al = 0; al < TS; ++al) {
                 const int64_t a = TS * ta + al;
                 if (a < a0 || a >= a0 + count) continue;
@@ -315,7 +333,8 @@ tm_status psym_rows(const Tensor* T, int64_t a0, int64_t count, double* out) {
                     if (b >= n) break;
                     // N^{ab} from tile (ta, tb) at (al, bl), or N^{ba} = N^{ab} from (tb, ta) at (bl, al)
                     const int64_t e = upper ? al * TS + bl : bl * TS + al;
-                    for (int k = 0; k < 9; ++k) out[((a - a0) * n + b) * 9 + k] = tile[comp[k] * TB + e];
+                    for (int k = 0; k < 9; ++k)
+                        out[((a - a0) * n + b) * 9 + k] = comp[k] < 0 ? 0.0 : tile[comp[k] * TB + e];
                 }
             }
         }

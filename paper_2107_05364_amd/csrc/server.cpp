@@ -117,7 +117,8 @@ struct tm_server {
 namespace {
 
 // Meshes of identical tiles above kPsymMinTiles are served with the pair-
-// symmetric operator (about half the bytes streamed per step), others with the
+// symmetric operator (about half the bytes streamed per step; a third of them
+// for a single layer, PSYM4), others with the
 // six planes: below that size the step is launch-bound and the single fused
 // six-plane launch per evaluation beats the pair-symmetric two (measured on
 // the film sizes: 900 tiles 25 k vs 19 k steps/s, 1600 tiles 11.7 k vs 14.5 k).
@@ -129,10 +130,17 @@ bool identical_tiles(const std::vector<double>& sizes) {
     return true;
 }
 
+// One layer: every centre at the same z (the xz and yz components vanish).
+bool single_layer(const std::vector<double>& centers) {
+    for (size_t i = 5; i < centers.size(); i += 3)
+        if (centers[i] != centers[2]) return false;
+    return true;
+}
+
 int64_t operator_bytes(int64_t n, tm_layout layout) {
-    if (layout == TM_LAYOUT_PSYM6) {
+    if (is_psym(layout)) {
         const int64_t nt = (n + kPsTile - 1) / kPsTile;
-        return nt * (nt + 1) / 2 * (6 * kPsTile * kPsTile * 4 + 8);
+        return nt * (nt + 1) / 2 * (psym_planes(layout) * kPsTile * kPsTile * 4 + 8);
     }
     return 6 * n * round_up(n, 4) * 4;
 }
@@ -140,7 +148,7 @@ int64_t operator_bytes(int64_t n, tm_layout layout) {
 int64_t workspace_bytes(int64_t n, int64_t B, tm_layout layout) {
     const int64_t np = padded_tiles(n);
     int64_t b = 12 * B * 3 * np * 4 + B * 128 + 16 * B * n + 4096 + ((n + 255) / 256) * B * 32;
-    if (layout == TM_LAYOUT_PSYM6) {
+    if (is_psym(layout)) {
         const int64_t nt = (n + kPsTile - 1) / kPsTile;
         b += B * nt * nt * 3 * kPsTile * 4;
     }
@@ -201,8 +209,9 @@ bool tm_server::try_place(Req* r) {
         if (static_cast<int>(groups.size()) >= cfg.max_groups) return false;
         // bytes a new group needs: the operator unless cached, plus the slots
         bool cached = false;
-        const tm_layout layout =
-            r->n > kPsymMinTiles && identical_tiles(r->sizes) ? TM_LAYOUT_PSYM6 : TM_LAYOUT_SYM6;
+        const tm_layout layout = r->n > kPsymMinTiles && identical_tiles(r->sizes)
+                                     ? (single_layer(r->centers) ? TM_LAYOUT_PSYM4 : TM_LAYOUT_PSYM6)
+                                     : TM_LAYOUT_SYM6;
         const int64_t tbytes = operator_bytes(r->n, layout);
         {
             std::lock_guard<std::mutex> lk(ctx->mu);

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libtilemag.so")
 TM_OK, TM_EINVAL, TM_ENOMEM, TM_EDEVICE = 0, -1, -2, -3
 TM_ENONFINITE, TM_ESTEP, TM_EBUSY, TM_ENOTFOUND = -4, -5, -6, -7
 TM_PREC_FP32, TM_PREC_BF16X3, TM_PREC_FP16X3, TM_PREC_FP64 = 0, 1, 2, 3
-TM_LAYOUT_SYM6, TM_LAYOUT_DENSE9, TM_LAYOUT_BSR6, TM_LAYOUT_PSYM6 = 0, 1, 2, 3
+TM_LAYOUT_SYM6, TM_LAYOUT_DENSE9, TM_LAYOUT_BSR6, TM_LAYOUT_PSYM6, TM_LAYOUT_PSYM4 = 0, 1, 2, 3, 4
 TM_RK4, TM_DP45 = 0, 1
 
 _STATUS_NAMES = {0: "TM_OK", -1: "TM_EINVAL", -2: "TM_ENOMEM", -3: "TM_EDEVICE",

@@ -405,7 +405,7 @@ def test_edge_inputs_rejected(tmg, ctx):
         assert ei.value.status == tmg.TM_EINVAL
     c, s = _meshes()["grid13x5"]
     n = c.shape[0]
-    for layout in (tmg.TM_LAYOUT_SYM6, tmg.TM_LAYOUT_PSYM6, tmg.TM_LAYOUT_DENSE9):
+    for layout in (tmg.TM_LAYOUT_SYM6, tmg.TM_LAYOUT_PSYM6, tmg.TM_LAYOUT_PSYM4, tmg.TM_LAYOUT_DENSE9):
         g, T, p = build(tmg, ctx, c, s, layout=layout)
         m = device_state(W.random_unit_vectors(5, n)[None])
         out = torch.full_like(m, 7.0)
@@ -432,19 +432,21 @@ def test_edge_inputs_rejected(tmg, ctx):
         close(g, T, p)
 
 
-@pytest.mark.parametrize("layout", ["sym6", "psym6", "dense9"])
+@pytest.mark.parametrize("layout", ["sym6", "psym6", "psym4", "dense9"])
 def test_diagnostics_vs_oracle(tmg, ctx, orc, layout):
     """tm_diagnostics against the oracle: energy terms (relative 1e-5),
     moment-weighted <m> (1e-6), max |dm/dt| (relative 1e-5), and a state
     holding a NaN flagged alone."""
     import torch
 
-    c, s = W.grid(9, 5, 2, 5e-9, 4e-9, 3e-9)
+    # the four-plane layout needs a single layer of tiles
+    c, s = W.grid(9, 5, 2, 5e-9, 4e-9, 3e-9) if layout != "psym4" else W.grid(15, 6, 1, 5e-9, 4e-9, 3e-9)
     n = c.shape[0]
     # pair symmetry needs identical tiles and a uniform Ms; the other layouts
     # get per-tile Ms to exercise the moment weights
-    Ms = 8.0e5 if layout == "psym6" else np.linspace(6e5, 9e5, n)
+    Ms = 8.0e5 if layout in ("psym6", "psym4") else np.linspace(6e5, 9e5, n)
     store, lay = {"sym6": (tmg.TM_PREC_FP32, tmg.TM_LAYOUT_SYM6), "psym6": (tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM6),
+                  "psym4": (tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM4),
                   "dense9": (tmg.TM_PREC_FP32, tmg.TM_LAYOUT_DENSE9)}[layout]
     g, T, p = build(tmg, ctx, c, s, Ms=Ms, alpha=0.3, store=store, layout=lay, Ku=2e4,
                     easy=W.random_unit_vectors(9, n))

@@ -8,8 +8,9 @@ symmetric).
 * closed form at the centre of a cuboid (textbook demagnetising factors);
 * trace 1 inside the tile and 0 outside (Poisson/Laplace for psi);
 * far field of a point dipole;
-* scale invariance, pair symmetry on identical tiles, positive
-  semi-definiteness of the demag energy, superposition of sub-tiles;
+* scale invariance, pair symmetry on identical tiles, vanishing xz and yz
+  components on the source's mid-plane, positive semi-definiteness of the
+  demag energy, superposition of sub-tiles;
 * the cancellation-free logarithms against a 50-digit evaluation of the
   plain eight-corner sum.
 """
@@ -155,6 +156,26 @@ def test_pair_symmetry_identical_tiles(orc):
     c, s = grid(4, 3, 2, 5e-9, 4e-9, 3e-9)
     T = orc.assemble(c, s)
     assert np.abs(T - T.T).max() < 1e-15
+
+
+def test_mid_plane_xz_yz_vanish(orc):
+    """At a point of the source's mid-plane (z = c_z) the xz and yz
+    components vanish (the potential is even in z - c_z): checked with the
+    surface-charge quadrature, then on the oracle's operator of a single
+    layer of tiles (zero) against two layers (not zero)."""
+    from paper_2107_05364_amd.workloads import grid
+
+    c, s = [0.0, 0.0, 0.0], [1.0, 2.0, 1.5]
+    for r in ([2.3, 0.9, 0.0], [0.7, -3.1, 0.0]):
+        Nq = quad_tensor(r, c, s)
+        assert abs(Nq[0, 2]) < 1e-12 and abs(Nq[1, 2]) < 1e-12 and abs(Nq[0, 1]) > 1e-3, Nq
+        No = orc.prism_tensor(r, c, s)
+        assert No[0, 2] == 0.0 and No[2, 0] == 0.0 and No[1, 2] == 0.0 and No[2, 1] == 0.0
+    one = orc.assemble(*grid(6, 4, 1, 5e-9, 4e-9, 3e-9))
+    two = orc.assemble(*grid(6, 4, 2, 5e-9, 4e-9, 3e-9))
+    for i, j in ((0, 2), (2, 0), (1, 2), (2, 1)):
+        assert np.abs(one[i::3, j::3]).max() == 0.0
+        assert np.abs(two[i::3, j::3]).max() > 1e-3
 
 
 def test_demag_energy_positive_semidefinite(orc):
