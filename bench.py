@@ -326,6 +326,7 @@ def sp4_sweep_section(tmg, W, torch, attempts=300):
         # the same film with the pair-symmetric operator (identical tiles)
         Tp = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM6)
         pp = tmg.Problem(ctx, geom, Tp, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+        tmg.tm_problem_tune(pp.handle, 1, 10)
         msp, nbp = tmg.tm_profile_field(pp.handle, 1, 50)
         row.update({"psym6_field_us": round(msp * 1e3, 2), "psym6_steps_per_s": round(steps_per_s(pp), 1)})
         pp.close()
@@ -333,6 +334,7 @@ def sp4_sweep_section(tmg, W, torch, attempts=300):
         # and with its four planes (one layer: xz = yz = 0)
         T4 = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM4)
         p4 = tmg.Problem(ctx, geom, T4, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+        tmg.tm_problem_tune(p4.handle, 1, 10)
         ms4, _ = tmg.tm_profile_field(p4.handle, 1, 50)
         row.update({"psym4_field_us": round(ms4 * 1e3, 2), "psym4_steps_per_s": round(steps_per_s(p4), 1)})
         rows.append(row)
@@ -623,8 +625,9 @@ def main():
     asm_ms = (time.perf_counter() - t0) * 1e3
     p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
     # project autotuner: fastest launch shape of the fused stage kernel for this N
-    # (the pair-symmetric layout has one kernel shape)
+    # (pair-symmetric layouts: cached or nontemporal operator loads in the tile pass)
     shape, _ = tmg.tm_problem_tune(p.handle, 1, 50)
+    nt_loads = psym and shape == 1
     # dominant kernel: the operator pass (mode 3: the tile pass of the
     # pair-symmetric layout; the fused stage kernel of the six-plane layout)
     prof_mode = 3 if psym else 0
@@ -659,7 +662,7 @@ def main():
     eval_ms, _ = tmg.tm_profile_field(p.handle, 1, args.profile_iters)
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9
     if psym:
-        kname = "k_psym_tiles<true,true,%s,%d>" % ("true" if T.nbytes > (192 << 20) else "false",
+        kname = "k_psym_tiles<true,true,%s,%d>" % ("true" if nt_loads else "false",
                                                    4 if args.layout == "psym4" else 6)
         kdesc = (" (pair-symmetric tile pass of the demag product; the slot sum and epilogue run in "
                  "a second launch, included in field_evaluation_us)")
@@ -685,7 +688,8 @@ def main():
                                "adaptive DP45, fp32 %s operator" % args.layout.upper(),
                    "n_tiles": n, "batch": 1, "integrator": "DP45", "operator": "fp32 " + args.layout,
                    "accepted_steps": accepted, "rejected_steps": int(st.rejected),
-                   "stage_kernel_shape": shape,
+                   "stage_kernel_shape": -1 if psym else shape,
+                   "tile_pass_loads": ("nontemporal" if nt_loads else "cached") if psym else None,
                    "simulated_ns": round(float(tt.cpu()[0]) * 1e9, 4),
                    "assembly_ms": round(asm_ms, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

@@ -334,8 +334,11 @@ tm_status tm_problem_set_shape(tm_problem* p, int32_t shape);
  * are the numbers of K splits (2, 3, 4, 5, 6, 8) and chosen is the split
  * count kept; the split count sets the summation order, so results are
  * bitwise reproducible for a fixed count and independent of the batch.
- * For the other operators (one kernel shape each) it only times that
- * kernel and reports chosen = -1. */
+ * For PSYM6 / PSYM4 it times the evaluation with cached (chosen = 0) and
+ * with nontemporal (chosen = 1) operator loads in the tile pass and keeps
+ * the faster (the results are the same either way).  For the other
+ * operators (one kernel shape each) it only times that kernel and reports
+ * chosen = -1. */
 tm_status tm_problem_tune(tm_problem* p, int64_t B, int32_t iters, hipStream_t stream,
                           int32_t* chosen, double* best_ms);
 

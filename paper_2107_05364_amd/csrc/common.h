@@ -175,6 +175,8 @@ struct Problem {
     int64_t nnz = 0;
     int shape = -1;             // field-kernel launch shape (-1: default for n)
     int gemm_splits = 0;        // batched product: K splits (0: default for the operator)
+    int psym_nt = -1;           // pair-symmetric tile pass: nontemporal operator loads (1) or
+                                // cached (0); -1: by operator size
     int64_t bytes = 0;          // device bytes owned by the problem
     std::unique_ptr<Workspace> ws;
     DevProblem dev() const;

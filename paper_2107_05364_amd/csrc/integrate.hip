@@ -501,6 +501,36 @@ extern "C" tm_status tm_problem_tune(tm_problem* pp, int64_t B, int32_t iters, h
         if (best_ms) *best_ms = best_t;
         return TM_OK;
     }
+    if (is_psym(p->T->layout)) {
+        // the pair-symmetric tile pass: cached (0) or nontemporal (1) operator
+        // loads, each timed over the whole evaluation, the faster kept
+        const int keep = p->psym_nt;
+        int best = 0;
+        double best_t = 1e30;
+        for (int c = 0; c < 2; ++c) {
+            p->psym_nt = c;
+            double ms = 0.0;
+            st = time_field(p, B, 0, iters, s, &ms);
+            if (st != TM_OK) {
+                p->psym_nt = keep;
+                return st;
+            }
+            if (ms < best_t) {
+                best_t = ms;
+                best = c;
+            }
+        }
+        p->psym_nt = best;
+        if (best != keep && p->ws) {
+            // captured graphs hold the other tile-pass kernel
+            if (p->ws->graph1) (void)hipGraphExecDestroy(p->ws->graph1);
+            if (p->ws->graphK) (void)hipGraphExecDestroy(p->ws->graphK);
+            p->ws->graph1 = p->ws->graphK = nullptr;
+        }
+        if (chosen) *chosen = best;
+        if (best_ms) *best_ms = best_t;
+        return TM_OK;
+    }
     if (p->T->layout != TM_LAYOUT_SYM6) {
         // launch shapes belong to the dense SYM6 kernel; other layouts have one
         double ms = 0.0;

@@ -141,8 +141,11 @@ __global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const
     }
 }
 
-// Operators larger than the Infinity Cache are streamed with nontemporal
-// loads (each tile is read once per evaluation and cannot stay cached anyway).
+// By default operators larger than the Infinity Cache are streamed with
+// nontemporal loads (each tile is read once per evaluation and cannot stay
+// cached anyway).  Which loads are faster below that size varies (the film
+// at N = 2500 streams faster with nontemporal loads, at N = 4900 in four
+// planes slower), so tm_problem_tune times both on the caller's problem.
 constexpr int64_t kPsymStreamBytes = 192ll << 20;
 
 template <bool STEPPING, bool LOCALF, int NP>
@@ -156,9 +159,9 @@ inline void launch_tiles_np(dim3 grid, hipStream_t st, bool nt_loads, const DevP
 }
 
 template <bool STEPPING, bool LOCALF>
-inline void launch_tiles(const Tensor* T, dim3 grid, hipStream_t st, const DevProblem& P, const float* Ms,
-                         const float* X, int64_t sx, const double* h, const float* Ha, float* part) {
-    const bool nt_loads = T->bytes > kPsymStreamBytes;
+inline void launch_tiles(const Tensor* T, bool nt_loads, dim3 grid, hipStream_t st, const DevProblem& P,
+                         const float* Ms, const float* X, int64_t sx, const double* h, const float* Ha,
+                         float* part) {
     const float* tiles = static_cast<const float*>(T->data);
     if (T->layout == TM_LAYOUT_PSYM4)
         launch_tiles_np<STEPPING, LOCALF, 4>(grid, st, nt_loads, P, tiles, T->pairs, T->nt, Ms, X, sx, h, Ha, part);
@@ -261,14 +264,20 @@ __global__ __launch_bounds__(kFinishThreads) void k_psym_finish(DevProblem P, co
 }
 
 template <Epi MODE>
-void launch_psym_t(const DevProblem& P, const Tensor* T, const float* Ms, float* part, int64_t B,
+void launch_psym_t(const DevProblem& P, const Tensor* T, bool nt_loads, const float* Ms, float* part, int64_t B,
                    const float* X, int64_t sx, const EpiArgs& e, hipStream_t s) {
     constexpr bool STEPPING = MODE == Epi::STAGE || MODE == Epi::RK4_FINAL || MODE == Epi::DP_LAST;
     constexpr bool LOCALF = MODE != Epi::HD;
     const dim3 g1(static_cast<unsigned>(T->npairs), static_cast<unsigned>(B));
-    launch_tiles<STEPPING, LOCALF>(T, g1, s, P, Ms, X, sx, e.h, e.Ha, part);
+    launch_tiles<STEPPING, LOCALF>(T, nt_loads, g1, s, P, Ms, X, sx, e.h, e.Ha, part);
     const dim3 g2(static_cast<unsigned>(T->nt), static_cast<unsigned>(B));
     k_psym_finish<MODE><<<g2, kFinishThreads, 0, s>>>(P, part, T->nt, X, sx, e);
+}
+
+// Operator loads of the tile pass: the problem's choice (tm_problem_tune),
+// else nontemporal beyond the Infinity Cache.
+bool psym_nt_loads(const Problem* p) {
+    return p->psym_nt >= 0 ? p->psym_nt == 1 : p->T->bytes > kPsymStreamBytes;
 }
 
 }  // namespace
@@ -282,7 +291,7 @@ tm_status launch_psym_tiles(const Problem* p, int64_t B, const float* X, const d
     TM_REQUIRE(is_psym(T->layout) && w && w->part && w->B >= B, TM_EINVAL,
                "pair-symmetric tile pass: not prepared");
     const dim3 g1(static_cast<unsigned>(T->npairs), static_cast<unsigned>(B));
-    launch_tiles<true, true>(T, g1, s, p->dev(), p->Ms, X, 3 * p->np, h, Ha, w->part);
+    launch_tiles<true, true>(T, psym_nt_loads(p), g1, s, p->dev(), p->Ms, X, 3 * p->np, h, Ha, w->part);
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
 }
@@ -299,13 +308,14 @@ tm_status launch_field_psym(const Problem* p, Epi mode, int64_t B, const float* 
     TM_REQUIRE(p->np >= TS * T->nt, TM_EINVAL, "pair-symmetric field evaluation: state padding too small");
     const DevProblem P = p->dev();
     const int64_t sx = 3 * p->np;
+    const bool nt = psym_nt_loads(p);
     switch (mode) {
-        case Epi::HD: launch_psym_t<Epi::HD>(P, T, p->Ms, w->part, B, X, sx, e, s); break;
-        case Epi::HEFF: launch_psym_t<Epi::HEFF>(P, T, p->Ms, w->part, B, X, sx, e, s); break;
-        case Epi::DMDT: launch_psym_t<Epi::DMDT>(P, T, p->Ms, w->part, B, X, sx, e, s); break;
-        case Epi::STAGE: launch_psym_t<Epi::STAGE>(P, T, p->Ms, w->part, B, X, sx, e, s); break;
-        case Epi::RK4_FINAL: launch_psym_t<Epi::RK4_FINAL>(P, T, p->Ms, w->part, B, X, sx, e, s); break;
-        case Epi::DP_LAST: launch_psym_t<Epi::DP_LAST>(P, T, p->Ms, w->part, B, X, sx, e, s); break;
+        case Epi::HD: launch_psym_t<Epi::HD>(P, T, nt, p->Ms, w->part, B, X, sx, e, s); break;
+        case Epi::HEFF: launch_psym_t<Epi::HEFF>(P, T, nt, p->Ms, w->part, B, X, sx, e, s); break;
+        case Epi::DMDT: launch_psym_t<Epi::DMDT>(P, T, nt, p->Ms, w->part, B, X, sx, e, s); break;
+        case Epi::STAGE: launch_psym_t<Epi::STAGE>(P, T, nt, p->Ms, w->part, B, X, sx, e, s); break;
+        case Epi::RK4_FINAL: launch_psym_t<Epi::RK4_FINAL>(P, T, nt, p->Ms, w->part, B, X, sx, e, s); break;
+        case Epi::DP_LAST: launch_psym_t<Epi::DP_LAST>(P, T, nt, p->Ms, w->part, B, X, sx, e, s); break;
     }
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;

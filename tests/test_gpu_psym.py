@@ -346,3 +346,18 @@ def test_psym4_streamed_size_rows(tmg, ctx, orc):
     e2, emax = rel_errors(Hd[rows], want)
     assert e2 <= 1e-5 and emax <= 1e-5, (e2, emax)
     close(g, T, p)
+
+
+def test_psym_tuned_loads_same_results(tmg, ctx):
+    """tm_problem_tune on a pair-symmetric problem picks cached (0) or
+    nontemporal (1) operator loads for the tile pass; the arithmetic is the
+    same, so the field is bitwise unchanged."""
+    for layout in (tmg.TM_LAYOUT_PSYM4, tmg.TM_LAYOUT_PSYM6):
+        c, s = _layers()["grid45x7"]
+        g, T, p = build(tmg, ctx, c, s, layout=layout)
+        md = device_state(np.stack([W.random_unit_vectors(120 + k, c.shape[0]) for k in range(2)]))
+        before = p.heff(md).cpu().numpy()
+        chosen, ms = tmg.tm_problem_tune(p.handle, 2, 3)
+        assert chosen in (0, 1) and ms > 0
+        assert np.array_equal(p.heff(md).cpu().numpy(), before)
+        close(g, T, p)
