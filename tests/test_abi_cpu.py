@@ -45,6 +45,20 @@ def test_binding_covers_the_header(tmg):
         assert callable(getattr(tmg, name)), name
 
 
+def test_binding_constants_match_the_header(tmg):
+    """Every TM_* enumerator the header assigns a value has the same value in
+    the binding (layouts, precisions, integrators, status codes)."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    pairs = re.findall(r"\b(TM_[A-Z0-9_]+)\s*=\s*(-?\d+)", text)
+    pairs += re.findall(r"#define\s+(TM_[A-Z0-9_]+)\s+\((-?\d+)\)", text)
+    assert len(pairs) >= 15
+    for name, val in pairs:
+        if hasattr(tmg, name):
+            assert getattr(tmg, name) == int(val), (name, val)
+    for must in ("TM_LAYOUT_PSYM4", "TM_LAYOUT_PSYM6", "TM_PREC_BF16X3", "TM_DP45", "TM_EINVAL"):
+        assert hasattr(tmg, must), must
+
+
 def test_version_and_error_text(tmg):
     assert tmg.load().tm_version() >= 100
     with pytest.raises(tmg.TilemagError) as ei:
