@@ -108,3 +108,26 @@ def test_admission_under_small_budget(tmg, ctx):
     srv.close()
     assert all(r.status == 0 for r in res), [r.status for r in res]
     assert rb.status == tmg.TM_ENOMEM
+
+
+def test_pair_symmetric_groups_relax(tmg, ctx):
+    """Above 1200 identical tiles the server streams the pair-symmetric
+    operator: four planes for a single layer (1280 tiles), six for four
+    layers (1600 tiles).  Both requests reach the equilibrium criterion,
+    checked independently with the six-plane operator."""
+    import torch
+
+    reqs = [_req(50, 40, 32), _req(51, 20, 20, 4)]
+    srv = tmg.Server(ctx, max_slots=2, max_groups=4, steps_per_round=64)
+    tks = [_submit(srv, r, max_steps=40000) for r in reqs]
+    res = [srv.poll(t) for t in tks]
+    srv.close()
+    for (c, s, m0, Ha), (r, m) in zip(reqs, res):
+        _say("pair-symmetric group n=%d: status %d, %d steps, %.1f ms" % (c.shape[0], r.status, r.steps, r.latency_ms))
+        assert r.status == 0 and r.steps > 0, (r.status, tmg.last_error())
+        g, T, p = build(tmg, ctx, c, s, alpha=0.5)
+        f = p.dmdt(device_state(m[None]), torch.tensor([Ha], dtype=torch.float32, device="cuda"))
+        mx = f.norm(dim=2).max().item()
+        close(g, T, p)
+        assert mx < 1.05 * STOP, (mx, STOP)
+        assert np.abs(np.linalg.norm(m, axis=1) - 1).max() < 1e-5
