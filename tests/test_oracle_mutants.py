@@ -29,10 +29,16 @@ MUTANTS = {
                              "int64_t r = (int64_t)floor(frac * (double)K);"),
     "threshold_self_blocks": ("if (row / 3 == col / 3) continue;", "if (row < 0) continue;"),
     "threshold_no_zero_floor": ("if (mag > floor32) v[K++] = mag;", "if (mag > 0.0) v[K++] = mag;"),
+    "demag_target_ms": ("acc += row[col] * Ms[col / 3] * m[col];", "acc += row[col] * Ms[r / 3] * m[col];"),
+    "rows_target_ms": ("double mx = Ms[b] * m[3 * b], my = Ms[b] * m[3 * b + 1], mz = Ms[b] * m[3 * b + 2];",
+                       "double mx = Ms[a] * m[3 * b], my = Ms[a] * m[3 * b + 1], mz = Ms[a] * m[3 * b + 2];"),
+    "rows_component_swap": ("h[1] += t6[1] * mx + t6[3] * my + t6[4] * mz;",
+                            "h[1] += t6[1] * mx + t6[4] * my + t6[3] * mz;"),
 }
 
 PIN_FILES = ["tests/test_oracle_tensor.py", "tests/test_oracle_fields.py",
-             "tests/test_oracle_dynamics.py", "tests/test_oracle_threshold.py"]
+             "tests/test_oracle_dynamics.py", "tests/test_oracle_threshold.py",
+             "tests/test_oracle_rows.py"]
 
 
 @pytest.mark.slow
