@@ -74,11 +74,13 @@ struct Group {
 };
 
 std::string group_key(const Req& r) {
-    // geometry bytes are compared through the hash plus the tensor cache's
-    // exact check; material and run settings must match exactly
+    // the geometry's canonical bytes, material and run settings, all compared
+    // exactly (the hash leads, so unlike keys usually differ in the first bytes)
     std::string k(reinterpret_cast<const char*>(&r.ghash), 8);
     auto add = [&k](const void* p, size_t len) { k.append(static_cast<const char*>(p), len); };
     add(&r.n, 8);
+    add(r.centers.data(), r.centers.size() * 8);
+    add(r.sizes.data(), r.sizes.size() * 8);
     add(r.Ms.data(), r.Ms.size() * 8);
     add(&r.A, 8);
     add(&r.alpha, 8);

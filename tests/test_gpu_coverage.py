@@ -1,0 +1,188 @@
+"""GPU parity of configurations that the autotuner, the headline run and the
+server can select, against the FP64 oracle:
+
+* every compiled launch shape of the fused six-plane stage kernel (any of them
+  can be kept by tm_problem_tune), on a non-uniform mesh with per-tile Ms and
+  anisotropy, three states with different applied fields: H_eff and one
+  Dormand-Prince attempt;
+* the pair-symmetric operators (PSYM6, PSYM4) with per-tile Ms (the tile pass
+  weights row sums by the source tile's Ms and column sums by the target
+  tile's): H_d, H_eff, one Dormand-Prince attempt and the diagnostics;
+* the four-plane operator of the headline run over 200 accepted adaptive
+  steps on the full film, compared with the oracle at the GPU's end time.
+
+Tolerances as in the other parity tests: H_eff relative 2-norm and max-norm
+<= 1e-5; one DP45 attempt |dm| <= 1e-5 and the proposed step within 1e-3
+(the error estimate of a float32 state sits at its noise floor); the
+200-step trajectory <= 5e-5 (twice the oracle's own discretisation error
+over that interval, 1.0e-5, plus margin for the float32 state).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_helpers import build, close, device_state, rel_errors, tilemag
+from paper_2107_05364_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NUM_SHAPES = 20  # compiled launch shapes of the six-plane stage kernel
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tmg():
+    return tilemag()
+
+
+@pytest.fixture(scope="module")
+def ctx(tmg):
+    c = tmg.Context(0)
+    yield c
+    try:
+        c.close()
+    except tmg.TilemagError:
+        pass
+
+
+@pytest.fixture(scope="module")
+def refined(orc):
+    """701-tile refined slab (edges 2.5-20 nm), per-tile Ms, uniaxial
+    anisotropy with random axes, three states and three applied fields."""
+    slab = W.refined_slab(n_target=701, lx=200e-9, ly=60e-9, lz=20e-9)
+    c, s = slab.centers, slab.sizes
+    n = c.shape[0]
+    Ms = np.linspace(6.0e5, 9.0e5, n)
+    Ku = np.full(n, 3.0e4)
+    easy = W.random_unit_vectors(11, n)
+    m = np.stack([W.random_unit_vectors(30 + k, n) for k in range(3)]).astype(np.float32)
+    Ha = np.array([[2e4, -1e4, 5e3], [0.0, 3e4, 0.0], [-1e4, 0.0, 2e4]], np.float32)
+    P = orc.Problem(c, s, Ms, 1.3e-11, 0.3, Ku=Ku, easy=easy)
+    H = [P.heff(m[k].astype(np.float64), Ha[k].astype(np.float64)) for k in range(3)]
+    steps = []
+    for k in range(3):
+        y = m[k].astype(np.float64).copy()
+        k1 = P.rhs(y, Ha[k].astype(np.float64))
+        ok, dtn, tn, err, _ = P.dp45_attempt(y, k1, Ha[k].astype(np.float64), 2e-14, 0.0)
+        steps.append((ok, dtn, tn, y))
+    return dict(c=c, s=s, Ms=Ms, Ku=Ku, easy=easy, m=m, Ha=Ha, H=H, steps=steps)
+
+
+def test_shape_count(tmg):
+    assert tmg.tm_num_shapes() == NUM_SHAPES
+
+
+@pytest.mark.parametrize("shape", list(range(NUM_SHAPES)))
+def test_every_launch_shape_matches_oracle(tmg, ctx, refined, shape):
+    import torch
+
+    R = refined
+    _say("launch shape %d: %s" % (shape, tmg.tm_shape_info(shape)))
+    g, T, p = build(tmg, ctx, R["c"], R["s"], Ms=R["Ms"], alpha=0.3, Ku=R["Ku"], easy=R["easy"])
+    tmg.tm_problem_set_shape(p.handle, shape)
+    assert tmg.tm_problem_shape(p.handle) == shape
+    Ha = torch.as_tensor(R["Ha"], device="cuda")
+    H = p.heff(device_state(R["m"]), Ha).cpu().numpy()
+    for k in range(3):
+        e2, emax = rel_errors(H[k], R["H"][k])
+        assert e2 <= 1e-5 and emax <= 1e-5, (shape, k, e2, emax)
+    md = device_state(R["m"])
+    t, dt, steps, st = p.run(md, Ha, tmg.TM_DP45, dt=2e-14, max_steps=1, max_attempts=1)
+    got = md.cpu().numpy()
+    for k in range(3):
+        ok, dtn, tn, y = R["steps"][k]
+        assert bool(int(steps.cpu()[k]) == 1) == ok, (shape, k)
+        assert float(t.cpu()[k]) == tn
+        assert np.abs(got[k] - y).max() <= 1e-5, (shape, k)
+        assert abs(float(dt.cpu()[k]) / dtn - 1) < 1e-3, (shape, k)
+    close(g, T, p)
+
+
+@pytest.mark.parametrize("layout", ["psym6", "psym4"])
+def test_pair_symmetric_per_tile_ms(tmg, ctx, orc, layout):
+    """Per-tile Ms on identical tiles: the stored operator is pair-symmetric,
+    the moments are not; a swapped source / target weight fails here."""
+    import torch
+
+    c, s = W.grid(19, 7, 2, 5e-9, 4e-9, 3e-9) if layout == "psym6" else W.grid(41, 9, 1, 5e-9, 4e-9, 3e-9)
+    n = c.shape[0]
+    Ms = np.linspace(6.0e5, 9.0e5, n)
+    easy = W.random_unit_vectors(13, n)
+    lay = tmg.TM_LAYOUT_PSYM6 if layout == "psym6" else tmg.TM_LAYOUT_PSYM4
+    _say("pair-symmetric %s with per-tile Ms, n=%d" % (layout, n))
+    g, T, p = build(tmg, ctx, c, s, Ms=Ms, alpha=0.3, Ku=2e4, easy=easy, layout=lay)
+    P = orc.Problem(c, s, Ms, 1.3e-11, 0.3, Ku=2e4, easy=easy)
+    m = np.stack([W.random_unit_vectors(40 + k, n) for k in range(3)]).astype(np.float32)
+    m[2, 7, 0] = np.nan  # diagnostics: flagged alone
+    Ha = np.array([[1e4, 2e4, -5e3], [0.0, 0.0, 3e4], [1e4, 0, 0]], np.float32)
+    Had = torch.as_tensor(Ha, device="cuda")
+    Hd = p.demag(device_state(m)).cpu().numpy()
+    He = p.heff(device_state(m), Had).cpu().numpy()
+    D = p.diagnostics(device_state(m), Had).cpu().numpy()
+    for k in range(2):
+        mk = m[k].astype(np.float64)
+        e2, emax = rel_errors(Hd[k], P.demag(mk))
+        assert e2 <= 1e-5 and emax <= 1e-5, ("demag", k, e2, emax)
+        e2, emax = rel_errors(He[k], P.heff(mk, Ha[k].astype(np.float64)))
+        assert e2 <= 1e-5 and emax <= 1e-5, ("heff", k, e2, emax)
+        want = P.diagnostics(mk, Ha[k].astype(np.float64))
+        np.testing.assert_allclose(D[k, :4], want[:4], rtol=1e-5, atol=1e-12 * np.abs(want[:4]).max())
+        np.testing.assert_allclose(D[k, 4:7], want[4:7], rtol=0, atol=1e-6)
+        assert abs(D[k, 7] - want[7]) <= 1e-5 * want[7]
+        assert D[k, 8] == 0.0
+    assert D[2, 8] == 1.0
+    # one Dormand-Prince attempt of the two finite states
+    md = device_state(m[:2])
+    t, dt, steps, st = p.run(md, Had[:2].contiguous(), tmg.TM_DP45, dt=2e-14, max_steps=1, max_attempts=1)
+    got = md.cpu().numpy()
+    for k in range(2):
+        y = m[k].astype(np.float64).copy()
+        k1 = P.rhs(y, Ha[k].astype(np.float64))
+        ok, dtn, tn, err, _ = P.dp45_attempt(y, k1, Ha[k].astype(np.float64), 2e-14, 0.0)
+        assert ok and int(steps.cpu()[k]) == 1
+        assert float(t.cpu()[k]) == tn
+        assert np.abs(got[k] - y).max() <= 1e-5, k
+        assert abs(float(dt.cpu()[k]) / dtn - 1) < 1e-3
+    close(g, T, p)
+
+
+def _oracle_to_time(P, y0, Ha, t_end, tol, dt0=1e-14):
+    y = np.array(y0, np.float64).copy()
+    k1 = P.rhs(y, Ha)
+    dt, t = dt0, 0.0
+    while t < t_end:
+        ok, dt, t, _, _ = P.dp45_attempt(y, k1, Ha, dt, t, tol, tol, True, t_end)
+    return y
+
+
+def test_psym4_film_200_steps_vs_oracle(tmg, ctx, orc):
+    """The headline configuration (full film, four-plane operator, adaptive
+    DP45) over 200 accepted steps, against the oracle integrated to the GPU's
+    end time."""
+    import torch
+
+    wl = W.thin_film()
+    _say("psym4 film 200 accepted steps vs oracle")
+    g, T, p = build(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha, layout=tmg.TM_LAYOUT_PSYM4)
+    m0 = wl.m0.astype(np.float32)
+    Ha = wl.Ha.astype(np.float32)
+    md = device_state(m0)
+    t, dt, steps, st = p.run(md, torch.as_tensor(Ha, device="cuda"), tmg.TM_DP45, dt=1e-14,
+                             max_steps=200)
+    assert int(steps.cpu()[0]) == 200
+    t_gpu = float(t.cpu()[0])
+    P = orc.Problem(wl.centers, wl.sizes, wl.Ms, wl.A, wl.alpha)
+    h = Ha[0].astype(np.float64)
+    _, tn, _, _ = P.dp45(m0[0].astype(np.float64), h, 1e-14, 200)
+    assert abs(t_gpu / tn - 1) < 1e-3
+    y = _oracle_to_time(P, m0[0], h, t_gpu, 1e-6)
+    got = md.cpu().numpy()[0]
+    _say("psym4 film 200 steps: t_gpu %.6e t_orc %.6e |dm| %.2e" % (t_gpu, tn, np.abs(got - y).max()))
+    assert np.abs(got - y).max() <= 5e-5
+    assert np.abs(np.linalg.norm(got, axis=1) - 1).max() < 1e-6
+    close(g, T, p)

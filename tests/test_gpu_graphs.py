@@ -32,7 +32,7 @@ def ctx(tmg):
         pass
 
 
-CASES = ["sym6", "psym6", "bsr6", "dense9_fp32", "dense9_fp16x3"]
+CASES = ["sym6", "psym6", "psym4", "bsr6", "dense9_fp32", "dense9_bf16x3", "dense9_fp16x3"]
 
 
 @pytest.mark.parametrize("case", CASES)
@@ -46,12 +46,16 @@ def test_graph_replays_match_direct_launches(tmg, ctx, case):
     extra = []
     if case == "psym6":
         T = tmg.Tensor(ctx, g, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM6)
+    elif case == "psym4":  # the film is one layer of identical tiles
+        T = tmg.Tensor(ctx, g, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM4)
     elif case == "bsr6":
         T0 = tmg.Tensor(ctx, g)
         T = T0.threshold(0.4)
         extra.append(T0)
     elif case == "dense9_fp32":
         T = tmg.Tensor(ctx, g, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_DENSE9)
+    elif case == "dense9_bf16x3":
+        T = tmg.Tensor(ctx, g, tmg.TM_PREC_BF16X3, tmg.TM_LAYOUT_DENSE9)
     elif case == "dense9_fp16x3":
         T = tmg.Tensor(ctx, g, tmg.TM_PREC_FP16X3, tmg.TM_LAYOUT_DENSE9)
     else:

@@ -442,9 +442,9 @@ def test_diagnostics_vs_oracle(tmg, ctx, orc, layout):
     # the four-plane layout needs a single layer of tiles
     c, s = W.grid(9, 5, 2, 5e-9, 4e-9, 3e-9) if layout != "psym4" else W.grid(15, 6, 1, 5e-9, 4e-9, 3e-9)
     n = c.shape[0]
-    # pair symmetry needs identical tiles and a uniform Ms; the other layouts
-    # get per-tile Ms to exercise the moment weights
-    Ms = 8.0e5 if layout in ("psym6", "psym4") else np.linspace(6e5, 9e5, n)
+    # per-tile Ms exercises the moment weights (pair symmetry is a property
+    # of the operator of identical tiles, not of the moments)
+    Ms = np.linspace(6e5, 9e5, n)
     store, lay = {"sym6": (tmg.TM_PREC_FP32, tmg.TM_LAYOUT_SYM6), "psym6": (tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM6),
                   "psym4": (tmg.TM_PREC_FP32, tmg.TM_LAYOUT_PSYM4),
                   "dense9": (tmg.TM_PREC_FP32, tmg.TM_LAYOUT_DENSE9)}[layout]
