@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-threshold", action="store_true")
     ap.add_argument("--no-sp3", action="store_true")
+    ap.add_argument("--no-cache-free", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="counter runs: one 1 GiB device copy (calibration) and the stage kernel "
                          "of the film workload only")
@@ -97,9 +98,12 @@ def counter_traffic(layout, kname):
     return int(vals["traffic_bytes_per_launch"].strip())
 
 
-def cpu_baseline(wl, nsteps):
+def cpu_baseline(wl, nsteps, m_final=None, hd_final=None, batched=None):
     """The FP64 oracle, as it stands, on a bounded sample of the same
-    workload: operator assembly once, then `nsteps` attempted DP45 steps."""
+    workload: operator assembly once, then `nsteps` attempted DP45 steps.
+    The same leg states the GPU results' errors against the oracle: H_d of
+    the headline run's final state, and H_d of the batched states for each
+    storage precision (one FP64 product with the oracle's dense operator)."""
     import oracle
 
     t0 = time.perf_counter()
@@ -122,31 +126,52 @@ def cpu_baseline(wl, nsteps):
         _, dt, t, _, _ = P.dp45_attempt(y, k1, Ha, dt, t)
     el1 = time.perf_counter() - t0
     oracle.set_num_threads(cores)
-    return {"value": nsteps / el, "unit": "steps/s", "cores": cores, "kind": "oracle",
+    base = {"value": nsteps / el, "unit": "steps/s", "cores": cores, "kind": "oracle",
             "sample": "%d attempted DP45 steps of the same film workload after one FP64 operator "
                       "assembly (%.1f s, not included); single-thread rate from %d further steps"
                       % (nsteps, t_asm, n1),
             "single_thread_steps_per_s": round(n1 / el1, 2), "assembly_s": round(t_asm, 3)}
+    errs = {}
+    if m_final is not None:
+        want = P.demag(m_final.astype(np.float64))
+        errs["headline"] = rel_errors(hd_final, want)
+    if batched:
+        # the oracle's dense FP64 operator of the batched film (same geometry
+        # and Ms), one product for all states
+        A = oracle.assemble(batched["centers"], batched["sizes"])
+        m32 = batched["m"].astype(np.float64)
+        B = m32.shape[0]
+        ref = -(batched["Ms"] * m32.reshape(B, -1)) @ A.T
+        del A
+        for name, hd in batched["hd"].items():
+            errs["batched_" + name] = rel_errors(hd.reshape(B, -1), ref)
+    return base, errs
+
+
+def rel_errors(got, want):
+    """Relative 2-norm and max-norm errors of a GPU result against the oracle."""
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    d = got - want
+    return {"rel_err_2norm": float(np.linalg.norm(d) / np.linalg.norm(want)),
+            "rel_err_max": float(np.abs(d).max() / np.abs(want).max())}
 
 
 def batched_section(tmg, W, torch, attempts=60, profile_iters=20):
     """B = 128 states on the film geometry sharing one DENSE9 operator: one
     MFMA GEMM per right-hand side, in float32 and in bf16 / fp16 hi + lo
-    split precision.  The H_d error is measured against the product with the
-    float64 operator assembled by the library (float64 on the host)."""
+    split precision.  Returns the record and the GPU H_d of the initial
+    states per precision, whose errors the oracle leg states."""
     wl = W.hysteresis_batch(B=128)
     n, B = wl.n, wl.batch
     ctx = tmg.Context(0)
     geom = tmg.Geometry(ctx, wl.centers, wl.sizes)
-    T64 = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP64, tmg.TM_LAYOUT_DENSE9)
-    A = T64.dense()
-    T64.close()
     m32 = wl.m0.astype(np.float32)
-    ref = -(wl.Ms * m32.astype(np.float64).reshape(B, -1)) @ A.T
-    del A
     Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
     out = {"workload": "hysteresis film 100x25x1 (N=2500), B=128 states, +80..-80 mT, DP45",
-           "err_reference": "H_d from the library's FP64 operator, FP64 product on the host"}
+           "err_reference": "H_d of the initial states against the FP64 oracle (its dense operator, "
+                            "one FP64 product on the host), stated by the cpu_baseline leg"}
+    hds = {}
     peaks = {"fp32": 157.3, "bf16x3": 2500.0, "fp16x3": 2500.0}
     for prec, name in ((tmg.TM_PREC_FP32, "fp32"), (tmg.TM_PREC_BF16X3, "bf16x3"),
                        (tmg.TM_PREC_FP16X3, "fp16x3")):
@@ -154,9 +179,7 @@ def batched_section(tmg, W, torch, attempts=60, profile_iters=20):
         p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
         ksplits, _ = tmg.tm_problem_tune(p.handle, B, 5)  # K splits of the product
         m = torch.as_tensor(m32, device="cuda")
-        hd = p.demag(m).cpu().numpy().reshape(B, -1).astype(np.float64)
-        err2 = float(np.linalg.norm(hd - ref) / np.linalg.norm(ref))
-        errm = float(np.abs(hd - ref).max() / np.abs(ref).max())
+        hds[name] = p.demag(m).cpu().numpy()
         rhs_ms, _ = tmg.tm_profile_field(p.handle, B, profile_iters)
         flops = 2.0 * 9 * n * n * B * (3 if name != "fp32" else 1)
         op_bytes = 36.0 * n * n
@@ -173,13 +196,49 @@ def batched_section(tmg, W, torch, attempts=60, profile_iters=20):
                      "mfma_tflops": round(flops / (rhs_ms * 1e-3) / 1e12, 2),
                      "mfma_frac": round(flops / (rhs_ms * 1e-3) / 1e12 / peaks[name], 4),
                      "operator_gbs": round(op_bytes / (rhs_ms * 1e-3) / 1e9, 1),
-                     "hd_rel_err_2norm": err2, "hd_rel_err_max": errm, "k_splits_tuned": ksplits,
+                     "k_splits_tuned": ksplits,
                      "accepted_min": int(st.accepted_min), "rejected": int(st.rejected)}
         p.close()
         T.close()
     geom.close()
     ctx.close()
-    return out
+    return out, {"centers": wl.centers, "sizes": wl.sizes, "Ms": wl.Ms, "m": m32, "hd": hds}
+
+
+def cache_free_section(tmg, W, torch, layout, attempts=20):
+    """The headline's operator pass on an operator larger than the 256 MB
+    Infinity Cache: the SP4 film at [160, 40, 1] tiles (N = 6400; PSYM4
+    327.7 MB, PSYM6 491.6 MB, SYM6 983 MB), timed inside DP45 steps like
+    the headline."""
+    wl = W.thin_film(nx=160, ny=40)
+    n = wl.n
+    ctx = tmg.Context(0)
+    geom = tmg.Geometry(ctx, wl.centers, wl.sizes)
+    T = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, LAYOUT_CODE[layout])
+    p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
+    choice, _ = tmg.tm_problem_tune(p.handle, 1, 10)
+    m = torch.as_tensor(wl.m0.astype(np.float32), device="cuda")
+    Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt = torch.full((1,), 1e-14, dtype=torch.float64, device="cuda")
+    p.run(m, Ha, tmg.TM_DP45, dt=dt, t=t, max_steps=1 << 40, max_attempts=5)
+    op_ms, op_n = tmg.tm_profile_run(p.handle, n, tmg.TM_DP45, m, Ha, t, dt,
+                                     tmg.tm_run_cfg(1 << 40, attempts, 0.0, 1e-6, 1e-6, 0.0, 0.0, 1, 0, 64))
+    _, stored = tmg.tm_profile_field(p.handle, 1, 5)
+    p.close()
+    T.close()
+    geom.close()
+    ctx.close()
+    if layout == "sym6":
+        alg = 24 * n * n + 24 * n
+    else:
+        alg = n * (n + 1) // 2 * (4 if layout == "psym4" else 6) * 4 + 24 * n
+    avg = op_ms / op_n
+    return {"workload": "SP4 film [160,40,1] tiles (N=%d), %s operator %.1f MB as stored" % (n, layout.upper(), stored / 1e6),
+            "tile_pass_loads" if layout != "sym6" else "stage_kernel_shape":
+                (("nontemporal" if choice == 1 else "cached") if layout != "sym6" else choice),
+            "avg_launch_us": round(avg * 1e3, 3), "launches_timed": op_n, "bytes_per_launch": alg,
+            "achieved": round(alg / (avg * 1e-3) / 1e9, 1), "frac": round(alg / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def large_section(tmg, W, torch, attempts=20, profile_iters=10, with_oracle=True):
@@ -628,47 +687,58 @@ def main():
     # (pair-symmetric layouts: cached or nontemporal operator loads in the tile pass)
     shape, _ = tmg.tm_problem_tune(p.handle, 1, 50)
     nt_loads = psym and shape == 1
-    # dominant kernel: the operator pass (mode 3: the tile pass of the
-    # pair-symmetric layout; the fused stage kernel of the six-plane layout)
-    prof_mode = 3 if psym else 0
-
-    if args.profile_only:
-        ms, nb = tmg.tm_profile_field_mode(p.handle, 1, prof_mode, args.profile_iters)
-        print(json.dumps({"profile_only": True, "stage_kernel_us": round(ms * 1e3, 3),
-                          "bytes_per_launch": nb, "launches": args.profile_iters + 1}), flush=True)
-        p.close()
-        T.close()
-        geom.close()
-        ctx.close()
-        return
     m = torch.as_tensor(wl.m0.astype(np.float32), device="cuda")
     Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
     t = torch.zeros(1, dtype=torch.float64, device="cuda")
     dt = torch.full((1,), 1e-14, dtype=torch.float64, device="cuda")
     big = 1 << 40
+
+    if args.profile_only:
+        # counter runs: the dominant kernel as it runs inside the steps
+        cfg = tmg.tm_run_cfg(big, args.profile_iters, 0.0, 1e-6, 1e-6, 0.0, 0.0, 1, 0, 64)
+        op_ms, op_n = tmg.tm_profile_run(p.handle, n, tmg.TM_DP45, m, Ha, t, dt, cfg)
+        print(json.dumps({"profile_only": True, "operator_pass_us": round(op_ms / op_n * 1e3, 3),
+                          "launches": op_n}), flush=True)
+        p.close()
+        T.close()
+        geom.close()
+        ctx.close()
+        return
     # warmup (graph capture happens here)
     p.run(m, Ha, tmg.TM_DP45, dt=dt, t=t, max_steps=big, max_attempts=max(1, args.warmup))
+    steps_buf = torch.zeros(1, dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tt, dd, steps, st = p.run(m, Ha, tmg.TM_DP45, dt=dt, t=t, max_steps=big,
-                              max_attempts=args.steps)
+    st = tmg.tm_run(p.handle, n, tmg.TM_DP45, m, Ha, t, dt, steps_buf,
+                    tmg.tm_run_cfg(big, args.steps, 0.0, 1e-6, 1e-6, 0.0, 0.0, 1, 1, 64))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     assert torch.isfinite(m).all().item(), "non-finite state after the timed run"
-    accepted = int(steps.cpu()[0])
+    accepted = int(steps_buf.cpu()[0])
+    t_sim = float(t.cpu()[0])
+    m_final = m.cpu().numpy()[0].copy()
+    hd_final = p.demag(m).cpu().numpy()[0]
 
-    # dominant kernel, timed with HIP events on the stream it runs on
-    avg_ms, bytes_per = tmg.tm_profile_field_mode(p.handle, 1, prof_mode, args.profile_iters)
-    eval_ms, _ = tmg.tm_profile_field(p.handle, 1, args.profile_iters)
-    achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+    # dominant kernel inside the step: the same number of attempts again from
+    # the final state, every operator pass stamped with its own start and end
+    # (kernel timestamps on the stream it runs on)
+    op_ms, op_n = tmg.tm_profile_run(p.handle, n, tmg.TM_DP45, m, Ha, t, dt,
+                                     tmg.tm_run_cfg(big, args.steps, 0.0, 1e-6, 1e-6, 0.0, 0.0, 1, 0, 64))
+    avg_ms = op_ms / op_n
+    eval_ms, stored_bytes = tmg.tm_profile_field(p.handle, 1, 20)
     if psym:
-        kname = "k_psym_tiles<true,true,%s,%d>" % ("true" if nt_loads else "false",
-                                                   4 if args.layout == "psym4" else 6)
+        planes = 4 if args.layout == "psym4" else 6
+        alg_bytes = n * (n + 1) // 2 * planes * 4 + 24 * n
+        alg_basis = "N(N+1)/2 blocks x %d planes x 4 B + 24 N (state in, slots out not counted)" % planes
+        kname = "k_psym_tiles<true,true,%s,%d>" % ("true" if nt_loads else "false", planes)
         kdesc = (" (pair-symmetric tile pass of the demag product; the slot sum and epilogue run in "
                  "a second launch, included in field_evaluation_us)")
     else:
+        alg_bytes = 24 * n * n + 24 * n
+        alg_basis = "6 planes x N^2 x 4 B + 24 N"
         kname = "k_field<%d,%d,%d,%d,STAGE>" % tmg.tm_shape_info(shape)
         kdesc = " (fused demag matvec + H_eff + LL + stage update)"
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     traffic = counter_traffic(args.layout, kname)
 
     rec = {
@@ -690,20 +760,28 @@ def main():
                    "accepted_steps": accepted, "rejected_steps": int(st.rejected),
                    "stage_kernel_shape": -1 if psym else shape,
                    "tile_pass_loads": ("nontemporal" if nt_loads else "cached") if psym else None,
-                   "simulated_ns": round(float(tt.cpu()[0]) * 1e9, 4),
+                   "simulated_ns": round(t_sim * 1e9, 4),
                    "assembly_ms": round(asm_ms, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": kname + kdesc,
-                     "avg_launch_us": round(avg_ms * 1e3, 3), "bytes_per_launch": bytes_per,
+                     "avg_launch_us": round(avg_ms * 1e3, 3), "launches_timed": op_n,
+                     "timing": "kernel start/end timestamps of every operator pass of %d further attempted "
+                               "steps from the final state (tm_profile_run, direct launches)" % args.steps,
+                     "bytes_per_launch": alg_bytes, "bytes_basis": "algorithmic: " + alg_basis,
+                     "stored_bytes_per_launch": stored_bytes,
+                     "cache_resident": stored_bytes < (256 << 20),
                      "field_evaluation_us": round(eval_ms * 1e3, 3)},
     }
+    if stored_bytes < (256 << 20) and not args.no_cache_free:
+        rec["roofline"]["cache_free"] = cache_free_section(tmg, W, torch, args.layout)
     p.close()
     T.close()
     geom.close()
     ctx.close()
+    batched_data = None
     if not args.no_batched:
-        bat = batched_section(tmg, W, torch)
+        bat, batched_data = batched_section(tmg, W, torch)
         best = max(v["state_steps_per_s"] for k, v in bat.items() if isinstance(v, dict))
         bat["vs_single_fp32_solve"] = round(best / rec["value"], 2)
         rec["batched"] = bat
@@ -722,7 +800,15 @@ def main():
     if not args.no_peaks:
         rec["achievable_peaks"] = peaks_section(torch, tmg)
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+        base, errs = cpu_baseline(wl, args.cpu_steps, m_final, hd_final, batched_data)
+        rec["cpu_baseline"] = base
+        rec["error_vs_oracle"] = dict(quantity="H_d of the timed run's final state against the FP64 oracle",
+                                      tolerance=1e-5, **errs["headline"])
+        if batched_data is not None:
+            for name in batched_data["hd"]:
+                e = errs["batched_" + name]
+                rec["batched"][name]["hd_rel_err_2norm"] = e["rel_err_2norm"]
+                rec["batched"][name]["hd_rel_err_max"] = e["rel_err_max"]
     print(json.dumps(rec), flush=True)
 
 

@@ -92,7 +92,9 @@ int32_t tm_version(void);
 /* Achievable rates of device `device`, measured with the library's own
  * kernels (context for the roofline fractions, which use published peaks):
  * a streaming read of a zero-filled read_bytes buffer (1 MiB .. 16 GiB,
- * allocated and freed by the call) in GB/s, and register-only loops of the
+ * rounded down to whole 64 KiB chunks, one workgroup per chunk as the
+ * operator passes read their tiles, the faster of cached and nontemporal
+ * loads; allocated and freed by the call) in GB/s, and register-only loops of the
  * 32x32x16 bf16 and 16x16x4 float32 MFMA instructions the batched product
  * issues, in TFLOP/s.  Output pointers may be NULL (that measurement is
  * skipped).  Blocking; uses the device's null stream.  TM_EINVAL for a size
@@ -308,6 +310,21 @@ tm_status tm_profile_field(tm_problem* p, int64_t B, int32_t iters, hipStream_t 
  * tile kernel without the reduction + epilogue launch; otherwise as 0). */
 tm_status tm_profile_field_mode(tm_problem* p, int64_t B, int32_t mode, int32_t iters,
                                 hipStream_t stream, double* avg_ms, int64_t* bytes_out);
+
+/* Durations of the operator pass inside an integration: runs B states for
+ * exactly cfg->max_attempts attempted steps (>= 1, <= 100000) as tm_run does
+ * (same kernels, launch shapes and order; m, t and dt are updated the same
+ * way; launched directly rather than from a captured graph), and stamps every
+ * launch of the operator kernel -- the pair-symmetric tile pass, the fused
+ * stage kernel of SYM6, the sparse kernel of BSR6 or the batched product of
+ * DENSE9 -- with its own start and end (hipExtLaunchKernelGGL events on
+ * `stream`).  op_ms receives the sum of those durations [ms], op_launches the
+ * number of launches (DP45: 1 + 6 per attempt; RK4: 4 per step).  Blocking.
+ * TM_EBUSY if called while another timing runs on the same thread;
+ * otherwise the errors of tm_run. */
+tm_status tm_profile_run(tm_problem* p, tm_integrator integ, int64_t B, float* m, const float* Ha, double* t,
+                         double* dt, const tm_run_cfg* cfg, double* op_ms, int64_t* op_launches,
+                         hipStream_t stream);
 
 /* Number of launch shapes (workgroup width x target tiles per workgroup x
  * load kind) the fused field kernel is compiled for. */

@@ -69,12 +69,13 @@ Workspace::~Workspace() {
     float* fl[] = {y, ya, yb, y5, k[0], k[1], k[2], k[3], k[4], k[5], k[6], Ha, hd, part};
     for (float* p : fl)
         if (p) (void)hipFree(p);
-    void* vp[] = {xh, xl, t, h, dt, errp, dmxp, snap, steps, rejected, flags, acc, params, esum, diag};
+    void* vp[] = {xh, xl, t, h, dt, errp, dmxp, snap, steps, rejected, flags, acc, params, esum, diag, stat};
     for (void* p : vp)
         if (p) (void)hipFree(p);
     if (host_params) (void)hipHostFree(host_params);
     if (host_flags) (void)hipHostFree(host_flags);
     if (host_steps) (void)hipHostFree(host_steps);
+    if (host_stat) (void)hipHostFree(host_stat);
     if (graph1) (void)hipGraphExecDestroy(graph1);
     if (graphK) (void)hipGraphExecDestroy(graphK);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -596,7 +597,7 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
     const bool psym = is_psym(T->layout);
     if (psym) pbytes = psym_partial_floats(T, bcap) * 4;
     const int64_t dbytes = bcap * (nblk * 6 + 4) * 8;  // diagnostics partials + energies
-    int64_t bytes = 12 * sb + bcap * 12 + bcap * (8 * 7 + 8 * 2 + 4 * 2 + 8 * kSnapStride) + 16 * bcap * n + 64 +
+    int64_t bytes = 12 * sb + bcap * 12 + bcap * (8 * 7 + 8 * 2 + 4 * 2 + 8 * kSnapStride + 24) + 16 * bcap * n + 64 +
                     RP_COUNT * 8 + nblk * bcap * 32 + xbytes + pbytes + dbytes;
     {
         std::lock_guard<std::mutex> lk(p->ctx->mu);
@@ -642,6 +643,7 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->params), RP_COUNT * 8);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->esum), nblk * bcap * 32);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->diag), dbytes);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->stat), bcap * 24);
     w->esum_blocks = nblk * bcap;
     if (dense && xbytes && e == hipSuccess) {
         const int64_t half = T->prec == TM_PREC_FP32 ? xbytes : xbytes / 2;
@@ -655,6 +657,7 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&w->host_params), RP_COUNT * 8);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&w->host_flags), bcap * 4);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&w->host_steps), bcap * 8 * 2);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&w->host_stat), bcap * 24);
     if (e != hipSuccess) {
         set_error("workspace allocation (%lld bytes): %s", static_cast<long long>(bytes),
                   hipGetErrorString(e));

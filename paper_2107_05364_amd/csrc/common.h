@@ -1,6 +1,7 @@
 // Internal declarations of the tilemag library (not part of the C ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -215,11 +216,13 @@ struct Workspace {
     double* params = nullptr; // RunParams on device
     double* esum = nullptr;   // energy partial sums
     double* diag = nullptr;   // diagnostics: [B][nblk][6] partials, then [B][4] energies
+    int64_t* stat = nullptr;  // end of a run: [3][B] accepted steps, rejected attempts, flags
     int64_t esum_blocks = 0;
     // pinned host mirrors (run parameters, polling)
     double* host_params = nullptr;
     int32_t* host_flags = nullptr;
     int64_t* host_steps = nullptr;
+    int64_t* host_stat = nullptr;  // pinned mirror of stat
     // captured step graphs: one attempt, and kGraphSteps attempts
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph1 = nullptr;
@@ -236,6 +239,30 @@ constexpr int kGraphSteps = 16;
 // flags as 64-bit integer bit patterns.
 enum SnapSlot : int { SN_H = 0, SN_T = 1, SN_DT = 2, SN_STEPS = 3, SN_REJ = 4, SN_FLAGS = 5 };
 constexpr int kSnapStride = 8;
+
+// Durations of the operator-pass launches inside an integration
+// (tm_profile_run).  While a timer is installed on the calling thread, the
+// launchers of the operator kernels (k_field, k_psym_tiles, k_field_bsr, the
+// batched products) take the next pair of events and launch through
+// hipExtLaunchKernelGGL, which stamps the kernel's own start and end on them;
+// once the pairs run out they launch plainly.
+struct OpTimer {
+    std::vector<hipEvent_t> ev;  // two per launch
+    int64_t used = 0;            // launches stamped
+};
+OpTimer*& op_timer();  // the calling thread's timer (nullptr: none)
+
+template <typename... Formals, typename... Actuals>
+inline void launch_op(void (*kernel)(Formals...), dim3 grid, dim3 block, hipStream_t s, Actuals... args) {
+    OpTimer* t = op_timer();
+    if (t && 2 * t->used + 1 < static_cast<int64_t>(t->ev.size())) {
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t->ev[2 * t->used], t->ev[2 * t->used + 1], 0,
+                              static_cast<Formals>(args)...);
+        ++t->used;
+    } else {
+        kernel<<<grid, block, 0, s>>>(args...);
+    }
+}
 
 // Kernel launchers (fieldstep.hip).
 enum class Epi : int { HD = 0, HEFF = 1, DMDT = 2, STAGE = 3, RK4_FINAL = 4, DP_LAST = 5 };

@@ -155,15 +155,15 @@ tm_status launch_tt(const DevProblem& P, const MvArgs& M, Epi mode, int64_t B, c
     const dim3 grid(static_cast<unsigned>((M.n + TT - 1) / TT), static_cast<unsigned>(B));
     const dim3 block(BLOCK);
     switch (mode) {
-        case Epi::HD: k_field<BLOCK, TT, NT, WPE, Epi::HD><<<grid, block, 0, st>>>(P, M, e); break;
-        case Epi::HEFF: k_field<BLOCK, TT, NT, WPE, Epi::HEFF><<<grid, block, 0, st>>>(P, M, e); break;
-        case Epi::DMDT: k_field<BLOCK, TT, NT, WPE, Epi::DMDT><<<grid, block, 0, st>>>(P, M, e); break;
-        case Epi::STAGE: k_field<BLOCK, TT, NT, WPE, Epi::STAGE><<<grid, block, 0, st>>>(P, M, e); break;
+        case Epi::HD: launch_op(k_field<BLOCK, TT, NT, WPE, Epi::HD>, grid, block, st, P, M, e); break;
+        case Epi::HEFF: launch_op(k_field<BLOCK, TT, NT, WPE, Epi::HEFF>, grid, block, st, P, M, e); break;
+        case Epi::DMDT: launch_op(k_field<BLOCK, TT, NT, WPE, Epi::DMDT>, grid, block, st, P, M, e); break;
+        case Epi::STAGE: launch_op(k_field<BLOCK, TT, NT, WPE, Epi::STAGE>, grid, block, st, P, M, e); break;
         case Epi::RK4_FINAL:
-            k_field<BLOCK, TT, NT, WPE, Epi::RK4_FINAL><<<grid, block, 0, st>>>(P, M, e);
+            launch_op(k_field<BLOCK, TT, NT, WPE, Epi::RK4_FINAL>, grid, block, st, P, M, e);
             break;
         case Epi::DP_LAST:
-            k_field<BLOCK, TT, NT, WPE, Epi::DP_LAST><<<grid, block, 0, st>>>(P, M, e);
+            launch_op(k_field<BLOCK, TT, NT, WPE, Epi::DP_LAST>, grid, block, st, P, M, e);
             break;
     }
     TM_TRY_HIP(hipGetLastError());

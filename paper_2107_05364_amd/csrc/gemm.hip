@@ -486,7 +486,8 @@ __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __res
 
 template <int PREC, int NST>
 tm_status launch_gemm_t(const GemmArgs& G, int64_t rowblocks, int64_t splits, hipStream_t s) {
-    k_gemm<PREC, NST><<<dim3(static_cast<unsigned>(rowblocks), static_cast<unsigned>(splits)), 256, 0, s>>>(G);
+    launch_op(k_gemm<PREC, NST>, dim3(static_cast<unsigned>(rowblocks), static_cast<unsigned>(splits)), dim3(256),
+              s, G);
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
 }
@@ -495,9 +496,9 @@ template <int PREC>
 tm_status launch_gemm_split(int nsb, const GemmArgs& G, int64_t rowblocks, int64_t splits, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(rowblocks), static_cast<unsigned>(splits));
     switch (nsb) {
-        case 1: k_gemm_split<PREC, 1><<<grid, 256, 0, s>>>(G); break;
-        case 2: k_gemm_split<PREC, 2><<<grid, 256, 0, s>>>(G); break;
-        case 4: k_gemm_split<PREC, 4><<<grid, 256, 0, s>>>(G); break;
+        case 1: launch_op(k_gemm_split<PREC, 1>, grid, dim3(256), s, G); break;
+        case 2: launch_op(k_gemm_split<PREC, 2>, grid, dim3(256), s, G); break;
+        case 4: launch_op(k_gemm_split<PREC, 4>, grid, dim3(256), s, G); break;
         default:
             set_error("batched product: unsupported 32-state tile count %d", nsb);
             return TM_EINVAL;

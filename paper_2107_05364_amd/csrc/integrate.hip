@@ -31,33 +31,68 @@ constexpr double kDpA[7][6] = {
     {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
     {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
 
-__global__ void k_init_run(int64_t B, const double* __restrict__ t_in, const double* __restrict__ dt_in,
-                           const double* __restrict__ prm, double* __restrict__ t,
-                           double* __restrict__ h, double* __restrict__ dt,
-                           int64_t* __restrict__ steps, int64_t* __restrict__ rejected,
-                           int32_t* __restrict__ flags, int32_t* __restrict__ acc) {
-    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= B) return;
-    const double t0 = t_in[s], d0 = dt_in[s], t_end = prm[RP_TEND];
-    t[s] = t0;
-    dt[s] = d0;
-    double hh = d0;
-    int32_t f = 0;
-    if (t_end > 0.0 && t0 + hh > t_end) hh = t_end - t0;
-    if (prm[RP_MAX_STEPS] <= 0.0 || (t_end > 0.0 && t0 >= t_end)) f = FLAG_DONE;
-    h[s] = f ? 0.0 : hh;
-    flags[s] = f;
-    steps[s] = 0;
-    rejected[s] = 0;
-    acc[s] = 0;
+// Run parameters passed by value to the prologue (RunParam order).
+struct RunParams {
+    double v[RP_COUNT];
+};
+
+// Prologue of tm_run, one launch: thread i packs element i of the caller's
+// states into the padded state y (zeros in the padding); threads i < B also
+// reset the control of state i, i < 3B copy the applied fields (zero when
+// none), i < RP_COUNT store the run parameters the step kernels read.
+__global__ void k_begin_run(const float* __restrict__ m, int64_t n, int64_t np, int64_t B,
+                            float* __restrict__ y, const float* __restrict__ Ha_in, float* __restrict__ Ha,
+                            RunParams rp, double* __restrict__ prm, const double* __restrict__ t_in,
+                            const double* __restrict__ dt_in, double* __restrict__ t,
+                            double* __restrict__ h, double* __restrict__ dt, int64_t* __restrict__ steps,
+                            int64_t* __restrict__ rejected, int32_t* __restrict__ flags,
+                            int32_t* __restrict__ acc) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < B * np * 3) {
+        const int64_t s = i / (3 * np), r = i % (3 * np);
+        y[i] = r < 3 * n ? m[s * 3 * n + r] : 0.0f;
+    }
+    if (i < RP_COUNT) prm[i] = rp.v[i];
+    if (i < 3 * B) Ha[i] = Ha_in ? Ha_in[i] : 0.0f;
+    if (i < B) {
+        const double t0 = t_in[i], d0 = dt_in[i], t_end = rp.v[RP_TEND];
+        t[i] = t0;
+        dt[i] = d0;
+        double hh = d0;
+        int32_t f = 0;
+        if (t_end > 0.0 && t0 + hh > t_end) hh = t_end - t0;
+        if (rp.v[RP_MAX_STEPS] <= 0.0 || (t_end > 0.0 && t0 >= t_end)) f = FLAG_DONE;
+        h[i] = f ? 0.0 : hh;
+        flags[i] = f;
+        steps[i] = 0;
+        rejected[i] = 0;
+        acc[i] = 0;
+    }
 }
 
-__global__ void k_unpack(const float* __restrict__ src, int64_t n, int64_t np, int64_t B,
-                         float* __restrict__ dst) {
+// Epilogue of tm_run, one launch: thread i unpacks element i of the final
+// states into the caller's array; threads i < B also hand back t, dt and the
+// accepted steps of state i and gather its counts and flags into stat
+// ([3][B]: accepted, rejected, flags) for one copy to the host.
+__global__ void k_end_run(const float* __restrict__ y, int64_t n, int64_t np, int64_t B, float* __restrict__ m,
+                          const double* __restrict__ t, const double* __restrict__ dt,
+                          const int64_t* __restrict__ steps, const int64_t* __restrict__ rejected,
+                          const int32_t* __restrict__ flags, double* __restrict__ t_out,
+                          double* __restrict__ dt_out, int64_t* __restrict__ steps_out,
+                          int64_t* __restrict__ stat) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= B * n * 3) return;
-    const int64_t s = i / (3 * n), r = i % (3 * n);
-    dst[i] = src[s * 3 * np + r];
+    if (i < B * n * 3) {
+        const int64_t s = i / (3 * n), r = i % (3 * n);
+        m[i] = y[s * 3 * np + r];
+    }
+    if (i < B) {
+        t_out[i] = t[i];
+        dt_out[i] = dt[i];
+        if (steps_out) steps_out[i] = steps[i];
+        stat[i] = steps[i];
+        stat[B + i] = rejected[i];
+        stat[2 * B + i] = flags[i];
+    }
 }
 
 EpiArgs stage_args(Workspace* w, float* kout, const float* const* kprev, int nprev,
@@ -231,25 +266,21 @@ extern "C" tm_status tm_run(tm_problem* pp, tm_integrator integ, int64_t B, floa
         if (w->graphK) (void)hipGraphExecDestroy(w->graphK);
         w->graphK = nullptr;
     }
-    TM_TRY_HIP(hipStreamSynchronize(s));  // pinned parameter buffer is about to be rewritten
-    double* hp = w->host_params;
-    hp[RP_ATOL] = cfg->atol;
-    hp[RP_RTOL] = cfg->rtol;
-    hp[RP_TEND] = cfg->t_end;
-    hp[RP_DTMIN] = cfg->dt_min;
-    hp[RP_DMDT_STOP] = cfg->dmdt_stop;
-    hp[RP_MAX_STEPS] = static_cast<double>(cfg->max_steps);
-    hp[RP_RENORM] = cfg->renorm ? 1.0 : 0.0;
-    TM_TRY_HIP(hipMemcpyAsync(w->params, hp, RP_COUNT * sizeof(double), hipMemcpyHostToDevice, s));
-    st = launch_pack(m, B, p->n, p->np, w->y, s);
-    if (st != TM_OK) return st;
-    if (Ha)
-        TM_TRY_HIP(hipMemcpyAsync(w->Ha, Ha, B * 12, hipMemcpyDeviceToDevice, s));
-    else
-        TM_TRY_HIP(hipMemsetAsync(w->Ha, 0, B * 12, s));
-    k_init_run<<<static_cast<unsigned>((B + 255) / 256), 256, 0, s>>>(
-        B, t, dt, w->params, w->t, w->h, w->dt, w->steps, w->rejected, w->flags, w->acc);
-    TM_TRY_HIP(hipGetLastError());
+    RunParams rp{};
+    rp.v[RP_ATOL] = cfg->atol;
+    rp.v[RP_RTOL] = cfg->rtol;
+    rp.v[RP_TEND] = cfg->t_end;
+    rp.v[RP_DTMIN] = cfg->dt_min;
+    rp.v[RP_DMDT_STOP] = cfg->dmdt_stop;
+    rp.v[RP_MAX_STEPS] = static_cast<double>(cfg->max_steps);
+    rp.v[RP_RENORM] = cfg->renorm ? 1.0 : 0.0;
+    {
+        const int64_t cnt = B * p->np * 3;  // >= 3 B and >= RP_COUNT (np >= 128)
+        k_begin_run<<<static_cast<unsigned>((cnt + 255) / 256), 256, 0, s>>>(
+            m, p->n, p->np, B, w->y, Ha, w->Ha, rp, w->params, t, dt, w->t, w->h, w->dt, w->steps,
+            w->rejected, w->flags, w->acc);
+        TM_TRY_HIP(hipGetLastError());
+    }
     if (integ == TM_DP45) {
         st = dp_first(p, w, B, s);
         if (st != TM_OK) return st;
@@ -291,23 +322,19 @@ extern "C" tm_status tm_run(tm_problem* pp, tm_integrator integ, int64_t B, floa
             if (all) break;
         }
     }
-    // results back to the caller's buffers
-    k_unpack<<<static_cast<unsigned>((B * p->n * 3 + 255) / 256), 256, 0, s>>>(w->y, p->n, p->np, B, m);
+    // results back to the caller's buffers, counts and flags to the host
+    k_end_run<<<static_cast<unsigned>((B * p->n * 3 + 255) / 256), 256, 0, s>>>(
+        w->y, p->n, p->np, B, m, w->t, w->dt, w->steps, w->rejected, w->flags, t, dt, steps_out, w->stat);
     TM_TRY_HIP(hipGetLastError());
-    TM_TRY_HIP(hipMemcpyAsync(t, w->t, B * 8, hipMemcpyDeviceToDevice, s));
-    TM_TRY_HIP(hipMemcpyAsync(dt, w->dt, B * 8, hipMemcpyDeviceToDevice, s));
-    if (steps_out) TM_TRY_HIP(hipMemcpyAsync(steps_out, w->steps, B * 8, hipMemcpyDeviceToDevice, s));
-    TM_TRY_HIP(hipMemcpyAsync(w->host_flags, w->flags, B * 4, hipMemcpyDeviceToHost, s));
-    TM_TRY_HIP(hipMemcpyAsync(w->host_steps, w->steps, B * 8, hipMemcpyDeviceToHost, s));
-    TM_TRY_HIP(hipMemcpyAsync(w->host_steps + B, w->rejected, B * 8, hipMemcpyDeviceToHost, s));
+    TM_TRY_HIP(hipMemcpyAsync(w->host_stat, w->stat, B * 24, hipMemcpyDeviceToHost, s));
     TM_TRY_HIP(hipStreamSynchronize(s));
     int64_t amin = INT64_MAX, amax = 0, rej = 0;
     int32_t done = 0, failed = 0, nonfinite = 0;
     for (int64_t i = 0; i < B; ++i) {
-        amin = std::min(amin, w->host_steps[i]);
-        amax = std::max(amax, w->host_steps[i]);
-        rej += w->host_steps[B + i];
-        const int32_t f = w->host_flags[i];
+        amin = std::min(amin, w->host_stat[i]);
+        amax = std::max(amax, w->host_stat[i]);
+        rej += w->host_stat[B + i];
+        const int32_t f = static_cast<int32_t>(w->host_stat[2 * B + i]);
         if (f & FLAG_DONE) ++done;
         if (f & (FLAG_NONFINITE | FLAG_STEP)) ++failed;
         if (f & FLAG_NONFINITE) ++nonfinite;
@@ -335,6 +362,63 @@ extern "C" tm_status tm_run(tm_problem* pp, tm_integrator integ, int64_t B, floa
                   static_cast<long long>(B - done), static_cast<long long>(attempts));
         return TM_ESTEP;
     }
+    return TM_OK;
+}
+
+namespace tmag {
+
+OpTimer*& op_timer() {
+    static thread_local OpTimer* t = nullptr;
+    return t;
+}
+
+}  // namespace tmag
+
+extern "C" tm_status tm_profile_run(tm_problem* pp, tm_integrator integ, int64_t B, float* m, const float* Ha,
+                                    double* t, double* dt, const tm_run_cfg* cfg, double* op_ms,
+                                    int64_t* op_launches, hipStream_t s) {
+    Problem* p = reinterpret_cast<Problem*>(pp);
+    TM_REQUIRE(p && cfg && op_ms && op_launches, TM_EINVAL, "tm_profile_run: null argument");
+    TM_REQUIRE(cfg->max_attempts >= 1 && cfg->max_attempts <= 100000, TM_EINVAL,
+               "tm_profile_run: max_attempts must be in [1, 100000]");
+    TM_REQUIRE(op_timer() == nullptr, TM_EBUSY, "tm_profile_run: already timing on this thread");
+    TM_TRY_HIP(hipSetDevice(p->ctx->device));
+    // operator passes: the first evaluation and six per attempt (DP45), four per step (RK4)
+    const int64_t launches = integ == TM_DP45 ? 1 + 6 * cfg->max_attempts : 4 * cfg->max_attempts;
+    OpTimer timer;
+    timer.ev.assign(2 * launches, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto& ev : timer.ev)
+        if (e == hipSuccess) e = hipEventCreate(&ev);
+    tm_status st = TM_OK;
+    if (e != hipSuccess) {
+        set_error("tm_profile_run: event creation failed: %s", hipGetErrorString(e));
+        st = TM_EDEVICE;
+    }
+    if (st == TM_OK) {
+        tm_run_cfg c = *cfg;
+        c.use_graph = 0;  // direct launches: every operator pass gets its own event pair
+        tm_run_stats rs{};
+        op_timer() = &timer;
+        st = tm_run(pp, integ, B, m, Ha, t, dt, nullptr, &c, &rs, s);  // returns after a stream sync
+        op_timer() = nullptr;
+    }
+    double sum = 0.0;
+    if (st == TM_OK) {
+        for (int64_t i = 0; i < timer.used && st == TM_OK; ++i) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, timer.ev[2 * i], timer.ev[2 * i + 1]) != hipSuccess) {
+                set_error("tm_profile_run: no kernel timestamps for launch %lld", static_cast<long long>(i));
+                st = TM_EDEVICE;
+            }
+            sum += ms;
+        }
+    }
+    for (auto& ev : timer.ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (st != TM_OK) return st;
+    *op_ms = sum;
+    *op_launches = timer.used;
     return TM_OK;
 }
 

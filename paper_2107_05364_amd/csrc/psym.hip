@@ -153,9 +153,11 @@ inline void launch_tiles_np(dim3 grid, hipStream_t st, bool nt_loads, const DevP
                             const int32_t* pairs, int64_t nt, const float* Ms, const float* X, int64_t sx,
                             const double* h, const float* Ha, float* part) {
     if (nt_loads)
-        k_psym_tiles<STEPPING, LOCALF, true, NP><<<grid, kTileThreads, 0, st>>>(P, tiles, pairs, nt, Ms, X, sx, h, Ha, part);
+        launch_op(k_psym_tiles<STEPPING, LOCALF, true, NP>, grid, dim3(kTileThreads), st, P, tiles, pairs, nt, Ms, X,
+                  sx, h, Ha, part);
     else
-        k_psym_tiles<STEPPING, LOCALF, false, NP><<<grid, kTileThreads, 0, st>>>(P, tiles, pairs, nt, Ms, X, sx, h, Ha, part);
+        launch_op(k_psym_tiles<STEPPING, LOCALF, false, NP>, grid, dim3(kTileThreads), st, P, tiles, pairs, nt, Ms,
+                  X, sx, h, Ha, part);
 }
 
 template <bool STEPPING, bool LOCALF>

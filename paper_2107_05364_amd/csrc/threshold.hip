@@ -281,11 +281,11 @@ void launch_bsr_t(const DevProblem& P, const Tensor* T, const float* Ms, bool un
                   const float* X, int64_t sx, const EpiArgs& e, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(T->n), static_cast<unsigned>(B));
     if (uni)
-        k_field_bsr<MODE, true><<<grid, 256, 0, s>>>(P, T->row_ptr, T->col, static_cast<const float*>(T->data),
-                                                     T->nnzb, Ms, ms_uni, X, sx, e);
+        launch_op(k_field_bsr<MODE, true>, grid, dim3(256), s, P, T->row_ptr, T->col,
+                  static_cast<const float*>(T->data), T->nnzb, Ms, ms_uni, X, sx, e);
     else
-        k_field_bsr<MODE, false><<<grid, 256, 0, s>>>(P, T->row_ptr, T->col, static_cast<const float*>(T->data),
-                                                      T->nnzb, Ms, ms_uni, X, sx, e);
+        launch_op(k_field_bsr<MODE, false>, grid, dim3(256), s, P, T->row_ptr, T->col,
+                  static_cast<const float*>(T->data), T->nnzb, Ms, ms_uni, X, sx, e);
 }
 
 }  // namespace

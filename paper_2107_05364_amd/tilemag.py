@@ -36,7 +36,7 @@ EXPORTS = [
     "tm_tensor_get", "tm_tensor_rows", "tm_tensor_bytes", "tm_tensor_release",
     "tm_problem_create", "tm_problem_destroy", "tm_demag", "tm_heff", "tm_dmdt", "tm_energy",
     "tm_diagnostics",
-    "tm_run", "tm_profile_field", "tm_profile_field_mode", "tm_num_shapes", "tm_shape_info",
+    "tm_run", "tm_profile_run", "tm_profile_field", "tm_profile_field_mode", "tm_num_shapes", "tm_shape_info",
     "tm_problem_shape", "tm_problem_set_shape",
     "tm_problem_tune", "tm_server_create", "tm_server_submit", "tm_server_poll", "tm_server_destroy",
 ]
@@ -134,6 +134,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "tm_energy": (i32, [vp, i64, vp, vp, vp, vp]),
         "tm_diagnostics": (i32, [vp, i64, vp, vp, vp, vp]),
         "tm_run": (i32, [vp, i32, i64, vp, vp, vp, vp, vp, P(tm_run_cfg), P(tm_run_stats), vp]),
+        "tm_profile_run": (i32, [vp, i32, i64, vp, vp, vp, vp, P(tm_run_cfg), P(d), P(i64), vp]),
         "tm_profile_field": (i32, [vp, i64, i32, vp, P(d), P(i64)]),
         "tm_profile_field_mode": (i32, [vp, i64, i32, i32, vp, P(d), P(i64)]),
         "tm_num_shapes": (i32, []),
@@ -410,6 +411,22 @@ def tm_run(p, n, integ, m, Ha, t, dt, steps_out, cfg: tm_run_cfg, check=True) ->
         _check(r)
     st.status = r
     return st
+
+
+def tm_profile_run(p, n, integ, m, Ha, t, dt, cfg: tm_run_cfg):
+    """(summed operator-pass duration [ms], operator-pass launches) of
+    cfg.max_attempts attempted steps integrated in place."""
+    import torch
+
+    B = _batch(m, n)
+    _shape(Ha, (B, 3), "Ha")
+    _shape(t, (B,), "t")
+    _shape(dt, (B,), "dt")
+    ms, cnt = C.c_double(), C.c_int64()
+    _check(load().tm_profile_run(p, int(integ), B, _dev(m, torch.float32, "m"), _dev(Ha, torch.float32, "Ha"),
+                                 _dev(t, torch.float64, "t"), _dev(dt, torch.float64, "dt"), C.byref(cfg),
+                                 C.byref(ms), C.byref(cnt), _stream()))
+    return ms.value, cnt.value
 
 
 def tm_profile_field(p, B: int, iters: int):

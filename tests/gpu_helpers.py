@@ -37,3 +37,18 @@ def rel_errors(got, want):
     want = np.asarray(want, np.float64)
     d = got - want
     return (np.linalg.norm(d) / np.linalg.norm(want), np.abs(d).max() / np.abs(want).max())
+
+
+# The float32 states and slopes of the GPU path resolve the scaled error
+# estimate of a Dormand-Prince attempt only to about one float32 ulp of a unit
+# vector component (2^-24) over the tolerance scale atol + rtol |y| (about
+# 0.03 for atol = rtol = 1e-6, measured deviations from the FP64 oracle
+# 1e-4 .. 1.5e-3).  The next step h min(5, max(0.2, 0.9 err^-1/5)) is then
+# known to lie between the proposals for err + d and err - d.
+def dp_step_bounds(h, err, atol=1e-6, rtol=1e-6):
+    d = 2.0 ** -24 / (atol + rtol)
+
+    def proposal(e):
+        return h * (5.0 if e <= 0.0 else min(5.0, max(0.2, 0.9 * e ** -0.2)))
+
+    return proposal(err + d) * (1 - 1e-12), proposal(max(err - d, 0.0)) * (1 + 1e-12)

@@ -12,8 +12,10 @@ server can select, against the FP64 oracle:
   steps on the full film, compared with the oracle at the GPU's end time.
 
 Tolerances as in the other parity tests: H_eff relative 2-norm and max-norm
-<= 1e-5; one DP45 attempt |dm| <= 1e-5 and the proposed step within 1e-3
-(the error estimate of a float32 state sits at its noise floor); the
+<= 1e-5; one DP45 attempt |dm| <= 1e-5, the same acceptance, and the
+proposed step within the range that the float32 resolution of the error
+estimate allows (gpu_helpers.dp_step_bounds: +-2^-24 / (atol + rtol) on the
+scaled error, first steps chosen so that it lies between 0.2 and 0.75); the
 200-step trajectory <= 5e-5 (twice the oracle's own discretisation error
 over that interval, 1.0e-5, plus margin for the float32 state).
 """
@@ -22,12 +24,17 @@ import sys
 import numpy as np
 import pytest
 
-from gpu_helpers import build, close, device_state, rel_errors, tilemag
+from gpu_helpers import build, close, device_state, dp_step_bounds, rel_errors, tilemag
 from paper_2107_05364_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
 NUM_SHAPES = 20  # compiled launch shapes of the six-plane stage kernel
+# First steps: their scaled error estimates lie between 0.2 and 0.75 (all
+# accepted by a margin well above the float32 resolution of the estimate), so
+# the proposed next step is a sharp check of the step control.
+DT_REFINED = 5e-14
+DT_PSYM = {"psym6": 1.2e-13, "psym4": 1.5e-13}
 
 
 def _say(msg):
@@ -68,8 +75,8 @@ def refined(orc):
     for k in range(3):
         y = m[k].astype(np.float64).copy()
         k1 = P.rhs(y, Ha[k].astype(np.float64))
-        ok, dtn, tn, err, _ = P.dp45_attempt(y, k1, Ha[k].astype(np.float64), 2e-14, 0.0)
-        steps.append((ok, dtn, tn, y))
+        ok, dtn, tn, err, _ = P.dp45_attempt(y, k1, Ha[k].astype(np.float64), DT_REFINED, 0.0)
+        steps.append((ok, err, tn, y))
     return dict(c=c, s=s, Ms=Ms, Ku=Ku, easy=easy, m=m, Ha=Ha, H=H, steps=steps)
 
 
@@ -92,14 +99,15 @@ def test_every_launch_shape_matches_oracle(tmg, ctx, refined, shape):
         e2, emax = rel_errors(H[k], R["H"][k])
         assert e2 <= 1e-5 and emax <= 1e-5, (shape, k, e2, emax)
     md = device_state(R["m"])
-    t, dt, steps, st = p.run(md, Ha, tmg.TM_DP45, dt=2e-14, max_steps=1, max_attempts=1)
+    t, dt, steps, st = p.run(md, Ha, tmg.TM_DP45, dt=DT_REFINED, max_steps=1, max_attempts=1)
     got = md.cpu().numpy()
     for k in range(3):
-        ok, dtn, tn, y = R["steps"][k]
+        ok, err, tn, y = R["steps"][k]
         assert bool(int(steps.cpu()[k]) == 1) == ok, (shape, k)
         assert float(t.cpu()[k]) == tn
         assert np.abs(got[k] - y).max() <= 1e-5, (shape, k)
-        assert abs(float(dt.cpu()[k]) / dtn - 1) < 1e-3, (shape, k)
+        lo, hi = dp_step_bounds(DT_REFINED, err)
+        assert lo <= float(dt.cpu()[k]) <= hi, (shape, k, float(dt.cpu()[k]), lo, hi)
     close(g, T, p)
 
 
@@ -138,16 +146,18 @@ def test_pair_symmetric_per_tile_ms(tmg, ctx, orc, layout):
     assert D[2, 8] == 1.0
     # one Dormand-Prince attempt of the two finite states
     md = device_state(m[:2])
-    t, dt, steps, st = p.run(md, Had[:2].contiguous(), tmg.TM_DP45, dt=2e-14, max_steps=1, max_attempts=1)
+    h0 = DT_PSYM[layout]
+    t, dt, steps, st = p.run(md, Had[:2].contiguous(), tmg.TM_DP45, dt=h0, max_steps=1, max_attempts=1)
     got = md.cpu().numpy()
     for k in range(2):
         y = m[k].astype(np.float64).copy()
         k1 = P.rhs(y, Ha[k].astype(np.float64))
-        ok, dtn, tn, err, _ = P.dp45_attempt(y, k1, Ha[k].astype(np.float64), 2e-14, 0.0)
+        ok, dtn, tn, err, _ = P.dp45_attempt(y, k1, Ha[k].astype(np.float64), h0, 0.0)
         assert ok and int(steps.cpu()[k]) == 1
         assert float(t.cpu()[k]) == tn
         assert np.abs(got[k] - y).max() <= 1e-5, k
-        assert abs(float(dt.cpu()[k]) / dtn - 1) < 1e-3
+        lo, hi = dp_step_bounds(h0, err)
+        assert lo <= float(dt.cpu()[k]) <= hi, (k, float(dt.cpu()[k]), lo, hi)
     close(g, T, p)
 
 
