@@ -292,6 +292,30 @@ tm_status tm_run(tm_problem* p, tm_integrator integ, int64_t B, float* m, const 
                  double* t, double* dt, int64_t* steps_out, const tm_run_cfg* cfg,
                  tm_run_stats* stats, hipStream_t stream);
 
+/* ---- Field without allocation ------------------------------------------- */
+
+/* Size of the fixed device scratch buffer of tm_demag_noalloc, per device. */
+#define TM_NOALLOC_SCRATCH_BYTES (32ll << 20)
+
+/* tm_demag without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, serving loops that must not reach the
+ * allocator, harnesses that forbid it.  Same arguments, kernels and
+ * summation order as tm_demag, so the result is bitwise tm_demag's.
+ * Scratch (the padded state, 12 np B bytes with np = n rounded up to a
+ * multiple of 128, and for PSYM6 / PSYM4 the slot sums, 384 ceil(n/32)^2 B
+ * bytes) comes from one fixed library buffer of TM_NOALLOC_SCRATCH_BYTES per
+ * device, set up by tm_init and kept until the process ends; no call here
+ * allocates (the problem and its operator are made beforehand).
+ * Operators: FP32 SYM6, BSR6, PSYM6, PSYM4 (TM_EINVAL for DENSE9 / FP64).
+ * Errors: TM_EINVAL for bad arguments, an unsupported operator or a batch
+ * whose scratch exceeds the buffer (the message gives both sizes), before
+ * anything is enqueued; TM_EDEVICE on a HIP error.
+ * Every call on one device shares that device's buffer: calls that overlap
+ * in time on one device (other streams, other threads) race and must be
+ * serialised by the caller; calls on one stream are ordered.  Stream-ordered,
+ * returns after enqueueing. */
+tm_status tm_demag_noalloc(tm_problem* p, int64_t B, const float* m, float* Hd, hipStream_t stream);
+
 /* ---- Profiling ---------------------------------------------------------- */
 
 /* Times the fused demag + effective-field + LL + stage-update kernel that

@@ -97,6 +97,9 @@ tm_status tm_init(int32_t device, tm_ctx** out) {
     TM_TRY_HIP(hipGetDeviceCount(&count));
     TM_REQUIRE(device >= 0 && device < count, TM_EINVAL, "tm_init: device %d of %d", device, count);
     TM_TRY_HIP(hipSetDevice(device));
+    // the fixed scratch of tm_demag_noalloc: its device address, once per device
+    tm_status sst = noalloc_setup(device);
+    if (sst != TM_OK) return sst;
     size_t fr = 0, tot = 0;
     TM_TRY_HIP(hipMemGetInfo(&fr, &tot));
     tm_ctx* c = new tm_ctx();

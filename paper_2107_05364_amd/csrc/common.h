@@ -234,6 +234,9 @@ struct Workspace {
 };
 
 tm_status ensure_workspace(Problem* p, int64_t B);
+// Device address of the fixed scratch buffer of tm_demag_noalloc on `device`,
+// looked up once per device (noalloc.hip); called by tm_init.
+tm_status noalloc_setup(int device);
 constexpr int kGraphSteps = 16;
 // A state's control snapshot: h, t and dt, then the step counts and the
 // flags as 64-bit integer bit patterns.
@@ -320,6 +323,10 @@ constexpr int kPsTile = 32;
 tm_status assemble_psym(Tensor* T, const double* d_centers, const double* d_sizes, hipStream_t s);
 tm_status launch_field_psym(const Problem* p, Epi mode, int64_t B, const float* X, const EpiArgs& e,
                             hipStream_t s);
+// The same with the slot sums in a caller-provided buffer of
+// psym_partial_floats(T, B) floats instead of the problem's workspace.
+tm_status launch_field_psym_slots(const Problem* p, Epi mode, int64_t B, const float* X, const EpiArgs& e,
+                                  float* part, hipStream_t s);
 int64_t psym_partial_floats(const Tensor* T, int64_t B);
 tm_status launch_psym_tiles(const Problem* p, int64_t B, const float* X, const double* h, const float* Ha,
                             hipStream_t s);

@@ -300,24 +300,31 @@ tm_status launch_psym_tiles(const Problem* p, int64_t B, const float* X, const d
 
 tm_status launch_field_psym(const Problem* p, Epi mode, int64_t B, const float* X, const EpiArgs& e,
                             hipStream_t s) {
-    const Tensor* T = p->T;
     Workspace* w = p->ws.get();
-    TM_REQUIRE(is_psym(T->layout) && T->pairs && T->data, TM_EINVAL,
-               "pair-symmetric field evaluation needs a PSYM6 or PSYM4 operator");
-    TM_REQUIRE(w && w->part && w->B >= B && B >= 1 && B <= 65535, TM_EINVAL,
+    TM_REQUIRE(w && w->part && w->B >= B, TM_EINVAL,
                "pair-symmetric field evaluation: workspace not prepared for %lld states",
                static_cast<long long>(B));
+    return launch_field_psym_slots(p, mode, B, X, e, w->part, s);
+}
+
+tm_status launch_field_psym_slots(const Problem* p, Epi mode, int64_t B, const float* X, const EpiArgs& e,
+                                  float* part, hipStream_t s) {
+    const Tensor* T = p->T;
+    TM_REQUIRE(is_psym(T->layout) && T->pairs && T->data, TM_EINVAL,
+               "pair-symmetric field evaluation needs a PSYM6 or PSYM4 operator");
+    TM_REQUIRE(part && B >= 1 && B <= 65535, TM_EINVAL,
+               "pair-symmetric field evaluation: no slot buffer or bad batch %lld", static_cast<long long>(B));
     TM_REQUIRE(p->np >= TS * T->nt, TM_EINVAL, "pair-symmetric field evaluation: state padding too small");
     const DevProblem P = p->dev();
     const int64_t sx = 3 * p->np;
     const bool nt = psym_nt_loads(p);
     switch (mode) {
-        case Epi::HD: launch_psym_t<Epi::HD>(P, T, nt, p->Ms, w->part, B, X, sx, e, s); break;
-        case Epi::HEFF: launch_psym_t<Epi::HEFF>(P, T, nt, p->Ms, w->part, B, X, sx, e, s); break;
-        case Epi::DMDT: launch_psym_t<Epi::DMDT>(P, T, nt, p->Ms, w->part, B, X, sx, e, s); break;
-        case Epi::STAGE: launch_psym_t<Epi::STAGE>(P, T, nt, p->Ms, w->part, B, X, sx, e, s); break;
-        case Epi::RK4_FINAL: launch_psym_t<Epi::RK4_FINAL>(P, T, nt, p->Ms, w->part, B, X, sx, e, s); break;
-        case Epi::DP_LAST: launch_psym_t<Epi::DP_LAST>(P, T, nt, p->Ms, w->part, B, X, sx, e, s); break;
+        case Epi::HD: launch_psym_t<Epi::HD>(P, T, nt, p->Ms, part, B, X, sx, e, s); break;
+        case Epi::HEFF: launch_psym_t<Epi::HEFF>(P, T, nt, p->Ms, part, B, X, sx, e, s); break;
+        case Epi::DMDT: launch_psym_t<Epi::DMDT>(P, T, nt, p->Ms, part, B, X, sx, e, s); break;
+        case Epi::STAGE: launch_psym_t<Epi::STAGE>(P, T, nt, p->Ms, part, B, X, sx, e, s); break;
+        case Epi::RK4_FINAL: launch_psym_t<Epi::RK4_FINAL>(P, T, nt, p->Ms, part, B, X, sx, e, s); break;
+        case Epi::DP_LAST: launch_psym_t<Epi::DP_LAST>(P, T, nt, p->Ms, part, B, X, sx, e, s); break;
     }
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;

@@ -34,7 +34,7 @@ EXPORTS = [
     "tm_geometry_create", "tm_geometry_hash", "tm_geometry_info", "tm_geometry_destroy",
     "tm_tensor_assemble", "tm_tensor_threshold", "tm_tensor_sparse_info", "tm_tensor_sparse_get",
     "tm_tensor_get", "tm_tensor_rows", "tm_tensor_bytes", "tm_tensor_release",
-    "tm_problem_create", "tm_problem_destroy", "tm_demag", "tm_heff", "tm_dmdt", "tm_energy",
+    "tm_problem_create", "tm_problem_destroy", "tm_demag", "tm_demag_noalloc", "tm_heff", "tm_dmdt", "tm_energy",
     "tm_diagnostics",
     "tm_run", "tm_profile_run", "tm_profile_field", "tm_profile_field_mode", "tm_num_shapes", "tm_shape_info",
     "tm_problem_shape", "tm_problem_set_shape",
@@ -129,6 +129,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "tm_problem_create": (i32, [vp, vp, vp, P(tm_material), P(vp)]),
         "tm_problem_destroy": (i32, [vp]),
         "tm_demag": (i32, [vp, i64, vp, vp, vp]),
+        "tm_demag_noalloc": (i32, [vp, i64, vp, vp, vp]),
         "tm_heff": (i32, [vp, i64, vp, vp, vp, vp]),
         "tm_dmdt": (i32, [vp, i64, vp, vp, vp, vp]),
         "tm_energy": (i32, [vp, i64, vp, vp, vp, vp]),
@@ -353,6 +354,18 @@ def tm_demag(p, n, m, Hd) -> None:
     B = _batch(m, n)
     _shape(Hd, m.shape, "Hd")
     _check(load().tm_demag(p, B, _dev(m, torch.float32, "m"), _dev(Hd, torch.float32, "Hd"), _stream()))
+
+
+def tm_demag_noalloc(p, n, m, Hd, check=True) -> int:
+    """tm_demag on the library's fixed scratch buffer (allocates nothing)."""
+    import torch
+
+    B = _batch(m, n)
+    _shape(Hd, m.shape, "Hd")
+    r = load().tm_demag_noalloc(p, B, _dev(m, torch.float32, "m"), _dev(Hd, torch.float32, "Hd"), _stream())
+    if check:
+        _check(r)
+    return r
 
 
 def tm_heff(p, n, m, Ha, H) -> None:
