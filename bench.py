@@ -50,10 +50,14 @@ def parse():
     ap.add_argument("--no-threshold", action="store_true")
     ap.add_argument("--no-sp3", action="store_true")
     ap.add_argument("--no-cache-free", action="store_true")
+    ap.add_argument("--no-sp4-dynamics", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="counter runs: one 1 GiB device copy (calibration) and the stage kernel "
                          "of the film workload only")
-    ap.add_argument("--serving-count", type=int, default=24)
+    ap.add_argument("--serving-count", type=int, default=40,
+                    help="requests of the serving stream (the full stream has 200)")
+    ap.add_argument("--serving-nmax", type=int, default=20000,
+                    help="largest tile count of the serving stream (log-uniform from 500)")
     ap.add_argument("--layout", choices=["psym4", "psym6", "sym6"], default="psym4",
                     help="operator layout of the headline run: pair-symmetric with four planes "
                          "(the film is one layer of identical tiles), pair-symmetric with six "
@@ -306,8 +310,10 @@ def large_section(tmg, W, torch, attempts=20, profile_iters=10, with_oracle=True
 
 def cube_section(tmg, W, torch, reps=5, with_oracle=True):
     """The 8 x 8 x 8 grid of 5 nm cubes (N = 512), RK4 at dt = 1e-13 s for
-    200 steps with the float32 SYM6 operator (3 MB, cache-resident): a
-    launch- and latency-bound case."""
+    200 steps with the float32 SYM6 operator (6 MB, cache-resident): a
+    launch- and latency-bound case, run as captured graphs of four stage
+    launches per step and as one persistent cooperative launch for the
+    whole run (operator rows resident in LDS, a grid barrier per stage)."""
     wl = W.cube_grid()
     nsteps = wl.extra["steps"]
     ctx = tmg.Context(0)
@@ -315,16 +321,22 @@ def cube_section(tmg, W, torch, reps=5, with_oracle=True):
     T = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, tmg.TM_LAYOUT_SYM6)
     p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
     m = torch.as_tensor(wl.m0.astype(np.float32), device="cuda")
-    p.run(m.clone(), None, tmg.TM_RK4, dt=wl.extra["dt"], max_steps=nsteps)
-    torch.cuda.synchronize()
-    best = 1e30
-    for _ in range(reps):
-        mm = m.clone()
+    def best_of(persistent):
+        p.run(m.clone(), None, tmg.TM_RK4, dt=wl.extra["dt"], max_steps=nsteps, persistent=persistent)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        p.run(mm, None, tmg.TM_RK4, dt=wl.extra["dt"], max_steps=nsteps)
-        torch.cuda.synchronize()
-        best = min(best, time.perf_counter() - t0)
+        best = 1e30
+        for _ in range(reps):
+            mm = m.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p.run(mm, None, tmg.TM_RK4, dt=wl.extra["dt"], max_steps=nsteps, persistent=persistent)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    best_graph = best_of(False)
+    best_pers = best_of(True)
+    best = min(best_graph, best_pers)
     ms, nb = tmg.tm_profile_field(p.handle, 1, 50)
     p.close()
     T.close()
@@ -332,6 +344,8 @@ def cube_section(tmg, W, torch, reps=5, with_oracle=True):
     ctx.close()
     out = {"workload": "8x8x8 cubes of 5 nm (N=512), alpha=0.5, RK4 dt=1e-13 s x %d steps, fp32 SYM6" % nsteps,
            "steps_per_s": round(nsteps / best, 1), "us_per_step": round(best / nsteps * 1e6, 2),
+           "steps_per_s_graph": round(nsteps / best_graph, 1),
+           "steps_per_s_persistent": round(nsteps / best_pers, 1),
            "stage_kernel_us": round(ms * 1e3, 2)}
     if with_oracle:
         import oracle
@@ -402,6 +416,49 @@ def sp4_sweep_section(tmg, W, torch, attempts=300):
         geom.close()
         ctx.close()
     return {"workload": "SP4 film [20n,5n,1] tiles, n=1..9, one state, DP45, fp32 SYM6 (and PSYM6, PSYM4)", "sizes": rows}
+
+
+def sp4_dynamics_section(tmg, W, torch, ns=range(1, 10), layouts=("psym4", "psym6", "sym6")):
+    """The paper's standard-problem-4 timing experiment (Sec. 4.3, Fig. 5b):
+    for each resolution [20n, 5n, 1] the s-state is prepared on the device
+    (field staircase along [1, 1, 1], pure-damping relaxation; timed apart,
+    as the paper leaves it out), then the dynamic part -- field 1 and field 2
+    switched on at t = 0 with the paper's LL parameters, adaptive DP45 to
+    1 ns -- is timed per operator layout."""
+    from paper_2107_05364_amd import sp4
+
+    rows = []
+    t_all = time.perf_counter()
+    for nn in ns:
+        wl = W.sp4_film(nn)
+        ctx = tmg.Context(0)
+        geom = tmg.Geometry(ctx, wl.centers, wl.sizes)
+        tensors = {name: tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, LAYOUT_CODE[name]) for name in layouts}
+        t0 = time.perf_counter()
+        m_s, levels = sp4.prepare_sstate(ctx, geom, tensors[layouts[0]], wl)
+        torch.cuda.synchronize()
+        row = {"n": nn, "tiles": wl.n,
+               "sstate": {"seconds": round(time.perf_counter() - t0, 3), "layout": layouts[0],
+                          "attempts": sum(lv["attempts"] for lv in levels),
+                          "mean_m": [round(x, 6) for x in levels[-1]["mean_m"]]}}
+        for name in layouts:
+            rec = {}
+            for field in (1, 2):
+                m, st, wall, mean = sp4.dynamics(ctx, geom, tensors[name], wl, m_s, field, tune_iters=5)
+                rec["field%d" % field] = {"seconds": round(wall, 4), "attempts": int(st.attempts),
+                                          "accepted": int(st.accepted_max), "rejected": int(st.rejected),
+                                          "mean_m_1ns": [round(float(x), 6) for x in mean]}
+            rec["seconds_both_fields"] = round(rec["field1"]["seconds"] + rec["field2"]["seconds"], 4)
+            row[name] = rec
+        rows.append(row)
+        for T in tensors.values():
+            T.close()
+        geom.close()
+        ctx.close()
+    return {"workload": "SP4 film [20n,5n,1], n=1..9: s-state (staircase 1000..0 mT along [1,1,1], pure "
+                        "damping to max|dm/dt| < 1e-4 gamma0 Ms), then field 1 / field 2 for 1 ns with "
+                        "c1 = 2.21e5, c2 = 4.42e3 (DP45, atol = rtol = 1e-6), one state, fp32",
+            "sizes": rows, "seconds": round(time.perf_counter() - t_all, 1)}
 
 
 def threshold_section(tmg, W, torch, attempts=300, fracs=(0.2, 0.4, 0.7)):
@@ -581,7 +638,7 @@ def peaks_section(torch, tmg):
     return out
 
 
-def serving_section(tmg, W, torch, count=24, n_max=4000, max_steps=3000, slots=8):
+def serving_section(tmg, W, torch, count=24, n_max=4000, max_steps=3000, slots=8, max_active=0, serial=True):
     """Poisson stream of relaxation requests (bounded sample of the serving
     workload: `count` requests, tile counts log-uniform in [500, n_max]):
     the continuous-batching server against serial FIFO plain-FP32 solves of
@@ -592,7 +649,7 @@ def serving_section(tmg, W, torch, count=24, n_max=4000, max_steps=3000, slots=8
     reqs = W.serving_stream(count=count, n_max=n_max)
     kw = dict(Ms=Ms, A_exch=A, alpha=alpha, dmdt_stop=stop, max_steps=max_steps, dt0=1e-14)
     ctx = tmg.Context(0)
-    srv = tmg.Server(ctx, max_slots=slots, max_groups=16, steps_per_round=64)
+    srv = tmg.Server(ctx, max_slots=slots, max_groups=16, steps_per_round=64, max_active=max_active)
     t0 = time.perf_counter()
     tks = []
     for r in reqs:
@@ -606,6 +663,16 @@ def serving_section(tmg, W, torch, count=24, n_max=4000, max_steps=3000, slots=8
     lat = np.array([r.latency_ms for r in res])
     conv = sum(1 for r in res if r.status == 0)
     hits = sum(1 for r in res if r.cache_hit)
+    out = {"workload": "Poisson stream 20 req/s, %d requests, N log-uniform 500-%d on 5x5x3 nm "
+                       "grids, 30%% repeated geometries, relax to max|dm/dt| < 1e-4 gamma0 Ms "
+                       "(cap %d steps)" % (count, n_max, max_steps),
+           "server": {"throughput_req_s": round(count / span, 3),
+                      "p50_ms": round(float(np.percentile(lat, 50)), 1),
+                      "p99_ms": round(float(np.percentile(lat, 99)), 1),
+                      "converged": conv, "cache_hits": hits, "slots": slots, "max_active": max_active}}
+    if not serial:
+        ctx.close()
+        return out
     # serial FIFO baseline on the same device (operator cache kept, as a
     # plain solver would keep its operator between repeated geometries)
     svc = []
@@ -640,16 +707,10 @@ def serving_section(tmg, W, torch, count=24, n_max=4000, max_steps=3000, slots=8
         g.close()
     ctx.close()
     lat_s = np.array(lat_s)
-    return {"workload": "Poisson stream 20 req/s, %d requests, N log-uniform 500-%d on 5x5x3 nm "
-                        "grids, 30%% repeated geometries, relax to max|dm/dt| < 1e-4 gamma0 Ms "
-                        "(cap %d steps)" % (count, n_max, max_steps),
-            "server": {"throughput_req_s": round(count / span, 3),
-                       "p50_ms": round(float(np.percentile(lat, 50)), 1),
-                       "p99_ms": round(float(np.percentile(lat, 99)), 1),
-                       "converged": conv, "cache_hits": hits, "slots": slots},
-            "serial_fp32": {"throughput_req_s": round(count / end, 3),
-                            "p50_ms": round(float(np.percentile(lat_s, 50)), 1),
-                            "p99_ms": round(float(np.percentile(lat_s, 99)), 1)}}
+    out["serial_fp32"] = {"throughput_req_s": round(count / end, 3),
+                          "p50_ms": round(float(np.percentile(lat_s, 50)), 1),
+                          "p99_ms": round(float(np.percentile(lat_s, 99)), 1)}
+    return out
 
 
 def main():
@@ -791,12 +852,14 @@ def main():
         rec["cube"] = cube_section(tmg, W, torch, with_oracle=not args.no_cpu_baseline)
     if not args.no_sweep:
         rec["sp4_sweep"] = sp4_sweep_section(tmg, W, torch)
+    if not args.no_sp4_dynamics:
+        rec["sp4_dynamics"] = sp4_dynamics_section(tmg, W, torch)
     if not args.no_threshold:
         rec["threshold"] = threshold_section(tmg, W, torch)
     if not args.no_sp3:
         rec["sp3"] = sp3_section(tmg, W, torch)
     if not args.no_serving:
-        rec["serving"] = serving_section(tmg, W, torch, count=args.serving_count)
+        rec["serving"] = serving_section(tmg, W, torch, count=args.serving_count, n_max=args.serving_nmax)
     if not args.no_peaks:
         rec["achievable_peaks"] = peaks_section(torch, tmg)
     if not args.no_cpu_baseline:

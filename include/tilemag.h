@@ -163,7 +163,10 @@ tm_status tm_tensor_assemble(tm_ctx* ctx, const tm_geom* g, tm_prec store, tm_la
  * which are kept whole.  frac = 0 removes nothing.
  * The result is a new operator of layout TM_LAYOUT_BSR6, precision FP32: for
  * each target tile, in ascending source order, the source tiles whose block
- * keeps at least one entry, with its 6 components (removed ones are 0).  It
+ * keeps at least one entry, with its 6 components (removed ones are 0); on a
+ * single layer of tiles (one z for every centre), where xz = yz = 0 in every
+ * block, only the planes xx, xy, yy, zz are stored (20 instead of 28 bytes
+ * per block; read-back returns xz = yz = 0).  It
  * is usable wherever an FP32 SYM6 operator is (tm_problem_create, one state
  * or many; not the DENSE9 batched product), is cached under (geometry, frac)
  * and is released with tm_tensor_release.  Blocking.
@@ -266,6 +269,10 @@ typedef struct {
     int32_t renorm;        /* 1: |m_a| := 1 after each accepted step */
     int32_t use_graph;     /* 1: capture one attempted step in a hipGraph and replay it */
     int32_t poll_every;    /* attempts between host checks of the done flags (0: 64) */
+    int32_t persistent;    /* 1: RK4 of one state with an FP32 SYM6 operator of at most 1024
+                              tiles as one cooperative launch for the whole run (each
+                              workgroup keeps its operator rows in LDS, a grid barrier
+                              ends each stage); TM_EINVAL for any other case */
 } tm_run_cfg;
 
 typedef struct {
@@ -342,7 +349,9 @@ tm_status tm_profile_field_mode(tm_problem* p, int64_t B, int32_t mode, int32_t 
  * launch of the operator kernel -- the pair-symmetric tile pass, the fused
  * stage kernel of SYM6, the sparse kernel of BSR6 or the batched product of
  * DENSE9 -- with its own start and end (hipExtLaunchKernelGGL events on
- * `stream`).  op_ms receives the sum of those durations [ms], op_launches the
+ * `stream`).  The launches are queued behind a hold kernel (2 ms + 1 ms per
+ * attempt, at most 200 ms) so that they run back to back as in a graph
+ * replay.  op_ms receives the sum of those durations [ms], op_launches the
  * number of launches (DP45: 1 + 6 per attempt; RK4: 4 per step).  Blocking.
  * TM_EBUSY if called while another timing runs on the same thread;
  * otherwise the errors of tm_run. */
@@ -369,19 +378,38 @@ tm_status tm_problem_shape(const tm_problem* p, int32_t* shape);
  * for a fixed shape and independent of the batch size. */
 tm_status tm_problem_set_shape(tm_problem* p, int32_t shape);
 
-/* Autotuner: times every shape (iters launches each, B states) and keeps the
- * fastest for p.  Blocking.  chosen / best_ms may be NULL.  For a DENSE9
- * operator in FP32 / BF16X3 / FP16X3 (the batched product) the candidates
- * are the numbers of K splits (2, 3, 4, 5, 6, 8) and chosen is the split
- * count kept; the split count sets the summation order, so results are
- * bitwise reproducible for a fixed count and independent of the batch.
- * For PSYM6 / PSYM4 it times the evaluation with cached (chosen = 0) and
- * with nontemporal (chosen = 1) operator loads in the tile pass and keeps
- * the faster (the results are the same either way).  For the other
- * operators (one kernel shape each) it only times that kernel and reports
- * chosen = -1. */
+/* Autotuner: times every candidate (|iters| launches each, B states) and
+ * keeps the fastest for p.  Blocking.  chosen / best_ms may be NULL.  For the
+ * six-plane stage kernel (SYM6) the candidates are its launch shapes and
+ * chosen is the shape kept.  For a DENSE9 operator in FP32 / BF16X3 / FP16X3
+ * (the batched product) the candidates are the numbers of K splits (2, 3, 4,
+ * 5, 6, 8) and chosen is the split count kept; the split count sets the
+ * summation order, so results are bitwise reproducible for a fixed count and
+ * independent of the batch.  For PSYM6 / PSYM4 it times the evaluation with
+ * cached (chosen = 0) and with nontemporal (chosen = 1) operator loads in the
+ * tile pass and keeps the faster (the results are the same either way).  For
+ * the other operators (one kernel shape each) it only times that kernel and
+ * reports chosen = -1.
+ * Every result is kept in a process-wide table keyed by (device architecture
+ * and compute-unit count, layout, precision, tile count, B).  iters >= 1
+ * reuses the table's result for p's key, if there is one, without timing
+ * (best_ms is then the stored time); iters <= -1 always times (|iters|
+ * launches per candidate) and replaces the entry.  iters = 0: TM_EINVAL. */
 tm_status tm_problem_tune(tm_problem* p, int64_t B, int32_t iters, hipStream_t stream,
                           int32_t* chosen, double* best_ms);
+
+/* The autotuner's table as a JSON file (one entry per line: arch, cus,
+ * layout, prec, n, batch, choice, ms), so that a later process reuses the
+ * tuned choices.  tm_tune_cache_save writes every entry (TM_EINVAL if the
+ * file cannot be written); tm_tune_cache_load merges the entries of a file
+ * written by tm_tune_cache_save (TM_ENOTFOUND if it cannot be read, TM_EINVAL
+ * if it is not such a file); tm_tune_cache_clear empties the table;
+ * tm_tune_cache_size gives its number of entries.  An entry whose choice is
+ * not a candidate for the problem it is looked up for is ignored. */
+tm_status tm_tune_cache_save(const char* path);
+tm_status tm_tune_cache_load(const char* path);
+tm_status tm_tune_cache_clear(void);
+tm_status tm_tune_cache_size(int64_t* entries);
 
 /* ---- Serving: continuous batching of relaxation requests -------------- */
 
@@ -391,6 +419,8 @@ typedef struct {
     int32_t max_groups;      /* geometry groups resident at once, >= 1 */
     int32_t steps_per_round; /* attempted steps per group between scheduler checks */
     tm_prec prec;            /* operator precision (FP32 only at present) */
+    int32_t max_active;      /* groups advanced at once, those with the oldest requests
+                                first (0: every resident group) */
 } tm_server_cfg;
 
 typedef struct {

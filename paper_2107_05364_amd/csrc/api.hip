@@ -69,7 +69,8 @@ Workspace::~Workspace() {
     float* fl[] = {y, ya, yb, y5, k[0], k[1], k[2], k[3], k[4], k[5], k[6], Ha, hd, part};
     for (float* p : fl)
         if (p) (void)hipFree(p);
-    void* vp[] = {xh, xl, t, h, dt, errp, dmxp, snap, steps, rejected, flags, acc, params, esum, diag, stat};
+    void* vp[] = {xh, xl, t, h, dt, errp, dmxp, snap, steps, rejected, flags, acc, params, esum, diag, stat, bar,
+                  bar_fail};
     for (void* p : vp)
         if (p) (void)hipFree(p);
     if (host_params) (void)hipHostFree(host_params);
@@ -600,7 +601,7 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
     const bool psym = is_psym(T->layout);
     if (psym) pbytes = psym_partial_floats(T, bcap) * 4;
     const int64_t dbytes = bcap * (nblk * 6 + 4) * 8;  // diagnostics partials + energies
-    int64_t bytes = 12 * sb + bcap * 12 + bcap * (8 * 7 + 8 * 2 + 4 * 2 + 8 * kSnapStride + 24) + 16 * bcap * n + 64 +
+    int64_t bytes = 12 * sb + bcap * 12 + bcap * (8 * 7 + 8 * 2 + 4 * 2 + 8 * kSnapStride + 24) + 16 * bcap * n + 576 +
                     RP_COUNT * 8 + nblk * bcap * 32 + xbytes + pbytes + dbytes;
     {
         std::lock_guard<std::mutex> lk(p->ctx->mu);
@@ -647,6 +648,8 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->esum), nblk * bcap * 32);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->diag), dbytes);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->stat), bcap * 24);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->bar), 256);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->bar_fail), 256);
     w->esum_blocks = nblk * bcap;
     if (dense && xbytes && e == hipSuccess) {
         const int64_t half = T->prec == TM_PREC_FP32 ? xbytes : xbytes / 2;

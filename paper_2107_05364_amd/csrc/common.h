@@ -128,6 +128,7 @@ struct Tensor {
     // PSYM4 the same with the planes (xx, xy, yy, zz) of a single layer of tiles
     int32_t* pairs = nullptr;
     int64_t npairs = 0, nt = 0;
+    int bsr_planes = 6;      // BSR6: component planes stored (4 for a single layer: xz = yz = 0)
     double frac = -1.0;      // BSR6: removed fraction requested
     double cut = -1.0;       // BSR6: magnitude cut (-1: nothing removed)
     int64_t bytes = 0;
@@ -217,6 +218,8 @@ struct Workspace {
     double* esum = nullptr;   // energy partial sums
     double* diag = nullptr;   // diagnostics: [B][nblk][6] partials, then [B][4] energies
     int64_t* stat = nullptr;  // end of a run: [3][B] accepted steps, rejected attempts, flags
+    unsigned* bar = nullptr;  // persistent RK4: grid-barrier counter
+    int32_t* bar_fail = nullptr;  // persistent RK4: a barrier wait gave up
     int64_t esum_blocks = 0;
     // pinned host mirrors (run parameters, polling)
     double* host_params = nullptr;
@@ -368,6 +371,21 @@ tm_status launch_energy(const Problem* p, int64_t B, const float* X, const float
 // the energies E4 [B][4] in 0..3 (fieldstep.hip).
 tm_status launch_diagnostics(const Problem* p, int64_t B, const float* X, const float* Hd,
                              const float* dmdt, const double* E4, double* D, hipStream_t s);
+
+// Autotuner cache (tunecache.cpp): a process-wide table of tm_problem_tune
+// results keyed by device, layout, precision, tile count and batch.
+struct TuneResult {
+    int choice = -1;
+    double ms = 0.0;
+};
+bool tune_lookup(const Problem* p, int64_t B, TuneResult* out);
+void tune_store(const Problem* p, int64_t B, const TuneResult& r);
+
+// Persistent RK4 (persist.hip): one cooperative launch integrates one state
+// whose FP32 SYM6 operator rows fit in the LDS of the workgroups.
+constexpr int64_t kPersistMaxTiles = 1024;  // padded tiles
+bool persistent_eligible(const Problem* p, int integ, int64_t B);
+tm_status launch_persistent_rk4(const Problem* p, Workspace* w, const tm_run_cfg* cfg, hipStream_t s);
 
 // Integrator pieces shared with the server (integrate.hip).
 tm_status enqueue_attempts(const Problem* p, Workspace* w, int integ, int64_t B, int renorm,

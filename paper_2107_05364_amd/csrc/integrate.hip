@@ -253,6 +253,9 @@ extern "C" tm_status tm_run(tm_problem* pp, tm_integrator integ, int64_t B, floa
                "tm_run: DP45 needs atol > 0 or rtol > 0");
     TM_REQUIRE((reinterpret_cast<uintptr_t>(m) & 15) == 0, TM_EINVAL, "tm_run: m must be 16-byte aligned");
     TM_REQUIRE(B <= (int64_t(1) << 16), TM_EINVAL, "tm_run: batch too large");
+    TM_REQUIRE(!cfg->persistent || persistent_eligible(p, integ, B), TM_EINVAL,
+               "tm_run: persistent mode needs RK4, one state and an FP32 SYM6 operator of at most %lld "
+               "padded tiles", static_cast<long long>(kPersistMaxTiles));
     TM_TRY_HIP(hipSetDevice(p->ctx->device));
     tm_status st = ensure_workspace(p, B);
     if (st != TM_OK) return st;
@@ -281,11 +284,19 @@ extern "C" tm_status tm_run(tm_problem* pp, tm_integrator integ, int64_t B, floa
             w->rejected, w->flags, w->acc);
         TM_TRY_HIP(hipGetLastError());
     }
+    int64_t attempts = 0;
+    const bool persistent = cfg->persistent != 0;
+    if (persistent) {
+        st = launch_persistent_rk4(p, w, cfg, s);
+        if (st != TM_OK) return st;
+        attempts = cfg->max_steps;
+        TM_TRY_HIP(hipMemcpyAsync(w->host_flags, w->bar_fail, 4, hipMemcpyDeviceToHost, s));
+    }
     if (integ == TM_DP45) {
         st = dp_first(p, w, B, s);
         if (st != TM_OK) return st;
     }
-    if (cfg->use_graph && !w->graph1) {
+    if (!persistent && cfg->use_graph && !w->graph1) {
         st = capture(p, w, integ, B, renorm, 1, &w->graph1);
         if (st != TM_OK) return st;
         st = capture(p, w, integ, B, renorm, kGraphSteps, &w->graphK);
@@ -301,8 +312,9 @@ extern "C" tm_status tm_run(tm_problem* pp, tm_integrator integ, int64_t B, floa
         for (int64_t i = 0; i < r; ++i) TM_TRY_HIP(hipGraphLaunch(w->graph1, s));
         return TM_OK;
     };
-    int64_t attempts = 0;
-    if (cfg->max_attempts > 0) {
+    if (persistent) {
+        // the whole run was one launch
+    } else if (cfg->max_attempts > 0) {
         st = run_chunk(cfg->max_attempts);
         if (st != TM_OK) return st;
         attempts = cfg->max_attempts;
@@ -328,6 +340,10 @@ extern "C" tm_status tm_run(tm_problem* pp, tm_integrator integ, int64_t B, floa
     TM_TRY_HIP(hipGetLastError());
     TM_TRY_HIP(hipMemcpyAsync(w->host_stat, w->stat, B * 24, hipMemcpyDeviceToHost, s));
     TM_TRY_HIP(hipStreamSynchronize(s));
+    if (persistent && w->host_flags[0] != 0) {
+        set_error("tm_run: a grid barrier of the persistent RK4 kernel timed out");
+        return TM_EDEVICE;
+    }
     int64_t amin = INT64_MAX, amax = 0, rej = 0;
     int32_t done = 0, failed = 0, nonfinite = 0;
     for (int64_t i = 0; i < B; ++i) {
@@ -372,6 +388,18 @@ OpTimer*& op_timer() {
     return t;
 }
 
+namespace {
+
+// Holds the stream for `ticks` of the constant-rate wall clock (one wave,
+// bounded by construction), so that the host can enqueue a whole timed run
+// behind it and the kernels then follow each other without host gaps, as
+// in a graph replay.
+__global__ void k_hold(int64_t ticks) {
+    const long long t0 = wall_clock64();
+    while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(8);
+}
+
+}  // namespace
 }  // namespace tmag
 
 extern "C" tm_status tm_profile_run(tm_problem* pp, tm_integrator integ, int64_t B, float* m, const float* Ha,
@@ -394,6 +422,21 @@ extern "C" tm_status tm_profile_run(tm_problem* pp, tm_integrator integ, int64_t
     if (e != hipSuccess) {
         set_error("tm_profile_run: event creation failed: %s", hipGetErrorString(e));
         st = TM_EDEVICE;
+    }
+    if (st == TM_OK) {
+        // a head start for the host: 1 ms per attempt of enqueueing (about
+        // 13 launches with events; generous, so that a profiler's slower API
+        // calls still finish first)
+        int rate_khz = 0;
+        if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, p->ctx->device) != hipSuccess ||
+            rate_khz <= 0)
+            rate_khz = 100000;
+        const double hold_us = std::min(200000.0, 2000.0 + 1000.0 * static_cast<double>(cfg->max_attempts));
+        k_hold<<<1, 64, 0, s>>>(static_cast<int64_t>(hold_us * rate_khz / 1000.0));
+        if (hipGetLastError() != hipSuccess) {
+            set_error("tm_profile_run: hold kernel launch failed");
+            st = TM_EDEVICE;
+        }
     }
     if (st == TM_OK) {
         tm_run_cfg c = *cfg;
@@ -551,98 +594,127 @@ extern "C" tm_status tm_problem_set_shape(tm_problem* pp, int32_t shape) {
     return TM_OK;
 }
 
+namespace tmag {
+namespace {
+
+// The candidates tm_problem_tune times for p: the K-split counts of the
+// batched product, cached / nontemporal tile-pass loads of the pair-symmetric
+// layouts, or the launch shapes of the six-plane stage kernel; none for the
+// other operators (one kernel shape each).
+enum class TuneKind { SPLITS, LOADS, SHAPES, NONE };
+
+TuneKind tune_kind(const Problem* p) {
+    if (p->T->layout == TM_LAYOUT_DENSE9 && p->T->prec != TM_PREC_FP64) return TuneKind::SPLITS;
+    if (is_psym(p->T->layout)) return TuneKind::LOADS;
+    if (p->T->layout == TM_LAYOUT_SYM6) return TuneKind::SHAPES;
+    return TuneKind::NONE;
+}
+
+void drop_graphs(Problem* p) {
+    if (!p->ws) return;
+    if (p->ws->graph1) (void)hipGraphExecDestroy(p->ws->graph1);
+    if (p->ws->graphK) (void)hipGraphExecDestroy(p->ws->graphK);
+    p->ws->graph1 = p->ws->graphK = nullptr;
+}
+
+// Applies choice c of kind k to p (captured graphs hold the old kernels and
+// are dropped when it changes); false if c is not a candidate.
+bool apply_choice(Problem* p, TuneKind k, int c) {
+    static const int kCand[] = {2, 3, 4, 5, 6, 8};
+    switch (k) {
+        case TuneKind::SPLITS: {
+            bool ok = false;
+            for (int q : kCand) ok = ok || (q == c && c <= p->T->ld / kGemmKC);
+            if (!ok) return false;
+            if (p->gemm_splits != c) drop_graphs(p);
+            p->gemm_splits = c;
+            return true;
+        }
+        case TuneKind::LOADS:
+            if (c != 0 && c != 1) return false;
+            if (p->psym_nt != c) drop_graphs(p);
+            p->psym_nt = c;
+            return true;
+        case TuneKind::SHAPES:
+            if (c < 0 || c >= kNumShapes) return false;
+            if (p->shape != c) drop_graphs(p);
+            p->shape = c;
+            return true;
+        case TuneKind::NONE:
+            return c == -1;
+    }
+    return false;
+}
+
+}  // namespace
+}  // namespace tmag
+
 extern "C" tm_status tm_problem_tune(tm_problem* pp, int64_t B, int32_t iters, hipStream_t s,
                                      int32_t* chosen, double* best_ms) {
     Problem* p = reinterpret_cast<Problem*>(pp);
-    TM_REQUIRE(p && B >= 1 && iters >= 1, TM_EINVAL, "tm_problem_tune: bad arguments");
+    TM_REQUIRE(p && B >= 1 && iters != 0, TM_EINVAL, "tm_problem_tune: bad arguments");
     TM_TRY_HIP(hipSetDevice(p->ctx->device));
+    const TuneKind kind = tune_kind(p);
+    if (iters > 0) {
+        // a result for the same device, operator layout / precision, tile
+        // count and batch is reused without timing
+        TuneResult hit;
+        if (tune_lookup(p, B, &hit) && apply_choice(p, kind, hit.choice)) {
+            tm_status st = ensure_workspace(p, B);
+            if (st != TM_OK) return st;
+            if (chosen) *chosen = hit.choice;
+            if (best_ms) *best_ms = hit.ms;
+            return TM_OK;
+        }
+    }
+    const int32_t reps = iters > 0 ? iters : -iters;
     tm_status st = ensure_workspace(p, B);
     if (st != TM_OK) return st;
-    if (p->T->layout == TM_LAYOUT_DENSE9 && p->T->prec != TM_PREC_FP64) {
-        // the batched product: the number of K splits (split-K workgroups
-        // against the partial-sum pass), each candidate timed, the fastest kept
-        static const int kCand[] = {2, 3, 4, 5, 6, 8};
-        const int keep = p->gemm_splits;
-        int best = 0;
-        double best_t = 1e30;
-        for (int c : kCand) {
-            if (c > p->T->ld / kGemmKC) continue;
-            p->gemm_splits = c;
-            double ms = 0.0;
-            st = ensure_workspace(p, B);
-            if (st == TM_OK) st = time_field(p, B, 0, iters, s, &ms);
-            if (st != TM_OK) {
-                p->gemm_splits = keep;
-                return st;
-            }
-            if (ms < best_t) {
-                best_t = ms;
-                best = c;
-            }
-        }
-        p->gemm_splits = best;
-        if (chosen) *chosen = best;
-        if (best_ms) *best_ms = best_t;
-        return TM_OK;
+    std::vector<int> cand;
+    if (kind == TuneKind::SPLITS) {
+        for (int c : {2, 3, 4, 5, 6, 8})
+            if (c <= p->T->ld / kGemmKC) cand.push_back(c);
+    } else if (kind == TuneKind::LOADS) {
+        cand = {0, 1};
+    } else if (kind == TuneKind::SHAPES) {
+        for (int c = 0; c < kNumShapes; ++c) cand.push_back(c);
+    } else {
+        cand = {-1};
     }
-    if (is_psym(p->T->layout)) {
-        // the pair-symmetric tile pass: cached (0) or nontemporal (1) operator
-        // loads, each timed over the whole evaluation, the faster kept
-        const int keep = p->psym_nt;
-        int best = 0;
-        double best_t = 1e30;
-        for (int c = 0; c < 2; ++c) {
-            p->psym_nt = c;
-            double ms = 0.0;
-            st = time_field(p, B, 0, iters, s, &ms);
-            if (st != TM_OK) {
-                p->psym_nt = keep;
-                return st;
-            }
-            if (ms < best_t) {
-                best_t = ms;
-                best = c;
-            }
-        }
-        p->psym_nt = best;
-        if (best != keep && p->ws) {
-            // captured graphs hold the other tile-pass kernel
-            if (p->ws->graph1) (void)hipGraphExecDestroy(p->ws->graph1);
-            if (p->ws->graphK) (void)hipGraphExecDestroy(p->ws->graphK);
-            p->ws->graph1 = p->ws->graphK = nullptr;
-        }
-        if (chosen) *chosen = best;
-        if (best_ms) *best_ms = best_t;
-        return TM_OK;
-    }
-    if (p->T->layout != TM_LAYOUT_SYM6) {
-        // launch shapes belong to the dense SYM6 kernel; other layouts have one
-        double ms = 0.0;
-        st = time_field(p, B, 0, iters, s, &ms);
-        if (st != TM_OK) return st;
-        if (chosen) *chosen = -1;
-        if (best_ms) *best_ms = ms;
-        return TM_OK;
-    }
-    const int keep = p->shape;
-    int best = -1;
+    const int keep_splits = p->gemm_splits, keep_nt = p->psym_nt, keep_shape = p->shape;
+    int best = cand.front();
     double best_t = 1e30;
-    for (int sh = 0; sh < kNumShapes; ++sh) {
-        p->shape = sh;
+    for (int c : cand) {
+        if (kind == TuneKind::SPLITS) p->gemm_splits = c;
+        if (kind == TuneKind::LOADS) p->psym_nt = c;
+        if (kind == TuneKind::SHAPES) p->shape = c;
         double ms = 0.0;
-        st = time_field(p, B, 0, iters, s, &ms);
+        st = ensure_workspace(p, B);  // the split count sizes the partial sums
+        if (st == TM_OK) st = time_field(p, B, 0, reps, s, &ms);
         if (st != TM_OK) {
-            p->shape = keep;
+            p->gemm_splits = keep_splits;
+            p->psym_nt = keep_nt;
+            p->shape = keep_shape;
             return st;
         }
         if (ms < best_t) {
             best_t = ms;
-            best = sh;
+            best = c;
         }
     }
-    p->shape = keep;
-    st = tm_problem_set_shape(pp, best);
-    if (st != TM_OK) return st;
+    // back to the previous settings, then the winner (graphs dropped if it differs)
+    p->gemm_splits = keep_splits;
+    p->psym_nt = keep_nt;
+    p->shape = keep_shape;
+    (void)apply_choice(p, kind, best);
+    if (kind == TuneKind::SPLITS) {
+        st = ensure_workspace(p, B);
+        if (st != TM_OK) return st;
+    }
+    TuneResult r;
+    r.choice = best;
+    r.ms = best_t;
+    tune_store(p, B, r);
     if (chosen) *chosen = best;
     if (best_ms) *best_ms = best_t;
     return TM_OK;

@@ -10,8 +10,8 @@
 // four planes: the xz and yz components are odd in the z offset and vanish.
 //
 // Product, two launches per field evaluation:
-//  * k_psym_tiles: one workgroup per (tile pair, state) reads its tile once
-//    and forms both uses of it: the row sums  sum_b N^{ab} (Ms m)_b  for the
+//  * k_psym_tiles: one workgroup per tile pair (and group of states) reads its
+//    tile once and forms both uses of it for each state: the row sums  sum_b N^{ab} (Ms m)_b  for the
 //    targets a of tile I, and for I < J the column sums
 //    sum_a N^{ab} (Ms m)_a = sum_a N^{ba} (Ms m)_a  for the targets b of
 //    tile J.  Each lands in its own slot part[s][K][j][TS][3] (K = the target
@@ -25,6 +25,7 @@
 // against 24 N^2 for SYM6 (PSYM4: 16 B x TS^2, about 8 N^2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "common.h"
@@ -54,18 +55,23 @@ inline int64_t pair_index(int64_t I, int64_t J, int64_t nt) {
     return I == J ? I : nt + I * (nt - 1) - I * (I - 1) / 2 + (J - I - 1);
 }
 
-// One workgroup per (tile pair, state).  Thread t takes column b = t % TS of
-// the tile and rows rg RPT .. rg RPT + RPT - 1 (rg = t / TS): each row's six
-// components are coalesced loads, the row sums go through LDS to a sum over
-// the TS columns, the column sums through LDS to a sum over the RG groups
-// (both in a fixed order).
+// One workgroup per tile pair and group of states: it reads its tile once
+// and applies it to states s = blockIdx.y, blockIdx.y + gridDim.y, ... (one
+// state per workgroup when the grid has B rows; every state of the batch
+// when it has one, so that a batch streams the operator once).  Thread t
+// takes column b = t % TS of the tile and rows rg RPT .. rg RPT + RPT - 1
+// (rg = t / TS): each row's components are coalesced loads; per state the
+// row sums go through LDS to a sum over the TS columns, the column sums
+// through LDS to a sum over the RG groups (both in a fixed order, the same
+// for every grid shape: results do not depend on the batch).
 //
 // LOCALF: the workgroups of diagonal pairs (I == J) also evaluate the local
 // field terms (exchange, anisotropy, applied field) of their TS tiles --
-// issued before the tile is streamed, so that the dependent neighbour loads
-// overlap it, and dispatched first (diagonal pairs lead the pair table) --
-// and subtract them from their own slot, so that minus the slot sum is the
-// whole effective field and the finish kernel has no dependent loads left.
+// issued before the tile's products, so that the dependent neighbour loads
+// overlap the tile loads, and dispatched first (diagonal pairs lead the pair
+// table) -- and subtract them from their own slot, so that minus the slot sum
+// is the whole effective field and the finish kernel has no dependent loads
+// left.
 // NP = 6: planes (xx, xy, xz, yy, yz, zz); NP = 4 (a single layer): (xx, xy,
 // yy, zz), with xz = yz = 0.
 template <bool STEPPING, bool LOCALF, bool NTL, int NP>
@@ -73,13 +79,18 @@ __global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const
                                                     const int32_t* __restrict__ pairs, int64_t nt,
                                                     const float* __restrict__ Ms, const float* __restrict__ X,
                                                     int64_t sx, const double* __restrict__ h,
-                                                    const float* __restrict__ Ha, float* __restrict__ part) {
+                                                    const float* __restrict__ Ha, float* __restrict__ part,
+                                                    int64_t B) {
     const int64_t p = blockIdx.x;
-    const int64_t s = blockIdx.y;
     const int t = threadIdx.x;
     const int b = t % TS, rg = t / TS;
-    // a frozen state reads no operator (a batch may hold many of them)
-    if (STEPPING && h[s] == 0.0) return;
+    // frozen states read no operator (a batch may hold many of them): a
+    // workgroup whose states are all frozen stops before loading its tile
+    if (STEPPING) {
+        bool live = false;
+        for (int64_t s = blockIdx.y; s < B && !live; s += gridDim.y) live = h[s] != 0.0;
+        if (!live) return;
+    }
     const float* tile = tiles + p * NP * TB;
     float v[RPT][NP];
 #pragma unroll
@@ -90,53 +101,59 @@ __global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const
     __shared__ float rred[TS][3][TS + 1];  // row sums before the column reduction
     __shared__ float cred[RG][TS][3];      // column sums per row group
     __shared__ float hl[TS][3];            // local field terms (diagonal pairs)
-    const float* x = X + s * sx;
-    if (LOCALF && I == J && t < TS) {
-        const int64_t a = TS * I + t;
-        float H0 = 0.0f, H1 = 0.0f, H2 = 0.0f;
-        if (a < P.n)
-            add_local_field(P, x, Ha, static_cast<int>(s), static_cast<int>(a), x[3 * a], x[3 * a + 1],
-                            x[3 * a + 2], H0, H1, H2);
-        hl[t][0] = H0;
-        hl[t][1] = H1;
-        hl[t][2] = H2;
-    }
     const int64_t bg = TS * J + b;
     const float msb = Ms[bg];
-    const float xb0 = x[3 * bg] * msb, xb1 = x[3 * bg + 1] * msb, xb2 = x[3 * bg + 2] * msb;
-    float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    bool first = true;
+    for (int64_t s = blockIdx.y; s < B; s += gridDim.y) {
+        if (STEPPING && h[s] == 0.0) continue;
+        if (!first) __syncthreads();  // the previous state's sums have been read
+        first = false;
+        const float* x = X + s * sx;
+        if (LOCALF && I == J && t < TS) {
+            const int64_t a = TS * I + t;
+            float H0 = 0.0f, H1 = 0.0f, H2 = 0.0f;
+            if (a < P.n)
+                add_local_field(P, x, Ha, static_cast<int>(s), static_cast<int>(a), x[3 * a], x[3 * a + 1],
+                                x[3 * a + 2], H0, H1, H2);
+            hl[t][0] = H0;
+            hl[t][1] = H1;
+            hl[t][2] = H2;
+        }
+        const float xb0 = x[3 * bg] * msb, xb1 = x[3 * bg + 1] * msb, xb2 = x[3 * bg + 2] * msb;
+        float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-        const int al = RPT * rg + i;
-        const int64_t ag = TS * I + al;
-        const float msa = Ms[ag];
-        const float xa0 = x[3 * ag] * msa, xa1 = x[3 * ag + 1] * msa, xa2 = x[3 * ag + 2] * msa;
-        const float v0 = v[i][0], v1 = v[i][1];
-        const float v2 = NP == 6 ? v[i][2] : 0.0f, v3 = v[i][NP == 6 ? 3 : 2];
-        const float v4 = NP == 6 ? v[i][4] : 0.0f, v5 = v[i][NP - 1];
-        rred[al][0][b] = v0 * xb0 + v1 * xb1 + v2 * xb2;
-        rred[al][1][b] = v1 * xb0 + v3 * xb1 + v4 * xb2;
-        rred[al][2][b] = v2 * xb0 + v4 * xb1 + v5 * xb2;
-        c0 += v0 * xa0 + v1 * xa1 + v2 * xa2;
-        c1 += v1 * xa0 + v3 * xa1 + v4 * xa2;
-        c2 += v2 * xa0 + v4 * xa1 + v5 * xa2;
-    }
-    cred[rg][b][0] = c0;
-    cred[rg][b][1] = c1;
-    cred[rg][b][2] = c2;
-    __syncthreads();
-    if (t < 3 * TS) {
-        const int r = t / 3, c = t % 3;
-        float acc = 0.0f;
+        for (int i = 0; i < RPT; ++i) {
+            const int al = RPT * rg + i;
+            const int64_t ag = TS * I + al;
+            const float msa = Ms[ag];
+            const float xa0 = x[3 * ag] * msa, xa1 = x[3 * ag + 1] * msa, xa2 = x[3 * ag + 2] * msa;
+            const float v0 = v[i][0], v1 = v[i][1];
+            const float v2 = NP == 6 ? v[i][2] : 0.0f, v3 = v[i][NP == 6 ? 3 : 2];
+            const float v4 = NP == 6 ? v[i][4] : 0.0f, v5 = v[i][NP - 1];
+            rred[al][0][b] = v0 * xb0 + v1 * xb1 + v2 * xb2;
+            rred[al][1][b] = v1 * xb0 + v3 * xb1 + v4 * xb2;
+            rred[al][2][b] = v2 * xb0 + v4 * xb1 + v5 * xb2;
+            c0 += v0 * xa0 + v1 * xa1 + v2 * xa2;
+            c1 += v1 * xa0 + v3 * xa1 + v4 * xa2;
+            c2 += v2 * xa0 + v4 * xa1 + v5 * xa2;
+        }
+        cred[rg][b][0] = c0;
+        cred[rg][b][1] = c1;
+        cred[rg][b][2] = c2;
+        __syncthreads();
+        if (t < 3 * TS) {
+            const int r = t / 3, c = t % 3;
+            float acc = 0.0f;
 #pragma unroll 8
-        for (int l = 0; l < TS; ++l) acc += rred[r][c][l];
-        if (LOCALF && I == J) acc -= hl[r][c];
-        part[((s * nt + I) * nt + J) * (3 * TS) + t] = acc;
-        if (I != J) {
-            float cs = 0.0f;
+            for (int l = 0; l < TS; ++l) acc += rred[r][c][l];
+            if (LOCALF && I == J) acc -= hl[r][c];
+            part[((s * nt + I) * nt + J) * (3 * TS) + t] = acc;
+            if (I != J) {
+                float cs = 0.0f;
 #pragma unroll
-            for (int q = 0; q < RG; ++q) cs += cred[q][r][c];
-            part[((s * nt + J) * nt + I) * (3 * TS) + t] = cs;
+                for (int q = 0; q < RG; ++q) cs += cred[q][r][c];
+                part[((s * nt + J) * nt + I) * (3 * TS) + t] = cs;
+            }
         }
     }
 }
@@ -151,24 +168,35 @@ constexpr int64_t kPsymStreamBytes = 192ll << 20;
 template <bool STEPPING, bool LOCALF, int NP>
 inline void launch_tiles_np(dim3 grid, hipStream_t st, bool nt_loads, const DevProblem& P, const float* tiles,
                             const int32_t* pairs, int64_t nt, const float* Ms, const float* X, int64_t sx,
-                            const double* h, const float* Ha, float* part) {
+                            const double* h, const float* Ha, float* part, int64_t B) {
     if (nt_loads)
         launch_op(k_psym_tiles<STEPPING, LOCALF, true, NP>, grid, dim3(kTileThreads), st, P, tiles, pairs, nt, Ms, X,
-                  sx, h, Ha, part);
+                  sx, h, Ha, part, B);
     else
         launch_op(k_psym_tiles<STEPPING, LOCALF, false, NP>, grid, dim3(kTileThreads), st, P, tiles, pairs, nt, Ms,
-                  X, sx, h, Ha, part);
+                  X, sx, h, Ha, part, B);
+}
+
+// Grid of the tile pass for B states: one workgroup per tile pair and group
+// of states.  A pair's tile is read once per group, so the fewer groups the
+// fewer operator bytes; the states are split over several groups only while
+// the pairs alone leave the 256 CUs short of work (kTileWorkgroups).
+constexpr int64_t kTileWorkgroups = 1024;
+dim3 tile_grid(const Tensor* T, int64_t B) {
+    const int64_t groups = std::min<int64_t>(B, std::max<int64_t>(1, (kTileWorkgroups + T->npairs - 1) / T->npairs));
+    return dim3(static_cast<unsigned>(T->npairs), static_cast<unsigned>(groups));
 }
 
 template <bool STEPPING, bool LOCALF>
-inline void launch_tiles(const Tensor* T, bool nt_loads, dim3 grid, hipStream_t st, const DevProblem& P,
+inline void launch_tiles(const Tensor* T, bool nt_loads, int64_t B, hipStream_t st, const DevProblem& P,
                          const float* Ms, const float* X, int64_t sx, const double* h, const float* Ha,
                          float* part) {
     const float* tiles = static_cast<const float*>(T->data);
+    const dim3 grid = tile_grid(T, B);
     if (T->layout == TM_LAYOUT_PSYM4)
-        launch_tiles_np<STEPPING, LOCALF, 4>(grid, st, nt_loads, P, tiles, T->pairs, T->nt, Ms, X, sx, h, Ha, part);
+        launch_tiles_np<STEPPING, LOCALF, 4>(grid, st, nt_loads, P, tiles, T->pairs, T->nt, Ms, X, sx, h, Ha, part, B);
     else
-        launch_tiles_np<STEPPING, LOCALF, 6>(grid, st, nt_loads, P, tiles, T->pairs, T->nt, Ms, X, sx, h, Ha, part);
+        launch_tiles_np<STEPPING, LOCALF, 6>(grid, st, nt_loads, P, tiles, T->pairs, T->nt, Ms, X, sx, h, Ha, part, B);
 }
 
 // One workgroup per (target tile K, state): the nt slots of K are contiguous
@@ -270,8 +298,7 @@ void launch_psym_t(const DevProblem& P, const Tensor* T, bool nt_loads, const fl
                    const float* X, int64_t sx, const EpiArgs& e, hipStream_t s) {
     constexpr bool STEPPING = MODE == Epi::STAGE || MODE == Epi::RK4_FINAL || MODE == Epi::DP_LAST;
     constexpr bool LOCALF = MODE != Epi::HD;
-    const dim3 g1(static_cast<unsigned>(T->npairs), static_cast<unsigned>(B));
-    launch_tiles<STEPPING, LOCALF>(T, nt_loads, g1, s, P, Ms, X, sx, e.h, e.Ha, part);
+    launch_tiles<STEPPING, LOCALF>(T, nt_loads, B, s, P, Ms, X, sx, e.h, e.Ha, part);
     const dim3 g2(static_cast<unsigned>(T->nt), static_cast<unsigned>(B));
     k_psym_finish<MODE><<<g2, kFinishThreads, 0, s>>>(P, part, T->nt, X, sx, e);
 }
@@ -292,8 +319,7 @@ tm_status launch_psym_tiles(const Problem* p, int64_t B, const float* X, const d
     Workspace* w = p->ws.get();
     TM_REQUIRE(is_psym(T->layout) && w && w->part && w->B >= B, TM_EINVAL,
                "pair-symmetric tile pass: not prepared");
-    const dim3 g1(static_cast<unsigned>(T->npairs), static_cast<unsigned>(B));
-    launch_tiles<true, true>(T, psym_nt_loads(p), g1, s, p->dev(), p->Ms, X, 3 * p->np, h, Ha, w->part);
+    launch_tiles<true, true>(T, psym_nt_loads(p), B, s, p->dev(), p->Ms, X, 3 * p->np, h, Ha, w->part);
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
 }

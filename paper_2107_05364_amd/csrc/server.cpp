@@ -380,9 +380,24 @@ void tm_server::run() {
                 still.push_back(r);
         }
         waiting.swap(still);
-        // the next round of every idle group with work
-        for (Group* g : groups) {
-            if (g->launched || !has_work(g)) continue;
+        // the next round of the idle groups with work; with max_active > 0 only
+        // the max_active groups holding the oldest requests advance, so that
+        // the device is not split over every resident group (the oldest
+        // requests finish first, as in arrival order)
+        std::vector<Group*> order;
+        for (Group* g : groups)
+            if (has_work(g)) order.push_back(g);
+        auto oldest = [](const Group* g) {
+            clock_t_::time_point t = clock_t_::time_point::max();
+            for (const Req* r : g->slot)
+                if (r && r->t_submit < t) t = r->t_submit;
+            return t;
+        };
+        std::stable_sort(order.begin(), order.end(),
+                         [&](const Group* a, const Group* b) { return oldest(a) < oldest(b); });
+        if (cfg.max_active > 0 && static_cast<int>(order.size()) > cfg.max_active) order.resize(cfg.max_active);
+        for (Group* g : order) {
+            if (g->launched) continue;
             Workspace* w = g->P->ws.get();
             const int rounds = std::max(1, cfg.steps_per_round / kGraphSteps);
             bool ok = true;
@@ -417,7 +432,7 @@ extern "C" {
 tm_status tm_server_create(tm_ctx* c, const tm_server_cfg* cfg, tm_server** out) {
     TM_REQUIRE(c && cfg && out, TM_EINVAL, "tm_server_create: null argument");
     TM_REQUIRE(cfg->max_slots >= 1 && cfg->max_slots <= 4096 && cfg->max_groups >= 1 &&
-                   cfg->steps_per_round >= 1,
+                   cfg->steps_per_round >= 1 && cfg->max_active >= 0,
                TM_EINVAL, "tm_server_create: bad slot / group / round settings");
     TM_REQUIRE(cfg->prec == TM_PREC_FP32, TM_EINVAL, "tm_server_create: only FP32 operators are served");
     Ctx* ctx = reinterpret_cast<Ctx*>(c);

@@ -38,7 +38,8 @@ EXPORTS = [
     "tm_diagnostics",
     "tm_run", "tm_profile_run", "tm_profile_field", "tm_profile_field_mode", "tm_num_shapes", "tm_shape_info",
     "tm_problem_shape", "tm_problem_set_shape",
-    "tm_problem_tune", "tm_server_create", "tm_server_submit", "tm_server_poll", "tm_server_destroy",
+    "tm_problem_tune", "tm_tune_cache_save", "tm_tune_cache_load", "tm_tune_cache_clear",
+    "tm_tune_cache_size", "tm_server_create", "tm_server_submit", "tm_server_poll", "tm_server_destroy",
 ]
 
 
@@ -58,7 +59,7 @@ class tm_run_cfg(C.Structure):
     _fields_ = [("max_steps", C.c_int64), ("max_attempts", C.c_int64), ("t_end", C.c_double),
                 ("atol", C.c_double), ("rtol", C.c_double), ("dt_min", C.c_double),
                 ("dmdt_stop", C.c_double), ("renorm", C.c_int32), ("use_graph", C.c_int32),
-                ("poll_every", C.c_int32)]
+                ("poll_every", C.c_int32), ("persistent", C.c_int32)]
 
 
 class tm_run_stats(C.Structure):
@@ -69,7 +70,7 @@ class tm_run_stats(C.Structure):
 
 class tm_server_cfg(C.Structure):
     _fields_ = [("memory_budget", C.c_int64), ("max_slots", C.c_int32), ("max_groups", C.c_int32),
-                ("steps_per_round", C.c_int32), ("prec", C.c_int32)]
+                ("steps_per_round", C.c_int32), ("prec", C.c_int32), ("max_active", C.c_int32)]
 
 
 class tm_request(C.Structure):
@@ -143,6 +144,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "tm_problem_shape": (i32, [vp, P(i32)]),
         "tm_problem_set_shape": (i32, [vp, i32]),
         "tm_problem_tune": (i32, [vp, i64, i32, vp, P(i32), P(d)]),
+        "tm_tune_cache_save": (i32, [C.c_char_p]),
+        "tm_tune_cache_load": (i32, [C.c_char_p]),
+        "tm_tune_cache_clear": (i32, []),
+        "tm_tune_cache_size": (i32, [P(i64)]),
         "tm_server_create": (i32, [vp, P(tm_server_cfg), P(vp)]),
         "tm_server_submit": (i32, [vp, P(tm_request), P(u64)]),
         "tm_server_poll": (i32, [vp, u64, i32, P(tm_result), P(C.c_float)]),
@@ -478,10 +483,33 @@ def tm_problem_set_shape(p, shape: int) -> None:
 
 
 def tm_problem_tune(p, B: int = 1, iters: int = 20):
-    """(chosen shape, its mean ms per launch)."""
+    """(chosen candidate, its mean ms per launch); iters < 0 times even when
+    the autotuner's table holds a result for this key."""
     ch, ms = C.c_int32(), C.c_double()
     _check(load().tm_problem_tune(p, int(B), int(iters), _stream(), C.byref(ch), C.byref(ms)))
     return ch.value, ms.value
+
+
+def tm_tune_cache_save(path: str) -> None:
+    _check(load().tm_tune_cache_save(os.fsencode(path)))
+
+
+def tm_tune_cache_load(path: str) -> int:
+    """Merges a saved table; returns the status (TM_ENOTFOUND if the file is missing)."""
+    r = load().tm_tune_cache_load(os.fsencode(path))
+    if r not in (TM_OK, TM_ENOTFOUND):
+        _check(r)
+    return r
+
+
+def tm_tune_cache_clear() -> None:
+    _check(load().tm_tune_cache_clear())
+
+
+def tm_tune_cache_size() -> int:
+    n = C.c_int64()
+    _check(load().tm_tune_cache_size(C.byref(n)))
+    return n.value
 
 
 # ------------------------------------------------------------ convenience
@@ -617,7 +645,7 @@ class Problem:
 
     def run(self, m, Ha=None, integ=TM_DP45, dt=1e-14, t=None, max_steps=1, max_attempts=0,
             atol=1e-6, rtol=1e-6, t_end=0.0, dt_min=0.0, dmdt_stop=0.0, renorm=True,
-            use_graph=True, poll_every=64, check=True):
+            use_graph=True, poll_every=64, check=True, persistent=False):
         """Integrates the states in place; returns (t, dt, steps, stats)."""
         import torch
 
@@ -631,7 +659,7 @@ class Problem:
         steps = torch.zeros(B, dtype=torch.int64, device=dev)
         cfg = tm_run_cfg(int(max_steps), int(max_attempts), float(t_end), float(atol), float(rtol),
                          float(dt_min), float(dmdt_stop), int(bool(renorm)), int(bool(use_graph)),
-                         int(poll_every))
+                         int(poll_every), int(bool(persistent)))
         st = tm_run(self.handle, self.n, integ, m, Ha, tt, dd, steps, cfg, check=check)
         return tt, dd, steps, st
 
@@ -642,9 +670,9 @@ class Problem:
 
 
 def tm_server_create(ctx, memory_budget=0, max_slots=8, max_groups=16, steps_per_round=64,
-                     prec=TM_PREC_FP32) -> C.c_void_p:
+                     prec=TM_PREC_FP32, max_active=0) -> C.c_void_p:
     cfg = tm_server_cfg(int(memory_budget), int(max_slots), int(max_groups), int(steps_per_round),
-                        int(prec))
+                        int(prec), int(max_active))
     out = C.c_void_p()
     _check(load().tm_server_create(ctx, C.byref(cfg), C.byref(out)))
     return out
@@ -683,9 +711,9 @@ class Server:
     """Continuous-batching server of LLG relaxation requests on one device."""
 
     def __init__(self, ctx: Context, memory_budget=0, max_slots=8, max_groups=16,
-                 steps_per_round=64):
+                 steps_per_round=64, max_active=0):
         self.handle = tm_server_create(ctx.handle, memory_budget, max_slots, max_groups,
-                                       steps_per_round)
+                                       steps_per_round, max_active=max_active)
         self._n = {}
 
     def submit(self, centers, sizes, m0, Ha, **kw) -> int:

@@ -148,6 +148,37 @@ def sp3_cube(n: int, lam: float, Ms: float = 8.0e5, edge: float = 20 * NM) -> Wo
                            "ll_form": 1, "volume": edge ** 3, "dmdt_stop": 1e-4 * GAMMA0 * Ms})
 
 
+# Standard problem 4 (paper Sec. 4.3): the s-state is prepared by saturating
+# along [1, 1, 1] and removing that field slowly; here a staircase of fields
+# along [1, 1, 1] (mT), each level relaxed by pure damping (LL with c1 = 0,
+# c2 = gamma0) until max_a |dm/dt|_a < SP4_RELAX_STOP.  The dynamics then use
+# the paper's LL parameters (ll_form 1: c1 = gamma = 2.21e5, c2 = alpha = 4.42e3)
+# under field 1 or field 2, switched on at t = 0, for SP4_DYN_TIME.
+SP4_LEVELS_MT = (1000.0, 300.0, 100.0, 30.0, 10.0, 3.0, 0.0)
+SP4_RELAX_STOP = 1e-4 * GAMMA0 * 8.0e5
+SP4_FIELDS_MT = {1: (-24.6, 4.3, 0.0), 2: (-35.5, -6.3, 0.0)}
+SP4_DYN_TIME = 1e-9
+
+
+def sp4_film(n: int) -> Workload:
+    """Standard-problem-4 film at resolution [20n, 5n, 1] (tiles of
+    25/n x 25/n x 3 nm), Ms = 8.0e5 A/m, A = 1.3e-11 J/m, starting saturated
+    along [1, 1, 1].  extra: the s-state staircase (applied fields [A/m] per
+    level), the relaxation LL parameters, the dynamics LL parameters and the
+    two reversal fields [A/m]."""
+    c, s = grid(20 * n, 5 * n, 1, 25 * NM / n, 25 * NM / n, 3 * NM)
+    d = np.ones(3) / math.sqrt(3.0)
+    m0 = np.tile(d, (c.shape[0], 1))[None]
+    levels = [d * (b * 1e-3 / MU0) for b in SP4_LEVELS_MT]
+    fields = {k: np.array(v) * 1e-3 / MU0 for k, v in SP4_FIELDS_MT.items()}
+    return Workload("sp4_film_n%d" % n, c, s, m0, np.zeros((1, 3)), Ms=8.0e5, A=1.3e-11,
+                    alpha=4.42e3, gamma0=GAMMA0,
+                    extra={"n": n, "levels": levels, "relax_stop": SP4_RELAX_STOP,
+                           "relax_ll": (0.0, GAMMA0),  # (c1, c2): pure damping
+                           "dyn_ll": (GAMMA0, 4.42e3), "ll_form": 1, "fields": fields,
+                           "dyn_time": SP4_DYN_TIME})
+
+
 def hysteresis_batch(B: int = 128, nx: int = 100, ny: int = 25, seed_axis: int = 2) -> Workload:
     """B independent states on the film geometry: fields evenly spaced from
     +80 mT to -80 mT along one seeded in-plane axis; state k starts from the

@@ -123,3 +123,38 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_tune_cache_file_round_trip(tmg, tmp_path):
+    """The autotuner table's JSON file: entries load, save and load back
+    unchanged; a missing file and a foreign or malformed one are refused
+    (host logic only, no device)."""
+    src = tmp_path / "tune.json"
+    src.write_text(
+        '{"tilemag_tune_cache": 1, "entries": [\n'
+        ' {"arch": "gfx950:sramecc+:xnack-", "cus": 256, "layout": 4, "prec": 0, "n": 2500, "batch": 1, '
+        '"choice": 1, "ms": 0.0127},\n'
+        ' {"arch": "gfx950:sramecc+:xnack-", "cus": 256, "layout": 0, "prec": 0, "n": 512, "batch": 1, '
+        '"choice": 10, "ms": 0.00426}\n]}\n')
+    tmg.tm_tune_cache_clear()
+    assert tmg.tm_tune_cache_size() == 0
+    assert tmg.tm_tune_cache_load(str(src)) == tmg.TM_OK
+    assert tmg.tm_tune_cache_size() == 2
+    out = tmp_path / "out.json"
+    tmg.tm_tune_cache_save(str(out))
+    tmg.tm_tune_cache_clear()
+    assert tmg.tm_tune_cache_load(str(out)) == tmg.TM_OK and tmg.tm_tune_cache_size() == 2
+    again = tmp_path / "again.json"
+    tmg.tm_tune_cache_save(str(again))
+    assert again.read_text() == out.read_text()
+    assert '"n": 2500, "batch": 1, "choice": 1, "ms": 0.0127' in out.read_text()
+    assert tmg.tm_tune_cache_load(str(tmp_path / "missing.json")) == tmg.TM_ENOTFOUND
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"something_else": 1}\n')
+    with pytest.raises(tmg.TilemagError):
+        tmg.tm_tune_cache_load(str(bad))
+    bad.write_text('{"tilemag_tune_cache": 1, "entries": [\n {"arch": "gfx950", "cus": 256}\n]}\n')
+    with pytest.raises(tmg.TilemagError):
+        tmg.tm_tune_cache_load(str(bad))
+    assert tmg.tm_tune_cache_size() == 2  # a refused file adds nothing
+    tmg.tm_tune_cache_clear()

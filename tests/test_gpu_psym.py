@@ -361,3 +361,35 @@ def test_psym_tuned_loads_same_results(tmg, ctx):
         assert chosen in (0, 1) and ms > 0
         assert np.array_equal(p.heff(md).cpu().numpy(), before)
         close(g, T, p)
+
+
+@pytest.mark.parametrize("layout", ["psym4", "psym6"])
+def test_psym_batch_shares_tile_reads_film(tmg, ctx, orc, layout):
+    """On the film (3160 tile pairs) one workgroup per pair applies its tile
+    to every state of the batch; each state's field and DP45 steps are
+    bitwise those it gets alone, and the field meets the oracle tolerance."""
+    import torch
+
+    wl = W.thin_film()
+    lay = tmg.TM_LAYOUT_PSYM4 if layout == "psym4" else tmg.TM_LAYOUT_PSYM6
+    _say("%s film batch of 3 sharing tile reads" % layout)
+    g, T, p = build(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha, layout=lay)
+    m = np.stack([W.film_texture(wl.centers, 500e-9, 200 + k) for k in range(3)]).astype(np.float32)
+    Ha = np.array([[2e4, 1e4, 0.0], [-3e4, 0.0, 0.0], [0.0, 2e4, 0.0]], np.float32)
+    H3 = p.heff(device_state(m), torch.as_tensor(Ha, device="cuda")).cpu().numpy()
+    P = orc.Problem(wl.centers, wl.sizes, wl.Ms, wl.A, wl.alpha)
+    for k in range(3):
+        one = p.heff(device_state(m[k:k + 1]), torch.as_tensor(Ha[k:k + 1], device="cuda")).cpu().numpy()
+        assert np.array_equal(H3[k], one[0]), k
+    e2, emax = rel_errors(H3[1], P.heff(m[1].astype(np.float64), Ha[1].astype(np.float64)))
+    assert e2 <= 1e-5 and emax <= 1e-5, (e2, emax)
+    md = device_state(m)
+    t, dt, steps, st = p.run(md, torch.as_tensor(Ha, device="cuda"), tmg.TM_DP45, dt=1e-14, max_steps=1 << 30,
+                             max_attempts=3)
+    got3 = md.cpu().numpy()
+    for k in range(3):
+        mk = device_state(m[k:k + 1])
+        p.run(mk, torch.as_tensor(Ha[k:k + 1], device="cuda"), tmg.TM_DP45, dt=1e-14, max_steps=1 << 30,
+              max_attempts=3)
+        assert np.array_equal(got3[k], mk.cpu().numpy()[0]), k
+    close(g, T, p)
