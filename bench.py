@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--no-sp3", action="store_true")
     ap.add_argument("--no-cache-free", action="store_true")
     ap.add_argument("--no-sp4-dynamics", action="store_true")
+    ap.add_argument("--profile-film", choices=["100x25", "160x40"], default="100x25",
+                    help="film of the counter runs (--profile-only): the headline N = 2500, or N = 6400 "
+                         "whose operator exceeds the Infinity Cache")
     ap.add_argument("--profile-only", action="store_true",
                     help="counter runs: one 1 GiB device copy (calibration) and the stage kernel "
                          "of the film workload only")
@@ -88,6 +91,16 @@ def kernel_source_hash(layout):
     return h.hexdigest()[:16]
 
 
+def _same_pass(a, b):
+    """The pair-symmetric tile pass reads the same bytes with cached or with
+    nontemporal operator loads (the autotuner picks either): its two load
+    variants count as one kernel here."""
+    import re
+
+    norm = lambda k: re.sub(r"^(k_psym_tiles<true,true,)(true|false)(,)", r"\1*\3", k.strip())
+    return norm(a) == norm(b)
+
+
 def counter_traffic(layout, kname):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE runs, calibrated against a 1 GiB copy),
@@ -97,7 +110,7 @@ def counter_traffic(layout, kname):
     except OSError:
         return None
     vals = dict(ln.split(":", 1) for ln in text.splitlines() if ln.startswith(("source_hash:", "kernel:", "traffic_bytes_per_launch:")))
-    if vals.get("source_hash", "").strip() != kernel_source_hash(layout) or vals.get("kernel", "").strip() != kname:
+    if vals.get("source_hash", "").strip() != kernel_source_hash(layout) or not _same_pass(vals.get("kernel", ""), kname):
         return None
     return int(vals["traffic_bytes_per_launch"].strip())
 
@@ -185,8 +198,11 @@ def batched_section(tmg, W, torch, attempts=60, profile_iters=20):
         m = torch.as_tensor(m32, device="cuda")
         hds[name] = p.demag(m).cpu().numpy()
         rhs_ms, _ = tmg.tm_profile_field(p.handle, B, profile_iters)
-        flops = 2.0 * 9 * n * n * B * (3 if name != "fp32" else 1)
-        op_bytes = 36.0 * n * n
+        # a single layer: the operator is stored without its two zero blocks
+        # (5 of the 9 components per block pair; bytes and products alike)
+        comps = 5 if np.all(wl.centers[:, 2] == wl.centers[0, 2]) else 9
+        flops = 2.0 * comps * n * n * B * (3 if name != "fp32" else 1)
+        op_bytes = 4.0 * comps * n * n
         p.run(m, Ha, tmg.TM_DP45, dt=1e-14, max_steps=1 << 40, max_attempts=10)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -733,7 +749,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    wl = W.thin_film()
+    wl = W.thin_film() if not args.profile_only or args.profile_film == "100x25" else W.thin_film(nx=160, ny=40)
     n = wl.n
     ctx = tmg.Context(0)
     geom = tmg.Geometry(ctx, wl.centers, wl.sizes)
@@ -791,7 +807,7 @@ def main():
         planes = 4 if args.layout == "psym4" else 6
         alg_bytes = n * (n + 1) // 2 * planes * 4 + 24 * n
         alg_basis = "N(N+1)/2 blocks x %d planes x 4 B + 24 N (state in, slots out not counted)" % planes
-        kname = "k_psym_tiles<true,true,%s,%d>" % ("true" if nt_loads else "false", planes)
+        kname = "k_psym_tiles<true,true,%s,%d,false>" % ("true" if nt_loads else "false", planes)
         kdesc = (" (pair-symmetric tile pass of the demag product; the slot sum and epilogue run in "
                  "a second launch, included in field_evaluation_us)")
     else:

@@ -63,7 +63,11 @@ typedef enum {
     TM_LAYOUT_SYM6 = 0,   /* 6 planes [6][N][ldN] of (xx,xy,xz,yy,yz,zz), each 3x3 block symmetric */
     TM_LAYOUT_DENSE9 = 1, /* dense [3N][ld3N] operator, the MFMA GEMM operand: FP64 row-major;
                              FP32 and the split forms in blocks of 128 rows x 64 columns
-                             ordered as the product loads them (read back row-major) */
+                             ordered as the product loads them (read back row-major); for a
+                             single layer of tiles (one z for every centre) FP32 and the split
+                             forms order rows and columns by component and leave out the two
+                             blocks that vanish there (xz and yz): 5/9 of the bytes and
+                             products */
     TM_LAYOUT_BSR6 = 2,   /* thresholded operator: block-sparse rows of 6-component blocks
                              (made by tm_tensor_threshold only) */
     TM_LAYOUT_PSYM6 = 3,  /* pair-symmetric operator of a mesh of identical tiles: only the

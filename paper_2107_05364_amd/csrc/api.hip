@@ -247,7 +247,12 @@ tm_status tm_tensor_assemble(tm_ctx* c, const tm_geom* g, tm_prec store, tm_layo
     } else {
         T->ld = 3 * np;
         T->rows = round_up(3 * np, 128);
-        main_bytes = T->rows * T->ld * static_cast<int64_t>(esz);
+        // a single layer of tiles in FP32 or split precision: the
+        // component-blocked form, which leaves out the two zero blocks
+        bool layer = store != TM_PREC_FP64;
+        for (int64_t a = 1; a < n && layer; ++a) layer = g->centers[3 * a + 2] == g->centers[2];
+        T->cblk = layer;
+        main_bytes = (layer ? 5 * np * np : T->rows * T->ld) * static_cast<int64_t>(esz);
         if (store == TM_PREC_BF16X3 || store == TM_PREC_FP16X3) lo_bytes = main_bytes;
         if (store == TM_PREC_FP16X3) sc_bytes = T->rows * 4;
     }

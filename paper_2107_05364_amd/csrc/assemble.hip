@@ -144,32 +144,40 @@ __global__ __launch_bounds__(256) void k_assemble_dense9(int32_t n, int64_t ld,
     r2[0] = cvt<OutT>(t6[2]); r2[1] = cvt<OutT>(t6[4]); r2[2] = cvt<OutT>(t6[5]);
 }
 
+// Stored place of tile-order element (r, k) of a blocked DENSE9 operator
+// (-1: a zero block of the component-blocked form, not stored).
+__device__ inline int64_t store_index(bool cblk, int64_t ld, int vec, int64_t r, int64_t k) {
+    return cblk ? dense9c_index(ld / 3, vec, r, k) : dense9_index(ld, vec, r, k);
+}
+
 // Split float32 entries (row-major src, rows x ld) into bf16 hi + lo (hi + lo
 // carries 16 significant bits), written in the blocked product order.
-__global__ __launch_bounds__(256) void k_split_bf16(int64_t rows, int64_t ld, const float* __restrict__ src,
+__global__ __launch_bounds__(256) void k_split_bf16(int64_t rows, int64_t ld, bool cblk, const float* __restrict__ src,
                                                     __hip_bfloat16* __restrict__ hi,
                                                     __hip_bfloat16* __restrict__ lo) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= rows * ld) return;
+    const int64_t o = store_index(cblk, ld, 8, i / ld, i % ld);
+    if (o < 0) return;
     const float v = src[i];
     const __hip_bfloat16 h = __float2bfloat16(v);
-    const int64_t o = dense9_index(ld, 8, i / ld, i % ld);
     hi[o] = h;
     lo[o] = __float2bfloat16(v - __bfloat162float(h));
 }
 
 // Row-major float32 (rows x ld) to the blocked product order.
-__global__ __launch_bounds__(256) void k_block_fp32(int64_t rows, int64_t ld, const float* __restrict__ src,
+__global__ __launch_bounds__(256) void k_block_fp32(int64_t rows, int64_t ld, bool cblk, const float* __restrict__ src,
                                                     float* __restrict__ dst) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= rows * ld) return;
-    dst[dense9_index(ld, 4, i / ld, i % ld)] = src[i];
+    const int64_t o = store_index(cblk, ld, 4, i / ld, i % ld);
+    if (o >= 0) dst[o] = src[i];
 }
 
 // Per-row power-of-two scale so that the row maximum maps to [2^13, 2^14),
 // then fp16 hi + lo of the scaled row in the blocked product order.  One
 // block per row.
-__global__ __launch_bounds__(256) void k_split_fp16_rows(int64_t ld, const float* __restrict__ src,
+__global__ __launch_bounds__(256) void k_split_fp16_rows(int64_t ld, bool cblk, const float* __restrict__ src,
                                                          __half* __restrict__ hi,
                                                          __half* __restrict__ lo,
                                                          float* __restrict__ rscale) {
@@ -189,11 +197,14 @@ __global__ __launch_bounds__(256) void k_split_fp16_rows(int64_t ld, const float
     if (mx > 0.0f) frexpf(mx, &e);  // mx = f * 2^e, f in [0.5, 1)
     const int sh = 14 - e;          // mx * 2^sh in [2^13, 2^14)
     const float scale = ldexpf(1.0f, sh);
-    if (threadIdx.x == 0) rscale[row] = ldexpf(1.0f, -sh);
+    // the scale belongs to the product's row: component order in the
+    // component-blocked form
+    if (threadIdx.x == 0) rscale[cblk ? (row % 3) * (ld / 3) + row / 3 : row] = ldexpf(1.0f, -sh);
     for (int64_t c = threadIdx.x; c < ld; c += blockDim.x) {
+        const int64_t o = store_index(cblk, ld, 8, row, c);
+        if (o < 0) continue;
         const float v = r[c] * scale;
         const __half h = __float2half(v);
-        const int64_t o = dense9_index(ld, 8, row, c);
         hi[o] = h;
         lo[o] = __float2half(v - __half2float(h));
     }
@@ -256,11 +267,12 @@ namespace {
 
 // Rows [r0, r0 + nrow) of a blocked DENSE9 array back in row-major order.
 template <typename E>
-__global__ __launch_bounds__(256) void k_gather_dense9(int64_t ld, int vec, int64_t r0, int64_t nrow,
+__global__ __launch_bounds__(256) void k_gather_dense9(int64_t ld, bool cblk, int vec, int64_t r0, int64_t nrow,
                                                        const E* __restrict__ src, E* __restrict__ dst) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= nrow * ld) return;
-    dst[i] = src[dense9_index(ld, vec, r0 + i / ld, i % ld)];
+    const int64_t o = store_index(cblk, ld, vec, r0 + i / ld, i % ld);
+    dst[i] = o >= 0 ? src[o] : E(0);
 }
 
 }  // namespace
@@ -277,10 +289,10 @@ tm_status dense9_rows_rowmajor(const Tensor* T, const void* src, int64_t r0, int
     TM_TRY_HIP(hipMalloc(&d, count * esz));
     const unsigned g = static_cast<unsigned>((count + 255) / 256);
     if (esz == 4)
-        k_gather_dense9<float><<<g, 256>>>(T->ld, vec, r0, nrow, static_cast<const float*>(src),
+        k_gather_dense9<float><<<g, 256>>>(T->ld, T->cblk, vec, r0, nrow, static_cast<const float*>(src),
                                            static_cast<float*>(d));
     else
-        k_gather_dense9<uint16_t><<<g, 256>>>(T->ld, vec, r0, nrow, static_cast<const uint16_t*>(src),
+        k_gather_dense9<uint16_t><<<g, 256>>>(T->ld, T->cblk, vec, r0, nrow, static_cast<const uint16_t*>(src),
                                               static_cast<uint16_t*>(d));
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpy(host, d, count * esz, hipMemcpyDeviceToHost);
@@ -327,16 +339,16 @@ tm_status assemble_device(Tensor* T, const double* d_centers, const double* d_si
     TM_TRY_HIP(hipGetLastError());
     if (T->prec == TM_PREC_FP32) {
         const unsigned g = static_cast<unsigned>((count + 255) / 256);
-        k_block_fp32<<<g, block, 0, s>>>(T->rows, T->ld, tmp, static_cast<float*>(T->data));
+        k_block_fp32<<<g, block, 0, s>>>(T->rows, T->ld, T->cblk, tmp, static_cast<float*>(T->data));
         TM_TRY_HIP(hipGetLastError());
     } else if (T->prec == TM_PREC_BF16X3) {
         const unsigned g = static_cast<unsigned>((count + 255) / 256);
-        k_split_bf16<<<g, block, 0, s>>>(T->rows, T->ld, tmp, static_cast<__hip_bfloat16*>(T->data),
+        k_split_bf16<<<g, block, 0, s>>>(T->rows, T->ld, T->cblk, tmp, static_cast<__hip_bfloat16*>(T->data),
                                          static_cast<__hip_bfloat16*>(T->lo));
         TM_TRY_HIP(hipGetLastError());
     } else if (T->prec == TM_PREC_FP16X3) {
         k_split_fp16_rows<<<static_cast<unsigned>(T->rows), block, 0, s>>>(
-            T->ld, tmp, static_cast<__half*>(T->data), static_cast<__half*>(T->lo), T->rscale);
+            T->ld, T->cblk, tmp, static_cast<__half*>(T->data), static_cast<__half*>(T->lo), T->rscale);
         TM_TRY_HIP(hipGetLastError());
     }
     if (tmp) TM_TRY_HIP(hipFreeAsync(tmp, s));

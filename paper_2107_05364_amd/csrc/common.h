@@ -57,18 +57,40 @@ inline int64_t padded_tiles(int64_t n) { return round_up(n, 128); }
 //     16 ks + 8 q + e at (((w * 4 + ks) * 64 + 32 q + i) * 8 + e.
 constexpr int kGemmRows = 128;
 constexpr int kGemmKC = 64;
-__host__ __device__ inline int64_t dense9_index(int64_t ld, int vec, int64_t r, int64_t k) {
-    const int64_t rb = r / kGemmRows, kc = k / kGemmKC;
-    const int rr = static_cast<int>(r % kGemmRows), kk = static_cast<int>(k % kGemmKC);
-    const int64_t base = (rb * (ld / kGemmKC) + kc) * (kGemmRows * kGemmKC);
+// Place of element (rr, kk) inside its 128 x 64 block.
+__host__ __device__ inline int64_t dense9_in_block(int vec, int rr, int kk) {
     const int w = rr / 32;
     if (vec == 8) {
         const int i = rr % 32, ks = kk / 16, q = (kk % 16) / 8, e = kk % 8;
-        return base + (((w * 4 + ks) * 64 + 32 * q + i) * 8 + e);
+        return ((w * 4 + ks) * 64 + 32 * q + i) * 8 + e;
     }
     const int rt = (rr % 32) / 16, j = rr % 16;
     const int sub = kk / 16, g = (kk % 16) / 4, e = kk % 4;
-    return base + ((((w * 4 + sub) * 2 + rt) * 64 + 16 * g + j) * 4 + e);
+    return (((w * 4 + sub) * 2 + rt) * 64 + 16 * g + j) * 4 + e;
+}
+__host__ __device__ inline int64_t dense9_index(int64_t ld, int vec, int64_t r, int64_t k) {
+    const int64_t rb = r / kGemmRows, kc = k / kGemmKC;
+    const int64_t base = (rb * (ld / kGemmKC) + kc) * (kGemmRows * kGemmKC);
+    return base + dense9_in_block(vec, static_cast<int>(r % kGemmRows), static_cast<int>(k % kGemmKC));
+}
+// Component-blocked DENSE9 of a single layer of tiles (xz = yz = 0 in every
+// block): rows and columns ordered by component, r' = i np + a and
+// k' = j np + b for the tile-order element (3a + i, 3b + j).  The operator is
+// then [[Nxx, Nxy, 0], [Nxy, Nyy, 0], [0, 0, Nzz]] in np x np blocks: the x
+// and y rows (row blocks below 2np) are stored over the x and y columns
+// (K in [0, 2np)), the z rows over the z columns (K in [2np, 3np)); the two
+// zero parts are not stored (-1).  Blocks of 128 x 64 as dense9_index, the
+// x/y rows first (2np / 64 chunks per row block), then the z rows (np / 64).
+__host__ __device__ inline int64_t dense9c_index(int64_t np, int vec, int64_t r, int64_t k) {
+    const int64_t a = r / 3, b = k / 3;
+    const int i = static_cast<int>(r % 3), j = static_cast<int>(k % 3);
+    if ((i < 2) != (j < 2)) return -1;
+    const int64_t rp = i * np + a, kp = j * np + b;
+    const int64_t rb = rp / kGemmRows, rb2 = 2 * np / kGemmRows;
+    const int64_t kc = kp / kGemmKC, kc2 = 2 * np / kGemmKC;
+    const int64_t blk = rb < rb2 ? rb * kc2 + kc : rb2 * kc2 + (rb - rb2) * (np / kGemmKC) + (kc - kc2);
+    return blk * (kGemmRows * kGemmKC) +
+           dense9_in_block(vec, static_cast<int>(rp % kGemmRows), static_cast<int>(kp % kGemmKC));
 }
 
 struct Tensor;
@@ -115,6 +137,7 @@ struct Tensor {
     int64_t ld = 0;       // row stride in elements
     int64_t plane = 0;    // SYM6: stride between component planes in elements
     int64_t rows = 0;     // DENSE9: allocated rows (>= 3n)
+    bool cblk = false;    // DENSE9 (FP32 / split): component-blocked single layer (dense9c_index)
     void* data = nullptr; // fp32 / fp64 entries, or the hi part
     void* lo = nullptr;   // lo part of split precisions
     float* rscale = nullptr; // FP16X3: per-row 1/scale (power of two)

@@ -58,7 +58,32 @@ struct GemmArgs {
     float* part;        // [splits][bpad][rows]
     int64_t rows;       // padded operator rows (multiple of 128)
     int64_t kper;       // K elements per split (multiple of KC)
+    int64_t np;         // padded tiles (component extent of the component-blocked form)
+    int32_t cblk;       // component-blocked single layer (dense9c_index)
 };
+
+// K range [k0, k1) of row block rb and the element offset of its first stored
+// block: every K for the dense form; for the component-blocked form the x/y
+// columns for the x/y rows and the z columns for the z rows.
+__device__ inline void row_block_k(const GemmArgs& G, int64_t rb, int64_t* k0, int64_t* k1, int64_t* base) {
+    constexpr int64_t BE = kBlockElems;
+    if (!G.cblk) {
+        *k0 = 0;
+        *k1 = G.ld;
+        *base = rb * (G.ld / KC) * BE;
+        return;
+    }
+    const int64_t rb2 = 2 * G.np / kGemmRows, kc2 = 2 * G.np / KC;
+    if (rb < rb2) {
+        *k0 = 0;
+        *k1 = 2 * G.np;
+        *base = rb * kc2 * BE;
+    } else {
+        *k0 = 2 * G.np;
+        *k1 = 3 * G.np;
+        *base = (rb2 * kc2 + (rb - rb2) * (G.np / KC)) * BE;
+    }
+}
 
 template <int PREC>
 struct Elt;
@@ -106,13 +131,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, j = lane & 15;
     const int64_t rowbase = static_cast<int64_t>(blockIdx.x) * kGemmRows + wave * 32;
-    const int64_t kb = static_cast<int64_t>(blockIdx.y) * G.kper;
-    const int64_t ke = min(kb + G.kper, G.ld);
-    const int nch = static_cast<int>((ke - kb) / KC);
-    const int64_t kc0 = kb / KC;
+    int64_t kfirst, klast, rbase;
+    row_block_k(G, blockIdx.x, &kfirst, &klast, &rbase);
+    const int64_t kb = kfirst + static_cast<int64_t>(blockIdx.y) * G.kper;
+    const int64_t ke = min(kb + G.kper, klast);
+    // a split past the row block's K range adds nothing: it writes zero partials
+    const int nch = ke > kb ? static_cast<int>((ke - kb) / KC) : 0;
+    const int64_t kc0 = (nch > 0 ? kb : kfirst) / KC;
 
     // this workgroup's first operator block and this lane's place in a block
-    const int64_t ablk = (static_cast<int64_t>(blockIdx.x) * (G.ld / KC) + kc0) * kBlockElems;
+    const int64_t ablk = rbase + (kc0 - kfirst / KC) * kBlockElems;
     const T* Ah = static_cast<const T*>(G.Ahi) + ablk;
     const T* Al = SPLIT ? static_cast<const T*>(G.Alo) + ablk : nullptr;
     const unsigned char* Xh = static_cast<const unsigned char*>(G.Xhi) + kc0 * XB;
@@ -268,12 +296,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t rowbase = static_cast<int64_t>(blockIdx.x) * kGemmRows + wave * 32;
-    const int64_t kb = static_cast<int64_t>(blockIdx.y) * G.kper;
-    const int64_t ke = min(kb + G.kper, G.ld);
-    const int nch = static_cast<int>((ke - kb) / KC);
-    const int64_t kc0 = kb / KC;
+    int64_t kfirst, klast, rbase;
+    row_block_k(G, blockIdx.x, &kfirst, &klast, &rbase);
+    const int64_t kb = kfirst + static_cast<int64_t>(blockIdx.y) * G.kper;
+    const int64_t ke = min(kb + G.kper, klast);
+    // a split past the row block's K range adds nothing: it writes zero partials
+    const int nch = ke > kb ? static_cast<int>((ke - kb) / KC) : 0;
+    const int64_t kc0 = (nch > 0 ? kb : kfirst) / KC;
 
-    const int64_t ablk = (static_cast<int64_t>(blockIdx.x) * (G.ld / KC) + kc0) * kBlockElems;
+    const int64_t ablk = rbase + (kc0 - kfirst / KC) * kBlockElems;
     const T* Ah = static_cast<const T*>(G.Ahi) + ablk;
     const T* Al = static_cast<const T*>(G.Alo) + ablk;
     const unsigned char* Xh = static_cast<const unsigned char*>(G.Xhi) + kc0 * XB;
@@ -408,10 +439,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 //   split forms (32-state tiles, nt = ns / 32): state 32 st + i, column
 //     kc KC + 16 ks + 8 q + e at ((ks nt + st) 64 + 32 q + i) 8 + e;
 // states B .. ns - 1 are zero.  One thread per output element.
+// With the component-blocked operator, K is in component order as well:
+// column k holds component k / np of tile k % np.
 template <int PREC>
-__global__ __launch_bounds__(256) void k_prep(int64_t B, int64_t ns, int64_t ld, int32_t n, const float* __restrict__ Y,
-                                              const float* __restrict__ Ms, float inv_ref,
-                                              void* __restrict__ xh, void* __restrict__ xl) {
+__global__ __launch_bounds__(256) void k_prep(int64_t B, int64_t ns, int64_t ld, int32_t n, bool cblk,
+                                              const float* __restrict__ Y, const float* __restrict__ Ms,
+                                              float inv_ref, void* __restrict__ xh, void* __restrict__ xl) {
     constexpr int VEC = Elt<PREC>::kVec;
     constexpr int TW = PREC == 0 ? 16 : 32;  // states per tile
     const int64_t nt = ns / TW;
@@ -432,8 +465,10 @@ __global__ __launch_bounds__(256) void k_prep(int64_t B, int64_t ns, int64_t ld,
         s = 32 * st + (ln & 31);
         k = kc * KC + 16 * sub + 8 * (ln >> 5) + e;
     }
-    const int64_t b = k / 3;
-    const float v = (s < B && b < n) ? Y[s * ld + k] * (Ms[b] * inv_ref) : 0.0f;
+    const int64_t np = ld / 3;
+    const int64_t b = cblk ? k % np : k / 3;
+    const int64_t y = cblk ? 3 * b + k / np : k;  // the element of the tile-order state
+    const float v = (s < B && b < n) ? Y[s * ld + y] * (Ms[b] * inv_ref) : 0.0f;
     if constexpr (PREC == 0) {
         static_cast<float*>(xh)[i] = v;
     } else if constexpr (PREC == 1) {
@@ -448,19 +483,23 @@ __global__ __launch_bounds__(256) void k_prep(int64_t B, int64_t ns, int64_t ld,
 }
 
 // Sum of the split-K partials in fixed order, then the per-tile finish.
+// Rows are in component order for the component-blocked operator (row
+// i np + a holds component i of tile a), else in tile order (3 a + i).
 template <Epi MODE>
 __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __restrict__ part,
-                                                int64_t splits, int64_t bpad, int64_t rows,
+                                                int64_t splits, int64_t bpad, int64_t rows, bool cblk,
                                                 float scale, const float* __restrict__ X, int64_t sx,
                                                 EpiArgs E) {
     const int s = blockIdx.y;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     double rmax = 0.0, dmax = 0.0;
     if (a < P.n) {
+        const int64_t r0 = cblk ? a : 3 * static_cast<int64_t>(a);
+        const int64_t rs = cblk ? P.np : 1;  // row stride between the components
         float h0 = 0.f, h1 = 0.f, h2 = 0.f;
         for (int64_t sp = 0; sp < splits; ++sp) {
-            const float* pp = part + (sp * bpad + s) * rows + 3 * static_cast<int64_t>(a);
-            h0 += pp[0]; h1 += pp[1]; h2 += pp[2];
+            const float* pp = part + (sp * bpad + s) * rows + r0;
+            h0 += pp[0]; h1 += pp[rs]; h2 += pp[2 * rs];
         }
         finish_tile<MODE>(P, X, sx, E, s, a, -scale * h0, -scale * h1, -scale * h2, &rmax, &dmax);
     }
@@ -564,11 +603,11 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
         const float inv = static_cast<float>(1.0 / p->ms_ref);
         const int32_t n32 = static_cast<int32_t>(p->n);
         if (prec == 0)
-            k_prep<0><<<grid, 256, 0, s>>>(B, ns, ld, n32, X, p->Ms, inv, w->xh, nullptr);
+            k_prep<0><<<grid, 256, 0, s>>>(B, ns, ld, n32, T->cblk, X, p->Ms, inv, w->xh, nullptr);
         else if (prec == 1)
-            k_prep<1><<<grid, 256, 0, s>>>(B, ns, ld, n32, X, p->Ms, inv, w->xh, w->xl);
+            k_prep<1><<<grid, 256, 0, s>>>(B, ns, ld, n32, T->cblk, X, p->Ms, inv, w->xh, w->xl);
         else
-            k_prep<2><<<grid, 256, 0, s>>>(B, ns, ld, n32, X, p->Ms, inv, w->xh, w->xl);
+            k_prep<2><<<grid, 256, 0, s>>>(B, ns, ld, n32, T->cblk, X, p->Ms, inv, w->xh, w->xl);
         TM_TRY_HIP(hipGetLastError());
     }
     GemmArgs G;
@@ -581,11 +620,15 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     G.Xlo = w->xl;
     G.part = w->part;
     G.rows = T->rows;
+    G.np = ld / 3;
+    G.cblk = T->cblk ? 1 : 0;
     const int64_t splits = gemm_splits(p);
     TM_REQUIRE(splits <= w->part_splits, TM_EINVAL, "batched product: workspace holds %lld K splits, %lld asked",
                static_cast<long long>(w->part_splits), static_cast<long long>(splits));
-    G.kper = round_up((ld + splits - 1) / splits, KC);
-    const int64_t used_splits = (ld + G.kper - 1) / G.kper;
+    // K per split from the longest row K range (all of K, or the x/y columns)
+    const int64_t kext = T->cblk ? 2 * G.np : ld;
+    G.kper = round_up((kext + splits - 1) / splits, KC);
+    const int64_t used_splits = (kext + G.kper - 1) / G.kper;
     const int64_t rowblocks = T->rows / kGemmRows;
     tm_status st = prec == 0   ? launch_gemm_p<0>(static_cast<int>(ns / 16), G, rowblocks, used_splits, s)
                    : prec == 1 ? launch_gemm_split<1>(static_cast<int>(ns / 32), G, rowblocks, used_splits, s)
@@ -597,12 +640,12 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     const dim3 grid(static_cast<unsigned>((p->n + 255) / 256), static_cast<unsigned>(B));
     const int64_t sx = 3 * p->np;
     switch (mode) {
-        case Epi::HD: k_finish<Epi::HD><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, scale, X, sx, e); break;
-        case Epi::HEFF: k_finish<Epi::HEFF><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, scale, X, sx, e); break;
-        case Epi::DMDT: k_finish<Epi::DMDT><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, scale, X, sx, e); break;
-        case Epi::STAGE: k_finish<Epi::STAGE><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, scale, X, sx, e); break;
-        case Epi::RK4_FINAL: k_finish<Epi::RK4_FINAL><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, scale, X, sx, e); break;
-        case Epi::DP_LAST: k_finish<Epi::DP_LAST><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, scale, X, sx, e); break;
+        case Epi::HD: k_finish<Epi::HD><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
+        case Epi::HEFF: k_finish<Epi::HEFF><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
+        case Epi::DMDT: k_finish<Epi::DMDT><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
+        case Epi::STAGE: k_finish<Epi::STAGE><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
+        case Epi::RK4_FINAL: k_finish<Epi::RK4_FINAL><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
+        case Epi::DP_LAST: k_finish<Epi::DP_LAST><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
     }
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;

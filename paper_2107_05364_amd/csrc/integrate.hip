@@ -545,7 +545,7 @@ extern "C" tm_status tm_profile_field_mode(tm_problem* pp, int64_t B, int32_t mo
         // stored tile pairs) + states in and out
         const Tensor* T = p->T;
         const int64_t op = (T->layout == TM_LAYOUT_BSR6 || is_psym(T->layout)) ? T->bytes - (T->pairs ? T->npairs * 8 : 0)
-                           : T->layout == TM_LAYOUT_DENSE9 ? 36 * p->n * p->n
+                           : T->layout == TM_LAYOUT_DENSE9 ? (T->cblk ? 20 : 36) * p->n * p->n
                                                            : 24 * p->n * p->n;
         *bytes_out = op + 24 * p->n * B;
     }

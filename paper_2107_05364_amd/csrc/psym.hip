@@ -55,15 +55,15 @@ inline int64_t pair_index(int64_t I, int64_t J, int64_t nt) {
     return I == J ? I : nt + I * (nt - 1) - I * (I - 1) / 2 + (J - I - 1);
 }
 
-// One workgroup per tile pair and group of states: it reads its tile once
-// and applies it to states s = blockIdx.y, blockIdx.y + gridDim.y, ... (one
-// state per workgroup when the grid has B rows; every state of the batch
-// when it has one, so that a batch streams the operator once).  Thread t
-// takes column b = t % TS of the tile and rows rg RPT .. rg RPT + RPT - 1
-// (rg = t / TS): each row's components are coalesced loads; per state the
-// row sums go through LDS to a sum over the TS columns, the column sums
-// through LDS to a sum over the RG groups (both in a fixed order, the same
-// for every grid shape: results do not depend on the batch).
+// One workgroup per tile pair and state (MULTI = false: the grid has B rows)
+// or per tile pair and group of states (MULTI = true: states s = blockIdx.y,
+// blockIdx.y + gridDim.y, ..., so that a batch streams each tile once per
+// group).  The workgroup reads its tile once and applies it to its states.
+// Thread t takes column b = t % TS of the tile and rows rg RPT .. rg RPT +
+// RPT - 1 (rg = t / TS): each row's components are coalesced loads; per
+// state the row sums go through LDS to a sum over the TS columns, the column
+// sums through LDS to a sum over the RG groups (both in a fixed order, the
+// same for either grid: results do not depend on the batch).
 //
 // LOCALF: the workgroups of diagonal pairs (I == J) also evaluate the local
 // field terms (exchange, anisotropy, applied field) of their TS tiles --
@@ -74,7 +74,7 @@ inline int64_t pair_index(int64_t I, int64_t J, int64_t nt) {
 // left.
 // NP = 6: planes (xx, xy, xz, yy, yz, zz); NP = 4 (a single layer): (xx, xy,
 // yy, zz), with xz = yz = 0.
-template <bool STEPPING, bool LOCALF, bool NTL, int NP>
+template <bool STEPPING, bool LOCALF, bool NTL, int NP, bool MULTI>
 __global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const float* __restrict__ tiles,
                                                     const int32_t* __restrict__ pairs, int64_t nt,
                                                     const float* __restrict__ Ms, const float* __restrict__ X,
@@ -88,7 +88,11 @@ __global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const
     // workgroup whose states are all frozen stops before loading its tile
     if (STEPPING) {
         bool live = false;
-        for (int64_t s = blockIdx.y; s < B && !live; s += gridDim.y) live = h[s] != 0.0;
+        if constexpr (MULTI) {
+            for (int64_t s = blockIdx.y; s < B && !live; s += gridDim.y) live = h[s] != 0.0;
+        } else {
+            live = h[blockIdx.y] != 0.0;
+        }
         if (!live) return;
     }
     const float* tile = tiles + p * NP * TB;
@@ -103,11 +107,8 @@ __global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const
     __shared__ float hl[TS][3];            // local field terms (diagonal pairs)
     const int64_t bg = TS * J + b;
     const float msb = Ms[bg];
-    bool first = true;
-    for (int64_t s = blockIdx.y; s < B; s += gridDim.y) {
-        if (STEPPING && h[s] == 0.0) continue;
-        if (!first) __syncthreads();  // the previous state's sums have been read
-        first = false;
+    // the products of state s with the tile in registers (slots of s written)
+    auto one_state = [&](int64_t s) {
         const float* x = X + s * sx;
         if (LOCALF && I == J && t < TS) {
             const int64_t a = TS * I + t;
@@ -155,6 +156,17 @@ __global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const
                 part[((s * nt + J) * nt + I) * (3 * TS) + t] = cs;
             }
         }
+    };
+    if constexpr (MULTI) {
+        bool first = true;
+        for (int64_t s = blockIdx.y; s < B; s += gridDim.y) {
+            if (STEPPING && h[s] == 0.0) continue;
+            if (!first) __syncthreads();  // the previous state's sums have been read
+            first = false;
+            one_state(s);
+        }
+    } else {
+        one_state(blockIdx.y);
     }
 }
 
@@ -169,12 +181,23 @@ template <bool STEPPING, bool LOCALF, int NP>
 inline void launch_tiles_np(dim3 grid, hipStream_t st, bool nt_loads, const DevProblem& P, const float* tiles,
                             const int32_t* pairs, int64_t nt, const float* Ms, const float* X, int64_t sx,
                             const double* h, const float* Ha, float* part, int64_t B) {
-    if (nt_loads)
-        launch_op(k_psym_tiles<STEPPING, LOCALF, true, NP>, grid, dim3(kTileThreads), st, P, tiles, pairs, nt, Ms, X,
-                  sx, h, Ha, part, B);
-    else
-        launch_op(k_psym_tiles<STEPPING, LOCALF, false, NP>, grid, dim3(kTileThreads), st, P, tiles, pairs, nt, Ms,
-                  X, sx, h, Ha, part, B);
+    // one state per workgroup when the grid has a row per state
+    const bool multi = grid.y < B;
+    if (nt_loads) {
+        if (multi)
+            launch_op(k_psym_tiles<STEPPING, LOCALF, true, NP, true>, grid, dim3(kTileThreads), st, P, tiles, pairs,
+                      nt, Ms, X, sx, h, Ha, part, B);
+        else
+            launch_op(k_psym_tiles<STEPPING, LOCALF, true, NP, false>, grid, dim3(kTileThreads), st, P, tiles, pairs,
+                      nt, Ms, X, sx, h, Ha, part, B);
+    } else {
+        if (multi)
+            launch_op(k_psym_tiles<STEPPING, LOCALF, false, NP, true>, grid, dim3(kTileThreads), st, P, tiles,
+                      pairs, nt, Ms, X, sx, h, Ha, part, B);
+        else
+            launch_op(k_psym_tiles<STEPPING, LOCALF, false, NP, false>, grid, dim3(kTileThreads), st, P, tiles,
+                      pairs, nt, Ms, X, sx, h, Ha, part, B);
+    }
 }
 
 // Grid of the tile pass for B states: one workgroup per tile pair and group
