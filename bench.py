@@ -26,6 +26,8 @@ import time
 
 import numpy as np
 
+_T_START = time.perf_counter()
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -61,6 +63,8 @@ def parse():
                     help="requests of the serving stream (the full stream has 200)")
     ap.add_argument("--serving-nmax", type=int, default=20000,
                     help="largest tile count of the serving stream (log-uniform from 500)")
+    ap.add_argument("--serving-max-active", type=int, default=3,
+                    help="groups the server advances per round, oldest first (0: all)")
     ap.add_argument("--layout", choices=["psym4", "psym6", "sym6"], default="psym4",
                     help="operator layout of the headline run: pair-symmetric with four planes "
                          "(the film is one layer of identical tiles), pair-symmetric with six "
@@ -89,6 +93,12 @@ def kernel_source_hash(layout):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def progress(section):
+    """One line per benchmark section on stderr (stdout carries only the
+    result line), so that a long default run shows it is alive."""
+    print("bench: %s (%.0f s)" % (section, time.perf_counter() - _T_START), file=sys.stderr, flush=True)
 
 
 def _same_pass(a, b):
@@ -851,6 +861,7 @@ def main():
                      "field_evaluation_us": round(eval_ms * 1e3, 3)},
     }
     if stored_bytes < (256 << 20) and not args.no_cache_free:
+        progress("cache-free roofline (N = 6400 film)")
         rec["roofline"]["cache_free"] = cache_free_section(tmg, W, torch, args.layout)
     p.close()
     T.close()
@@ -858,27 +869,38 @@ def main():
     ctx.close()
     batched_data = None
     if not args.no_batched:
+        progress("batched product (B = 128)")
         bat, batched_data = batched_section(tmg, W, torch)
         best = max(v["state_steps_per_s"] for k, v in bat.items() if isinstance(v, dict))
         bat["vs_single_fp32_solve"] = round(best / rec["value"], 2)
         rec["batched"] = bat
     if not args.no_large:
+        progress("refined slab N = 20000")
         rec["large"] = large_section(tmg, W, torch, with_oracle=not args.no_cpu_baseline)
     if not args.no_cube:
+        progress("cube RK4")
         rec["cube"] = cube_section(tmg, W, torch, with_oracle=not args.no_cpu_baseline)
     if not args.no_sweep:
+        progress("SP4 sweep")
         rec["sp4_sweep"] = sp4_sweep_section(tmg, W, torch)
     if not args.no_sp4_dynamics:
+        progress("SP4 dynamics")
         rec["sp4_dynamics"] = sp4_dynamics_section(tmg, W, torch)
     if not args.no_threshold:
+        progress("thresholding")
         rec["threshold"] = threshold_section(tmg, W, torch)
     if not args.no_sp3:
+        progress("standard problem 3")
         rec["sp3"] = sp3_section(tmg, W, torch)
     if not args.no_serving:
-        rec["serving"] = serving_section(tmg, W, torch, count=args.serving_count, n_max=args.serving_nmax)
+        progress("serving")
+        rec["serving"] = serving_section(tmg, W, torch, count=args.serving_count, n_max=args.serving_nmax,
+                                         max_active=args.serving_max_active)
     if not args.no_peaks:
+        progress("achievable peaks")
         rec["achievable_peaks"] = peaks_section(torch, tmg)
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle)")
         base, errs = cpu_baseline(wl, args.cpu_steps, m_final, hd_final, batched_data)
         rec["cpu_baseline"] = base
         rec["error_vs_oracle"] = dict(quantity="H_d of the timed run's final state against the FP64 oracle",
