@@ -102,12 +102,17 @@ def progress(section):
 
 
 def _same_pass(a, b):
-    """The pair-symmetric tile pass reads the same bytes with cached or with
-    nontemporal operator loads (the autotuner picks either): its two load
-    variants count as one kernel here."""
+    """The pair-symmetric tile pass reads the same operator bytes with cached
+    or with nontemporal operator loads (the autotuner picks either), and in
+    its stage-2 form that carries the previous attempt's commit: these
+    instances count as one kernel here."""
     import re
 
-    norm = lambda k: re.sub(r"^(k_psym_tiles<true,true,)(true|false)(,)", r"\1*\3", k.strip())
+    def norm(k):
+        k = re.sub(r"\s+", "", k.split("(")[0])
+        return re.sub(r"^k_psym_tiles<true,true,(true|false|\*),(\d),(true|false),(true|false|\*)>$",
+                      r"k_psym_tiles<true,true,*,\2,\3,*>", k)
+
     return norm(a) == norm(b)
 
 
@@ -817,9 +822,10 @@ def main():
         planes = 4 if args.layout == "psym4" else 6
         alg_bytes = n * (n + 1) // 2 * planes * 4 + 24 * n
         alg_basis = "N(N+1)/2 blocks x %d planes x 4 B + 24 N (state in, slots out not counted)" % planes
-        kname = "k_psym_tiles<true,true,%s,%d,false>" % ("true" if nt_loads else "false", planes)
-        kdesc = (" (pair-symmetric tile pass of the demag product; the slot sum and epilogue run in "
-                 "a second launch, included in field_evaluation_us)")
+        kname = "k_psym_tiles<true,true,%s,%d,false,*>" % ("true" if nt_loads else "false", planes)
+        kdesc = (" (pair-symmetric tile pass of the demag product, the last template argument true in "
+                 "the stage-2 pass that carries the previous attempt's commit; the slot sum and epilogue "
+                 "run in a second launch, included in field_evaluation_us)")
     else:
         alg_bytes = 24 * n * n + 24 * n
         alg_basis = "6 planes x N^2 x 4 B + 24 N"

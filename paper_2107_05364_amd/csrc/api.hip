@@ -77,9 +77,15 @@ Workspace::~Workspace() {
     if (host_flags) (void)hipHostFree(host_flags);
     if (host_steps) (void)hipHostFree(host_steps);
     if (host_stat) (void)hipHostFree(host_stat);
-    if (graph1) (void)hipGraphExecDestroy(graph1);
-    if (graphK) (void)hipGraphExecDestroy(graphK);
+    drop_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+}
+
+void Workspace::drop_graphs() {
+    for (hipGraphExec_t* g : {&graph1, &graphP[0], &graphP[1], &graphP[2], &graphK}) {
+        if (*g) (void)hipGraphExecDestroy(*g);
+        *g = nullptr;
+    }
 }
 
 }  // namespace tmag

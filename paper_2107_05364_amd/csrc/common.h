@@ -249,13 +249,17 @@ struct Workspace {
     int32_t* host_flags = nullptr;
     int64_t* host_steps = nullptr;
     int64_t* host_stat = nullptr;  // pinned mirror of stat
-    // captured step graphs: one attempt, and kGraphSteps attempts
+    // captured step graphs: one attempt, 2, 4 and 8 attempts, and kGraphSteps
+    // attempts (a run of c attempts replays at most one of each below
+    // kGraphSteps: each replay costs a few microseconds of its own)
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph1 = nullptr;
+    hipGraphExec_t graphP[3] = {nullptr, nullptr, nullptr};
     hipGraphExec_t graphK = nullptr;
     int graph_integ = -1;       // scheme, batch and renormalisation the graphs were captured for
     int64_t graph_B = -1;
     int graph_renorm = -1;
+    void drop_graphs();  // destroys the step graphs (they hold launch shapes and kernels)
     ~Workspace();
 };
 
@@ -263,7 +267,8 @@ tm_status ensure_workspace(Problem* p, int64_t B);
 // Device address of the fixed scratch buffer of tm_demag_noalloc on `device`,
 // looked up once per device (noalloc.hip); called by tm_init.
 tm_status noalloc_setup(int device);
-constexpr int kGraphSteps = 16;
+constexpr int kGraphSteps = 16;  // a power of two: the remainder of a run is replayed from the 1, 2, 4, 8 graphs
+static_assert(kGraphSteps == 16, "the step graphs cover remainders below 16 attempts");
 // A state's control snapshot: h, t and dt, then the step counts and the
 // flags as 64-bit integer bit patterns.
 enum SnapSlot : int { SN_H = 0, SN_T = 1, SN_DT = 2, SN_STEPS = 3, SN_REJ = 4, SN_FLAGS = 5 };

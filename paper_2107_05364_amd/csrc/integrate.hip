@@ -8,8 +8,8 @@
 // control kernel then decides acceptance and the next step per state, and
 // (DP45) a commit pass applies the accepted step, restores |m| = 1 and forms
 // the next attempt's first stage input.  Nothing returns to the host between
-// attempts; one attempt (or kGraphSteps of them) is captured in a hipGraph
-// and replayed.  States of a batch never couple: each has its own field,
+// attempts; runs of 1, 2, 4, 8 and kGraphSteps attempts are captured in
+// hipGraphs and a run of c attempts replays them by the binary digits of c.  States of a batch never couple: each has its own field,
 // time, step size and flags, and finished or failed states are frozen.
 #include <algorithm>
 #include <chrono>
@@ -263,12 +263,8 @@ extern "C" tm_status tm_run(tm_problem* pp, tm_integrator integ, int64_t B, floa
     // a graph holds B in its launch shapes: re-capture when B or the scheme changes
     const int renorm = cfg->renorm ? 1 : 0;
     if (w->graph1 && (w->graph_integ != static_cast<int>(integ) || w->graph_B != B ||
-                      w->graph_renorm != renorm)) {
-        (void)hipGraphExecDestroy(w->graph1);
-        w->graph1 = nullptr;
-        if (w->graphK) (void)hipGraphExecDestroy(w->graphK);
-        w->graphK = nullptr;
-    }
+                      w->graph_renorm != renorm))
+        w->drop_graphs();
     RunParams rp{};
     rp.v[RP_ATOL] = cfg->atol;
     rp.v[RP_RTOL] = cfg->rtol;
@@ -297,19 +293,26 @@ extern "C" tm_status tm_run(tm_problem* pp, tm_integrator integ, int64_t B, floa
         if (st != TM_OK) return st;
     }
     if (!persistent && cfg->use_graph && !w->graph1) {
-        st = capture(p, w, integ, B, renorm, 1, &w->graph1);
-        if (st != TM_OK) return st;
-        st = capture(p, w, integ, B, renorm, kGraphSteps, &w->graphK);
-        if (st != TM_OK) return st;
+        hipGraphExec_t* gs[5] = {&w->graph1, &w->graphP[0], &w->graphP[1], &w->graphP[2], &w->graphK};
+        const int counts[5] = {1, 2, 4, 8, kGraphSteps};
+        for (int i = 0; i < 5; ++i) {
+            st = capture(p, w, integ, B, renorm, counts[i], gs[i]);
+            if (st != TM_OK) {
+                w->drop_graphs();
+                return st;
+            }
+        }
         w->graph_integ = static_cast<int>(integ);
         w->graph_B = B;
         w->graph_renorm = renorm;
     }
     auto run_chunk = [&](int64_t cnt) -> tm_status {
         if (!cfg->use_graph) return enqueue_attempts(p, w, integ, B, renorm, static_cast<int>(cnt), s);
-        int64_t q = cnt / kGraphSteps, r = cnt % kGraphSteps;
+        const int64_t q = cnt / kGraphSteps, r = cnt % kGraphSteps;
         for (int64_t i = 0; i < q; ++i) TM_TRY_HIP(hipGraphLaunch(w->graphK, s));
-        for (int64_t i = 0; i < r; ++i) TM_TRY_HIP(hipGraphLaunch(w->graph1, s));
+        for (int b = 3; b >= 1; --b)
+            if (r & (1 << b)) TM_TRY_HIP(hipGraphLaunch(w->graphP[b - 1], s));
+        if (r & 1) TM_TRY_HIP(hipGraphLaunch(w->graph1, s));
         return TM_OK;
     };
     if (persistent) {
@@ -585,10 +588,7 @@ extern "C" tm_status tm_problem_set_shape(tm_problem* pp, int32_t shape) {
     Problem* p = reinterpret_cast<Problem*>(pp);
     TM_REQUIRE(p && shape >= -1 && shape < kNumShapes, TM_EINVAL, "tm_problem_set_shape: bad shape");
     if (p->shape != shape && p->ws) {
-        // captured graphs hold the old launch shape
-        if (p->ws->graph1) (void)hipGraphExecDestroy(p->ws->graph1);
-        if (p->ws->graphK) (void)hipGraphExecDestroy(p->ws->graphK);
-        p->ws->graph1 = p->ws->graphK = nullptr;
+        p->ws->drop_graphs();  // captured graphs hold the old launch shape
     }
     p->shape = shape;
     return TM_OK;
@@ -611,10 +611,7 @@ TuneKind tune_kind(const Problem* p) {
 }
 
 void drop_graphs(Problem* p) {
-    if (!p->ws) return;
-    if (p->ws->graph1) (void)hipGraphExecDestroy(p->ws->graph1);
-    if (p->ws->graphK) (void)hipGraphExecDestroy(p->ws->graphK);
-    p->ws->graph1 = p->ws->graphK = nullptr;
+    if (p->ws) p->ws->drop_graphs();
 }
 
 // Applies choice c of kind k to p (captured graphs hold the old kernels and

@@ -60,10 +60,12 @@ inline int64_t pair_index(int64_t I, int64_t J, int64_t nt) {
 // blockIdx.y + gridDim.y, ..., so that a batch streams each tile once per
 // group).  The workgroup reads its tile once and applies it to its states.
 // Thread t takes column b = t % TS of the tile and rows rg RPT .. rg RPT +
-// RPT - 1 (rg = t / TS): each row's components are coalesced loads; per
-// state the row sums go through LDS to a sum over the TS columns, the column
-// sums through LDS to a sum over the RG groups (both in a fixed order, the
-// same for either grid: results do not depend on the batch).
+// RPT - 1 (rg = t / TS): each row's components are coalesced loads.  Per
+// state the Ms-scaled inputs of the two tiles are staged in LDS (one
+// coalesced load per component), the row sums go through LDS to a sum over
+// the TS columns, the column sums through LDS to a sum over the RG groups
+// (both in a fixed order, the same for either grid: results do not depend on
+// the batch).
 //
 // LOCALF: the workgroups of diagonal pairs (I == J) also evaluate the local
 // field terms (exchange, anisotropy, applied field) of their TS tiles --
@@ -105,11 +107,17 @@ __global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const
     __shared__ float rred[TS][3][TS + 1];  // row sums before the column reduction
     __shared__ float cred[RG][TS][3];      // column sums per row group
     __shared__ float hl[TS][3];            // local field terms (diagonal pairs)
-    const int64_t bg = TS * J + b;
-    const float msb = Ms[bg];
+    __shared__ float xs[2][TS][3];         // Ms-scaled stage input of tile I (rows) and tile J (columns)
     // the products of state s with the tile in registers (slots of s written)
     auto one_state = [&](int64_t s) {
         const float* x = X + s * sx;
+        // the Ms-scaled inputs of the pair's 2 x TS tiles, staged once: one
+        // coalesced load per component instead of a load per thread and use
+        if (t < 6 * TS) {
+            const int half = t / (3 * TS), r = t % (3 * TS);
+            const int64_t q0 = TS * (half ? J : I);
+            xs[half][r / 3][r % 3] = x[3 * q0 + r] * Ms[q0 + r / 3];
+        }
         if (LOCALF && I == J && t < TS) {
             const int64_t a = TS * I + t;
             float H0 = 0.0f, H1 = 0.0f, H2 = 0.0f;
@@ -120,14 +128,13 @@ __global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const
             hl[t][1] = H1;
             hl[t][2] = H2;
         }
-        const float xb0 = x[3 * bg] * msb, xb1 = x[3 * bg + 1] * msb, xb2 = x[3 * bg + 2] * msb;
+        __syncthreads();
+        const float xb0 = xs[1][b][0], xb1 = xs[1][b][1], xb2 = xs[1][b][2];
         float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
             const int al = RPT * rg + i;
-            const int64_t ag = TS * I + al;
-            const float msa = Ms[ag];
-            const float xa0 = x[3 * ag] * msa, xa1 = x[3 * ag + 1] * msa, xa2 = x[3 * ag + 2] * msa;
+            const float xa0 = xs[0][al][0], xa1 = xs[0][al][1], xa2 = xs[0][al][2];
             const float v0 = v[i][0], v1 = v[i][1];
             const float v2 = NP == 6 ? v[i][2] : 0.0f, v3 = v[i][NP == 6 ? 3 : 2];
             const float v4 = NP == 6 ? v[i][4] : 0.0f, v5 = v[i][NP - 1];
