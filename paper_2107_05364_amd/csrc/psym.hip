@@ -40,8 +40,15 @@ constexpr int kTileThreads = 256;  // tile pass workgroup
 constexpr int RG = kTileThreads / TS;  // row groups of a workgroup (one column per lane)
 constexpr int RPT = TS / RG;       // rows per thread
 static_assert(TS * RG == kTileThreads && RPT * RG == TS, "tile size must divide the workgroup");
-constexpr int kFinishThreads = 1024;      // reduction + epilogue workgroup
-constexpr int FG = kFinishThreads / TS;   // slot groups of the reduction
+// reduction + epilogue workgroup: kFinishGroups groups of kFinishPos threads,
+// each thread adding kFinishLoads float4 of its group's slots per round
+constexpr int kFinishThreads = 256;
+constexpr int kFinishPos = 3 * TS / 4;   // float4 per slot
+constexpr int kFinishGroups = 10;
+constexpr int kFinishLoads = 8;
+static_assert(kFinishGroups * kFinishPos <= kFinishThreads && kFinishThreads >= 64 && 3 * TS % 4 == 0,
+              "finish workgroup shape");
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <bool NTL>
 __device__ inline float ldt(const float* p) {
@@ -230,86 +237,70 @@ inline void launch_tiles(const Tensor* T, bool nt_loads, int64_t B, hipStream_t 
 }
 
 // One workgroup per (target tile K, state): the nt slots of K are contiguous
-// ([nt][TS][3] floats); thread (g, q) = (t / TS, t % TS) adds the slots
-// j = g, g + FG, ... of tile q (independent coalesced loads, four in flight),
-// then the FG group sums are added in order g = 0 .. FG-1 and the first TS
-// lanes run the epilogue of their tile.
+// ([nt][TS][3] floats, kFinishPos float4 each).  Thread (g, pos) = (t /
+// kFinishPos, t % kFinishPos), g < kFinishGroups, adds float4 number pos of
+// the slots j = g, g + kFinishGroups, ... in ascending j, kFinishLoads
+// independent 16-byte loads per round (one round for nt <= 80; past the last
+// slot the load repeats it and the value is not added: no branches between
+// the loads); the group sums go through LDS and the first TS lanes of wave 0
+// add them in order g = 0 .. kFinishGroups - 1 per tile and run the epilogue.
+// The slots are requested before anything else (they depend only on K and
+// s), the epilogue's own inputs next; a frozen state then stops or skips.
 template <Epi MODE>
 __global__ __launch_bounds__(kFinishThreads) void k_psym_finish(DevProblem P, const float* __restrict__ part,
                                                                 int64_t nt, const float* X, int64_t sx, EpiArgs E) {
     constexpr bool STEPPING = MODE == Epi::STAGE || MODE == Epi::RK4_FINAL || MODE == Epi::DP_LAST;
+    constexpr int U = kFinishLoads, G = kFinishGroups;
     const int64_t K = blockIdx.x;
     const int s = blockIdx.y;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __shared__ float gs[FG][TS][3];
-    const int q = threadIdx.x % TS, grp = threadIdx.x / TS;
-    // Thread (grp, q) adds the slots j = grp, grp + FG, ... of tile q in
-    // ascending j, four independent loads per round (past the last slot the
-    // load repeats it and the value is not added: no branches between the
-    // loads).  The slots are requested before anything else (they depend
-    // only on K and s), the epilogue's own inputs next; a frozen state then
-    // stops or skips.
-    const float* src = part + (static_cast<int64_t>(s) * nt + K) * nt * (3 * TS) + 3 * q;
-    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-    int64_t j = grp;
-    const int64_t a = TS * K + lane;
-    EpiIn in;
-    bool mine = false, skip = false;
-    {
-        float v[4][3];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int pos = t % kFinishPos, g = t / kFinishPos;
+    const bool adds = g < G;
+    __shared__ f4 gs[G][kFinishPos];
+    const f4* src = reinterpret_cast<const f4*>(part + (static_cast<int64_t>(s) * nt + K) * nt * (3 * TS)) + pos;
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    int64_t j = g;
+    f4 v[U];
+    if (adds) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) v[u][c] = src[min(j + u * FG, nt - 1) * (3 * TS) + c];
-        const bool mine0 = wave == 0 && lane < TS && a < P.n;
-        EpiIn in0;
-        if (mine0) epi_load<MODE>(X, sx, E, s, static_cast<int>(a), in0);
-        bool frozen = false;
-        if constexpr (STEPPING) frozen = E.h[s] == 0.0;
-        if constexpr (MODE == Epi::STAGE || MODE == Epi::RK4_FINAL) {
-            if (frozen) return;
-        }
-        in = in0;
-        mine = mine0 && !frozen;
-        skip = frozen;
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (j + u * FG < nt) {
-                a0 += v[u][0];
-                a1 += v[u][1];
-                a2 += v[u][2];
-            }
-        j += 4 * FG;
+        for (int u = 0; u < U; ++u) v[u] = src[min(j + u * G, nt - 1) * kFinishPos];
     }
-    if (!skip) {
-        for (; j < nt; j += 4 * FG) {
-            float v[4][3];
+    const int64_t a = TS * K + lane;
+    const bool mine0 = wave == 0 && lane < TS && a < P.n;
+    EpiIn in;
+    if (mine0) epi_load<MODE>(X, sx, E, s, static_cast<int>(a), in);
+    bool frozen = false;
+    if constexpr (STEPPING) frozen = E.h[s] == 0.0;
+    if constexpr (MODE == Epi::STAGE || MODE == Epi::RK4_FINAL) {
+        if (frozen) return;
+    }
+    if (adds) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < U; ++u)
+            if (j + u * G < nt) acc += v[u];
+        j += U * G;
+        if (!frozen) {
+            for (; j < nt; j += U * G) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) v[u][c] = src[min(j + u * FG, nt - 1) * (3 * TS) + c];
+                for (int u = 0; u < U; ++u) v[u] = src[min(j + u * G, nt - 1) * kFinishPos];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (j + u * FG < nt) {
-                    a0 += v[u][0];
-                    a1 += v[u][1];
-                    a2 += v[u][2];
-                }
+                for (int u = 0; u < U; ++u)
+                    if (j + u * G < nt) acc += v[u];
+            }
         }
-        gs[grp][q][0] = a0;
-        gs[grp][q][1] = a1;
-        gs[grp][q][2] = a2;
+        gs[g][pos] = acc;
     }
     __syncthreads();
     if (wave != 0) return;
     double rmax = 0.0, dmax = 0.0;
-    if (mine) {
+    if (mine0 && !frozen) {
+        const float* gf = reinterpret_cast<const float*>(&gs[0][0]);
         float hx = 0.0f, hy = 0.0f, hz = 0.0f;
 #pragma unroll
-        for (int g2 = 0; g2 < FG; ++g2) {
-            hx += gs[g2][lane][0];
-            hy += gs[g2][lane][1];
-            hz += gs[g2][lane][2];
+        for (int g2 = 0; g2 < G; ++g2) {
+            hx += gf[g2 * 3 * TS + 3 * lane];
+            hy += gf[g2 * 3 * TS + 3 * lane + 1];
+            hz += gf[g2 * 3 * TS + 3 * lane + 2];
         }
         epi_compute<MODE>(P, sx, E, s, static_cast<int>(a), in, -hx, -hy, -hz, &rmax, &dmax);
     }
