@@ -60,7 +60,27 @@ struct GemmArgs {
     int64_t kper;       // K elements per split (multiple of KC)
     int64_t np;         // padded tiles (component extent of the component-blocked form)
     int32_t cblk;       // component-blocked single layer (dense9c_index)
+    // work items: the first rb2 row blocks take splits_xy K splits, the
+    // others (the z rows of the component-blocked form) splits_z
+    int64_t rowblocks, rb2, splits_xy, splits_z;
 };
+
+// Row block rb and K split sp of workgroup bid (a 1-D grid): the row blocks
+// of split 0, then of split 1, ..., first for the row blocks with the full K
+// range, then for the z row blocks of the component-blocked form, whose
+// shorter K range needs fewer splits of the same length: no workgroup
+// idles.
+__device__ inline void gemm_item(const GemmArgs& G, int64_t bid, int64_t* rb, int64_t* sp) {
+    const int64_t nxy = G.rb2 * G.splits_xy;
+    if (bid < nxy) {
+        *rb = bid % G.rb2;
+        *sp = bid / G.rb2;
+    } else {
+        const int64_t z = bid - nxy, nz = G.rowblocks - G.rb2;
+        *rb = G.rb2 + z % nz;
+        *sp = z / nz;
+    }
+}
 
 // K range [k0, k1) of row block rb and the element offset of its first stored
 // block: every K for the dense form; for the component-blocked form the x/y
@@ -130,10 +150,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, j = lane & 15;
-    const int64_t rowbase = static_cast<int64_t>(blockIdx.x) * kGemmRows + wave * 32;
+    int64_t rb, sp;
+    gemm_item(G, blockIdx.x, &rb, &sp);
+    const int64_t rowbase = rb * kGemmRows + wave * 32;
     int64_t kfirst, klast, rbase;
-    row_block_k(G, blockIdx.x, &kfirst, &klast, &rbase);
-    const int64_t kb = kfirst + static_cast<int64_t>(blockIdx.y) * G.kper;
+    row_block_k(G, rb, &kfirst, &klast, &rbase);
+    const int64_t kb = kfirst + sp * G.kper;
     const int64_t ke = min(kb + G.kper, klast);
     // a split past the row block's K range adds nothing: it writes zero partials
     const int nch = ke > kb ? static_cast<int>((ke - kb) / KC) : 0;
@@ -257,7 +279,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         if (c + 1 < nch) step(S1{}, c + 1);
     }
     // D[4 g + r][j] of tile (rt, st) -> part[split][state 16 st + j][row rowbase + 16 rt + 4 g + r]
-    float* out = G.part + static_cast<int64_t>(blockIdx.y) * G.bpad * G.rows;
+    float* out = G.part + sp * G.bpad * G.rows;
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
         const int64_t r0 = rowbase + 16 * rt + 4 * g;
@@ -295,10 +317,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t rowbase = static_cast<int64_t>(blockIdx.x) * kGemmRows + wave * 32;
+    int64_t rb, sp;
+    gemm_item(G, blockIdx.x, &rb, &sp);
+    const int64_t rowbase = rb * kGemmRows + wave * 32;
     int64_t kfirst, klast, rbase;
-    row_block_k(G, blockIdx.x, &kfirst, &klast, &rbase);
-    const int64_t kb = kfirst + static_cast<int64_t>(blockIdx.y) * G.kper;
+    row_block_k(G, rb, &kfirst, &klast, &rbase);
+    const int64_t kb = kfirst + sp * G.kper;
     const int64_t ke = min(kb + G.kper, klast);
     // a split past the row block's K range adds nothing: it writes zero partials
     const int nch = ke > kb ? static_cast<int>((ke - kb) / KC) : 0;
@@ -416,7 +440,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         if (c + 1 < nch) step(S1{}, c + 1);
     }
     // element 4 i + j of tile st -> part[split][state 32 st + l % 32][row rowbase + 8 i + 4 (l / 32) + j]
-    float* out = G.part + static_cast<int64_t>(blockIdx.y) * G.bpad * G.rows;
+    float* out = G.part + sp * G.bpad * G.rows;
     const int col = lane & 31, h = lane >> 5;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -485,10 +509,12 @@ __global__ __launch_bounds__(256) void k_prep(int64_t B, int64_t ns, int64_t ld,
 // Sum of the split-K partials in fixed order, then the per-tile finish.
 // Rows are in component order for the component-blocked operator (row
 // i np + a holds component i of tile a), else in tile order (3 a + i).
+// splits_z: the partials of the z rows of the component-blocked operator
+// (= splits in the dense form).
 template <Epi MODE>
 __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __restrict__ part,
-                                                int64_t splits, int64_t bpad, int64_t rows, bool cblk,
-                                                float scale, const float* __restrict__ X, int64_t sx,
+                                                int64_t splits, int64_t splits_z, int64_t bpad, int64_t rows,
+                                                bool cblk, float scale, const float* __restrict__ X, int64_t sx,
                                                 EpiArgs E) {
     const int s = blockIdx.y;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -499,7 +525,9 @@ __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __res
         float h0 = 0.f, h1 = 0.f, h2 = 0.f;
         for (int64_t sp = 0; sp < splits; ++sp) {
             const float* pp = part + (sp * bpad + s) * rows + r0;
-            h0 += pp[0]; h1 += pp[rs]; h2 += pp[2 * rs];
+            h0 += pp[0];
+            h1 += pp[rs];
+            if (sp < splits_z) h2 += pp[2 * rs];
         }
         finish_tile<MODE>(P, X, sx, E, s, a, -scale * h0, -scale * h1, -scale * h2, &rmax, &dmax);
     }
@@ -523,17 +551,25 @@ __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __res
     }
 }
 
+// workgroups of the 1-D product grid (gemm_item)
+inline unsigned gemm_items(const GemmArgs& G) {
+    return static_cast<unsigned>(G.rb2 * G.splits_xy + (G.rowblocks - G.rb2) * G.splits_z);
+}
+
 template <int PREC, int NST>
 tm_status launch_gemm_t(const GemmArgs& G, int64_t rowblocks, int64_t splits, hipStream_t s) {
-    launch_op(k_gemm<PREC, NST>, dim3(static_cast<unsigned>(rowblocks), static_cast<unsigned>(splits)), dim3(256),
-              s, G);
+    (void)rowblocks;
+    (void)splits;
+    launch_op(k_gemm<PREC, NST>, dim3(gemm_items(G)), dim3(256), s, G);
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
 }
 
 template <int PREC>
 tm_status launch_gemm_split(int nsb, const GemmArgs& G, int64_t rowblocks, int64_t splits, hipStream_t s) {
-    const dim3 grid(static_cast<unsigned>(rowblocks), static_cast<unsigned>(splits));
+    (void)rowblocks;
+    (void)splits;
+    const dim3 grid(gemm_items(G));
     switch (nsb) {
         case 1: launch_op(k_gemm_split<PREC, 1>, grid, dim3(256), s, G); break;
         case 2: launch_op(k_gemm_split<PREC, 2>, grid, dim3(256), s, G); break;
@@ -630,6 +666,10 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     G.kper = round_up((kext + splits - 1) / splits, KC);
     const int64_t used_splits = (kext + G.kper - 1) / G.kper;
     const int64_t rowblocks = T->rows / kGemmRows;
+    G.rowblocks = rowblocks;
+    G.rb2 = T->cblk ? 2 * G.np / kGemmRows : rowblocks;
+    G.splits_xy = used_splits;
+    G.splits_z = T->cblk ? (G.np + G.kper - 1) / G.kper : used_splits;
     tm_status st = prec == 0   ? launch_gemm_p<0>(static_cast<int>(ns / 16), G, rowblocks, used_splits, s)
                    : prec == 1 ? launch_gemm_split<1>(static_cast<int>(ns / 32), G, rowblocks, used_splits, s)
                                : launch_gemm_split<2>(static_cast<int>(ns / 32), G, rowblocks, used_splits, s);
@@ -640,12 +680,12 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     const dim3 grid(static_cast<unsigned>((p->n + 255) / 256), static_cast<unsigned>(B));
     const int64_t sx = 3 * p->np;
     switch (mode) {
-        case Epi::HD: k_finish<Epi::HD><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
-        case Epi::HEFF: k_finish<Epi::HEFF><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
-        case Epi::DMDT: k_finish<Epi::DMDT><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
-        case Epi::STAGE: k_finish<Epi::STAGE><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
-        case Epi::RK4_FINAL: k_finish<Epi::RK4_FINAL><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
-        case Epi::DP_LAST: k_finish<Epi::DP_LAST><<<grid, 256, 0, s>>>(P, w->part, used_splits, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
+        case Epi::HD: k_finish<Epi::HD><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
+        case Epi::HEFF: k_finish<Epi::HEFF><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
+        case Epi::DMDT: k_finish<Epi::DMDT><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
+        case Epi::STAGE: k_finish<Epi::STAGE><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
+        case Epi::RK4_FINAL: k_finish<Epi::RK4_FINAL><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
+        case Epi::DP_LAST: k_finish<Epi::DP_LAST><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
     }
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
