@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-sp3", action="store_true")
     ap.add_argument("--no-cache-free", action="store_true")
     ap.add_argument("--no-sp4-dynamics", action="store_true")
+    ap.add_argument("--tile-loads", choices=["auto", "cached", "nontemporal"], default="auto",
+                    help="pair-symmetric layouts: operator loads of the tile pass (auto: the autotuner's pick)")
     ap.add_argument("--profile-batch", type=int, default=1,
                     help="--profile-only: states integrated together (a batch reads each operator tile "
                          "once per tile pass)")
@@ -241,7 +243,18 @@ def batched_section(tmg, W, torch, attempts=60, profile_iters=20):
     return out, {"centers": wl.centers, "sizes": wl.sizes, "Ms": wl.Ms, "m": m32, "hd": hds}
 
 
-def cache_free_section(tmg, W, torch, layout, attempts=20):
+def tile_loads_choice(tmg, p, psym, forced, iters):
+    """The pair-symmetric tile pass's operator loads: the autotuner's pick, or
+    the one asked for (profiling runs: the profiler slows the timed
+    candidates unevenly, so they name the pick of an unprofiled run)."""
+    choice, _ = tmg.tm_problem_tune(p.handle, 1, iters)
+    if psym and forced != "auto":
+        choice = 1 if forced == "nontemporal" else 0
+        tmg.tm_problem_apply(p.handle, choice)
+    return choice
+
+
+def cache_free_section(tmg, W, torch, layout, attempts=20, tile_loads="auto"):
     """The headline's operator pass on an operator larger than the 256 MB
     Infinity Cache: the SP4 film at [160, 40, 1] tiles (N = 6400; PSYM4
     327.7 MB, PSYM6 491.6 MB, SYM6 983 MB), timed inside DP45 steps like
@@ -252,7 +265,7 @@ def cache_free_section(tmg, W, torch, layout, attempts=20):
     geom = tmg.Geometry(ctx, wl.centers, wl.sizes)
     T = tmg.Tensor(ctx, geom, tmg.TM_PREC_FP32, LAYOUT_CODE[layout])
     p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
-    choice, _ = tmg.tm_problem_tune(p.handle, 1, 10)
+    choice = tile_loads_choice(tmg, p, layout in ("psym4", "psym6"), tile_loads, 10)
     m = torch.as_tensor(wl.m0.astype(np.float32), device="cuda")
     Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
     t = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -778,7 +791,7 @@ def main():
     p = tmg.Problem(ctx, geom, T, wl.Ms, wl.A, wl.alpha, wl.gamma0)
     # project autotuner: fastest launch shape of the fused stage kernel for this N
     # (pair-symmetric layouts: cached or nontemporal operator loads in the tile pass)
-    shape, _ = tmg.tm_problem_tune(p.handle, 1, 50)
+    shape = tile_loads_choice(tmg, p, psym, args.tile_loads, 50)
     nt_loads = psym and shape == 1
     m = torch.as_tensor(wl.m0.astype(np.float32), device="cuda")
     Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
@@ -880,7 +893,7 @@ def main():
     }
     if stored_bytes < (256 << 20) and not args.no_cache_free:
         progress("cache-free roofline (N = 6400 film)")
-        rec["roofline"]["cache_free"] = cache_free_section(tmg, W, torch, args.layout)
+        rec["roofline"]["cache_free"] = cache_free_section(tmg, W, torch, args.layout, tile_loads=args.tile_loads)
     p.close()
     T.close()
     geom.close()

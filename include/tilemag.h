@@ -402,6 +402,13 @@ tm_status tm_problem_set_shape(tm_problem* p, int32_t shape);
 tm_status tm_problem_tune(tm_problem* p, int64_t B, int32_t iters, hipStream_t stream,
                           int32_t* chosen, double* best_ms);
 
+/* Applies a choice as tm_problem_tune reports it, without timing: a launch
+ * shape for SYM6, a K-split count for the batched DENSE9 product, 0 / 1
+ * (cached / nontemporal operator loads) for PSYM6 / PSYM4.  For reproducing
+ * a known configuration (a profiling run, another process) exactly.
+ * TM_EINVAL if the choice is not a candidate for p (nothing changes then). */
+tm_status tm_problem_apply(tm_problem* p, int32_t choice);
+
 /* The autotuner's table as a JSON file (one entry per line: arch, cus,
  * layout, prec, n, batch, choice, ms), so that a later process reuses the
  * tuned choices.  tm_tune_cache_save writes every entry (TM_EINVAL if the

@@ -65,21 +65,31 @@ struct GemmArgs {
     int64_t rowblocks, rb2, splits_xy, splits_z;
 };
 
-// Row block rb and K split sp of workgroup bid (a 1-D grid): the row blocks
-// of split 0, then of split 1, ..., first for the row blocks with the full K
-// range, then for the z row blocks of the component-blocked form, whose
-// shorter K range needs fewer splits of the same length: no workgroup
-// idles.
-__device__ inline void gemm_item(const GemmArgs& G, int64_t bid, int64_t* rb, int64_t* sp) {
+// Work items in split-major order: the row blocks of split 0, then of split
+// 1, ..., first for the row blocks with the full K range, then for the z
+// row blocks of the component-blocked form, whose shorter K range needs
+// fewer splits of the same length (no workgroup idles).  Consecutive
+// workgroups go to the eight XCDs in turn, each with its own L2; workgroup
+// bid takes item (bid mod 8) per + bid / 8, so that every XCD works through
+// one contiguous run of items and reads the right operand of only one or
+// two K ranges (per = items per XCD; the few workgroups past the last item
+// do nothing).  Returns false for those.
+constexpr int kXcds = 8;
+__device__ inline bool gemm_item(const GemmArgs& G, int64_t bid, int64_t* rb, int64_t* sp) {
+    const int64_t total = G.rb2 * G.splits_xy + (G.rowblocks - G.rb2) * G.splits_z;
+    const int64_t per = (total + kXcds - 1) / kXcds;
+    const int64_t item = (bid % kXcds) * per + bid / kXcds;
+    if (item >= total) return false;
     const int64_t nxy = G.rb2 * G.splits_xy;
-    if (bid < nxy) {
-        *rb = bid % G.rb2;
-        *sp = bid / G.rb2;
+    if (item < nxy) {
+        *rb = item % G.rb2;
+        *sp = item / G.rb2;
     } else {
-        const int64_t z = bid - nxy, nz = G.rowblocks - G.rb2;
+        const int64_t z = item - nxy, nz = G.rowblocks - G.rb2;
         *rb = G.rb2 + z % nz;
         *sp = z / nz;
     }
+    return true;
 }
 
 // K range [k0, k1) of row block rb and the element offset of its first stored
@@ -151,7 +161,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, j = lane & 15;
     int64_t rb, sp;
-    gemm_item(G, blockIdx.x, &rb, &sp);
+    if (!gemm_item(G, blockIdx.x, &rb, &sp)) return;
     const int64_t rowbase = rb * kGemmRows + wave * 32;
     int64_t kfirst, klast, rbase;
     row_block_k(G, rb, &kfirst, &klast, &rbase);
@@ -318,7 +328,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int64_t rb, sp;
-    gemm_item(G, blockIdx.x, &rb, &sp);
+    if (!gemm_item(G, blockIdx.x, &rb, &sp)) return;
     const int64_t rowbase = rb * kGemmRows + wave * 32;
     int64_t kfirst, klast, rbase;
     row_block_k(G, rb, &kfirst, &klast, &rbase);
@@ -551,9 +561,11 @@ __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __res
     }
 }
 
-// workgroups of the 1-D product grid (gemm_item)
+// workgroups of the 1-D product grid (gemm_item): the items rounded up to a
+// whole number per XCD
 inline unsigned gemm_items(const GemmArgs& G) {
-    return static_cast<unsigned>(G.rb2 * G.splits_xy + (G.rowblocks - G.rb2) * G.splits_z);
+    const int64_t total = G.rb2 * G.splits_xy + (G.rowblocks - G.rb2) * G.splits_z;
+    return static_cast<unsigned>((total + kXcds - 1) / kXcds * kXcds);
 }
 
 template <int PREC, int NST>

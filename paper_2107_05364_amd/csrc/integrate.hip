@@ -646,6 +646,16 @@ bool apply_choice(Problem* p, TuneKind k, int c) {
 }  // namespace
 }  // namespace tmag
 
+extern "C" tm_status tm_problem_apply(tm_problem* pp, int32_t choice) {
+    Problem* p = reinterpret_cast<Problem*>(pp);
+    TM_REQUIRE(p, TM_EINVAL, "tm_problem_apply: null problem");
+    const TuneKind kind = tune_kind(p);
+    TM_REQUIRE(kind != TuneKind::NONE, TM_EINVAL, "tm_problem_apply: this operator has no choices");
+    TM_REQUIRE(apply_choice(p, kind, choice), TM_EINVAL, "tm_problem_apply: %d is not a candidate for this problem",
+               static_cast<int>(choice));
+    return TM_OK;
+}
+
 extern "C" tm_status tm_problem_tune(tm_problem* pp, int64_t B, int32_t iters, hipStream_t s,
                                      int32_t* chosen, double* best_ms) {
     Problem* p = reinterpret_cast<Problem*>(pp);

@@ -38,7 +38,7 @@ EXPORTS = [
     "tm_diagnostics",
     "tm_run", "tm_profile_run", "tm_profile_field", "tm_profile_field_mode", "tm_num_shapes", "tm_shape_info",
     "tm_problem_shape", "tm_problem_set_shape",
-    "tm_problem_tune", "tm_tune_cache_save", "tm_tune_cache_load", "tm_tune_cache_clear",
+    "tm_problem_tune", "tm_problem_apply", "tm_tune_cache_save", "tm_tune_cache_load", "tm_tune_cache_clear",
     "tm_tune_cache_size", "tm_server_create", "tm_server_submit", "tm_server_poll", "tm_server_destroy",
 ]
 
@@ -144,6 +144,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "tm_problem_shape": (i32, [vp, P(i32)]),
         "tm_problem_set_shape": (i32, [vp, i32]),
         "tm_problem_tune": (i32, [vp, i64, i32, vp, P(i32), P(d)]),
+        "tm_problem_apply": (i32, [vp, i32]),
         "tm_tune_cache_save": (i32, [C.c_char_p]),
         "tm_tune_cache_load": (i32, [C.c_char_p]),
         "tm_tune_cache_clear": (i32, []),
@@ -488,6 +489,11 @@ def tm_problem_tune(p, B: int = 1, iters: int = 20):
     ch, ms = C.c_int32(), C.c_double()
     _check(load().tm_problem_tune(p, int(B), int(iters), _stream(), C.byref(ch), C.byref(ms)))
     return ch.value, ms.value
+
+
+def tm_problem_apply(p, choice: int) -> None:
+    """Applies a choice as tm_problem_tune reports it, without timing."""
+    _check(load().tm_problem_apply(p, int(choice)))
 
 
 def tm_tune_cache_save(path: str) -> None:

@@ -53,3 +53,32 @@ def test_tune_results_are_cached_and_reloaded(tmp_path):
     close(g, T, p)
     tmg.tm_tune_cache_clear()
     ctx.close()
+
+
+def test_apply_reproduces_a_choice():
+    """tm_problem_apply sets what tm_problem_tune would choose, untimed: the
+    pair-symmetric loads (the field is the same either way), a SYM6 launch
+    shape (tm_problem_shape reports it); a non-candidate is refused and
+    changes nothing."""
+    tmg = tilemag()
+    ctx = tmg.Context(0)
+    c, s = W.grid(30, 10, 1, 5e-9, 5e-9, 3e-9)
+    m = device_state(W.random_unit_vectors(7, c.shape[0])[None])
+    g, T, p = build(tmg, ctx, c, s, layout=tmg.TM_LAYOUT_PSYM4)
+    fields = []
+    for choice in (0, 1):
+        tmg.tm_problem_apply(p.handle, choice)
+        fields.append(p.heff(m).cpu().numpy())
+    assert np.array_equal(fields[0], fields[1])
+    with pytest.raises(tmg.TilemagError):
+        tmg.tm_problem_apply(p.handle, 2)
+    close(g, T, p)
+    g, T, p = build(tmg, ctx, c, s, layout=tmg.TM_LAYOUT_SYM6)
+    for shape in (3, tmg.tm_num_shapes() - 1):
+        tmg.tm_problem_apply(p.handle, shape)
+        assert tmg.tm_problem_shape(p.handle) == shape
+    with pytest.raises(tmg.TilemagError):
+        tmg.tm_problem_apply(p.handle, tmg.tm_num_shapes())
+    assert tmg.tm_problem_shape(p.handle) == tmg.tm_num_shapes() - 1
+    close(g, T, p)
+    ctx.close()
