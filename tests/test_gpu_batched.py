@@ -125,6 +125,38 @@ def test_tuned_split_count(tmg, ctx, orc, prec):
     close(g, T, p)
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("mesh", ["film", "slab"])
+def test_every_split_count(tmg, ctx, orc, prec, mesh):
+    """Every K-split count the autotuner can pick (applied with
+    tm_problem_apply), on a single layer (component-blocked operator: the z
+    rows take fewer splits, and some counts leave work items short of a whole
+    number per XCD) and on a three-layer mesh with per-tile Ms (dense form):
+    H_d against the oracle within the precision's tolerance, a repeat bitwise
+    identical."""
+    if mesh == "film":
+        wl = W.thin_film(nx=40, ny=10)
+        centers, sizes = wl.centers, wl.sizes
+        Ms = np.full(wl.n, 8.0e5)
+    else:
+        centers, sizes = W.grid(12, 8, 3, 5e-9, 5e-9, 3e-9)
+        Ms = 8.0e5 * (0.75 + 0.5 * W.uniform(3, centers.shape[0]))
+    n = centers.shape[0]
+    g, T, p = build(tmg, ctx, centers, sizes, Ms=Ms, store=prec, layout=tmg.TM_LAYOUT_DENSE9)
+    m = np.stack([W.random_unit_vectors(60 + k, n) for k in range(37)]).astype(np.float32)
+    Tref = orc.assemble(centers, sizes)
+    want = [orc.demag(Tref, Ms, m[k].astype(np.float64)) for k in (0, 18, 36)]
+    for splits in (2, 3, 4, 5, 6, 8):
+        tmg.tm_problem_apply(p.handle, splits)
+        H = p.demag(device_state(m)).cpu().numpy()
+        for k, w in zip((0, 18, 36), want):
+            e2, emax = rel_errors(H[k], w)
+            assert e2 <= TOL[prec] and emax <= TOL[prec], (splits, k, e2, emax)
+        assert np.array_equal(H, p.demag(device_state(m)).cpu().numpy()), splits
+        _say("  %s %s, %d K splits ok" % (mesh, NAMES[prec], splits))
+    close(g, T, p)
+
+
 def test_batched_dp45_matches_matvec_path(tmg, ctx):
     """DP45 on 8 states to a common end time: the FP32 GEMM path and the FP32
     matvec path (different summation orders) agree within the float32
