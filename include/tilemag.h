@@ -96,9 +96,11 @@ int32_t tm_version(void);
 /* Achievable rates of device `device`, measured with the library's own
  * kernels (context for the roofline fractions, which use published peaks):
  * a streaming read of a zero-filled read_bytes buffer (1 MiB .. 16 GiB,
- * rounded down to whole 64 KiB chunks, one workgroup per chunk as the
- * operator passes read their tiles, the faster of cached and nontemporal
- * loads; allocated and freed by the call) in GB/s, and register-only loops of the
+ * rounded down to whole 64 KiB chunks; allocated and freed by the call) in
+ * GB/s, the fastest of: one workgroup per chunk as the pair-symmetric tile
+ * pass reads its tiles, and one long contiguous stream per workgroup (2, 4 or
+ * 8 workgroups per CU) as the stage kernel reads its rows, each with cached
+ * and with nontemporal loads; and register-only loops of the
  * 32x32x16 bf16 and 16x16x4 float32 MFMA instructions the batched product
  * issues, in TFLOP/s.  Output pointers may be NULL (that measurement is
  * skipped).  Blocking; uses the device's null stream.  TM_EINVAL for a size
