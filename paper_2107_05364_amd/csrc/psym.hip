@@ -70,9 +70,9 @@ inline int64_t pair_index(int64_t I, int64_t J, int64_t nt) {
 // RPT - 1 (rg = t / TS): each row's components are coalesced loads.  Per
 // state the Ms-scaled inputs of the two tiles are staged in LDS (one
 // coalesced load per component), the row sums go through LDS to a sum over
-// the TS columns, the column sums through LDS to a sum over the RG groups
-// (both in a fixed order, the same for either grid: results do not depend on
-// the batch).
+// the TS columns (four interleaved partial sums), the column sums through LDS
+// to a sum over the RG groups (both in a fixed order, the same for either
+// grid: results do not depend on the batch).
 //
 // LOCALF: the workgroups of diagonal pairs (I == J) also evaluate the local
 // field terms (exchange, anisotropy, applied field) of their TS tiles --
@@ -158,16 +158,20 @@ __global__ __launch_bounds__(kTileThreads) void k_psym_tiles(DevProblem P, const
         __syncthreads();
         if (t < 3 * TS) {
             const int r = t / 3, c = t % 3;
-            float acc = 0.0f;
-#pragma unroll 8
-            for (int l = 0; l < TS; ++l) acc += rred[r][c][l];
+            // four interleaved partial sums (columns l mod 4), then a fixed
+            // pairwise order: a quarter of the dependent adds
+            float a4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int l = 0; l < TS; ++l) a4[l % 4] += rred[r][c][l];
+            float acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
             if (LOCALF && I == J) acc -= hl[r][c];
-            part[((s * nt + I) * nt + J) * (3 * TS) + t] = acc;
+            // the slots are read once, by the finish (on another XCD): streaming stores
+            __builtin_nontemporal_store(acc, part + ((s * nt + I) * nt + J) * (3 * TS) + t);
             if (I != J) {
                 float cs = 0.0f;
 #pragma unroll
                 for (int q = 0; q < RG; ++q) cs += cred[q][r][c];
-                part[((s * nt + J) * nt + I) * (3 * TS) + t] = cs;
+                __builtin_nontemporal_store(cs, part + ((s * nt + J) * nt + I) * (3 * TS) + t);
             }
         }
     };
