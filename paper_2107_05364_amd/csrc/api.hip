@@ -69,7 +69,7 @@ Workspace::~Workspace() {
     float* fl[] = {y, ya, yb, y5, k[0], k[1], k[2], k[3], k[4], k[5], k[6], Ha, hd, part};
     for (float* p : fl)
         if (p) (void)hipFree(p);
-    void* vp[] = {xh, xl, t, h, dt, errp, dmxp, snap, steps, rejected, flags, acc, params, esum, diag, stat, bar,
+    void* vp[] = {xh, xl, t, h, dt, t1, h1, steps1, flags1, errp, dmxp, snap, steps, rejected, flags, acc, params, esum, diag, stat, bar,
                   bar_fail};
     for (void* p : vp)
         if (p) (void)hipFree(p);
@@ -646,6 +646,10 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->t), bcap * 8);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->h), bcap * 8);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->dt), bcap * 8);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->t1), bcap * 8);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->h1), bcap * 8);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->steps1), bcap * 8);
+    if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->flags1), bcap * 4);
     w->pstride = n;  // at most one partial per target tile (one tile per block)
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->errp), bcap * n * 8);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&w->dmxp), bcap * n * 8);

@@ -228,6 +228,12 @@ struct Workspace {
     double* t = nullptr;
     double* h = nullptr;      // step used by the current attempt (0: frozen)
     double* dt = nullptr;     // proposal
+    // a second set of RK4 control values (t, h, steps, flags): an attempt
+    // whose last stage advances the control writes it, the next one reads it
+    double* t1 = nullptr;
+    double* h1 = nullptr;
+    int64_t* steps1 = nullptr;
+    int32_t* flags1 = nullptr;
     double* errp = nullptr;   // [B][pstride] per-block maxima of the scaled error
     double* dmxp = nullptr;   // [B][pstride] per-block maxima of |dm/dt|
     int64_t pstride = 0;
@@ -326,6 +332,13 @@ struct EpiArgs {
     const int64_t* rejected;
     const int32_t* flags;
     double* snap;
+    // RK4_FINAL with rk_t_out set: the first workgroup of each state also
+    // advances the RK4 step control from the values the stages read (t, h,
+    // steps, flags above) into this second set, which the next attempt reads
+    double* rk_t_out;
+    double* rk_h_out;
+    int64_t* rk_steps_out;
+    int32_t* rk_flags_out;
 };
 
 // H (or a stage) for B states whose inputs X are padded internal buffers.

@@ -174,6 +174,47 @@ __device__ void finish_tile(const DevProblem& P, const float* __restrict__ X, in
 }
 
 
+// RK4 step control of state s after its step of length h: t += h, one more
+// step, done at the step cap or at t_end; the next step is min(dt, t_end -
+// t), 0 when done or stopped.  Reads (t, h, steps, flags) and writes (to,
+// ho, so, fo): the same arrays for the control pass, the second set when the
+// last stage advances the control.
+__device__ inline void rk4_control(const double* __restrict__ prm, const double* t, const double* h,
+                                   const double* __restrict__ dt, const int64_t* steps, const int32_t* flags,
+                                   double* to, double* ho, int64_t* so, int32_t* fo, int64_t s) {
+    int32_t f = flags[s];
+    const double t0 = t[s], h0 = h[s];
+    const int64_t st0 = steps[s];
+    if (f & (FLAG_DONE | FLAG_NONFINITE | FLAG_STEP)) {
+        to[s] = t0;
+        so[s] = st0;
+        fo[s] = f;
+        ho[s] = 0.0;
+        return;
+    }
+    const double t_end = prm[RP_TEND];
+    const double tn = t0 + h0;
+    const int64_t sn = st0 + 1;
+    const bool done = static_cast<double>(sn) >= prm[RP_MAX_STEPS] || (t_end > 0.0 && tn >= t_end);
+    if (done) f |= FLAG_DONE;
+    to[s] = tn;
+    so[s] = sn;
+    fo[s] = f;
+    const double dn = dt[s];
+    ho[s] = done ? 0.0 : (t_end > 0.0 ? fmin(dn, t_end - tn) : dn);
+}
+
+// The last RK4 stage's share of the control: the first workgroup of each
+// state (before anything else, also for a frozen state) advances it.
+template <Epi MODE>
+__device__ inline void rk4_last_stage_control(const EpiArgs& E) {
+    if constexpr (MODE == Epi::RK4_FINAL) {
+        if (E.rk_t_out && blockIdx.x == 0 && threadIdx.x == 0)
+            rk4_control(E.params, E.t, E.h, E.dt, E.steps, E.flags, E.rk_t_out, E.rk_h_out, E.rk_steps_out,
+                        E.rk_flags_out, blockIdx.y);
+    }
+}
+
 // Dormand-Prince step control of one state: acceptance from the scaled
 // max-norm error e (accept iff e <= 1), next step h * min(5, max(0.2,
 // 0.9 e^-1/5)) (5 when e == 0), capped at t_end; done at the step cap, at

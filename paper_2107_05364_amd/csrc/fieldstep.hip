@@ -62,6 +62,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, WPE)))
     const int s = blockIdx.y;
     const int a0 = blockIdx.x * TT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    rk4_last_stage_control<MODE>(E);
     // a state that is done or failed has h = 0: its stages are skipped (the
     // last stage still reports to the step control)
     bool frozen = false;
@@ -186,20 +187,7 @@ __global__ void k_control_rk4(int64_t B, const double* __restrict__ prm, double*
                               int64_t* __restrict__ steps, int32_t* __restrict__ flags) {
     const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= B) return;
-    int32_t f = flags[s];
-    if (f & (FLAG_DONE | FLAG_NONFINITE | FLAG_STEP)) {
-        h[s] = 0.0;
-        return;
-    }
-    const double t_end = prm[RP_TEND];
-    const double tn = t[s] + h[s];
-    steps[s] += 1;
-    t[s] = tn;
-    const bool done = static_cast<double>(steps[s]) >= prm[RP_MAX_STEPS] || (t_end > 0.0 && tn >= t_end);
-    if (done) f |= FLAG_DONE;
-    flags[s] = f;
-    const double dn = dt[s];
-    h[s] = done ? 0.0 : (t_end > 0.0 ? fmin(dn, t_end - tn) : dn);
+    rk4_control(prm, t, h, dt, steps, flags, t, h, steps, flags, s);
 }
 
 // Accept / reject of a Dormand-Prince attempt.  Block (x, s) takes tiles

@@ -528,6 +528,7 @@ __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __res
                                                 EpiArgs E) {
     const int s = blockIdx.y;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    rk4_last_stage_control<MODE>(E);
     double rmax = 0.0, dmax = 0.0;
     if (a < P.n) {
         const int64_t r0 = cblk ? a : 3 * static_cast<int64_t>(a);

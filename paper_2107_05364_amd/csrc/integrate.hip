@@ -146,31 +146,72 @@ tm_status dp_attempt(const Problem* p, Workspace* w, int64_t B, hipStream_t s) {
     return launch_commit(p, w, B, s);  // step control fused into the commit pass
 }
 
-// One classical RK4 step.
-tm_status rk4_attempt(const Problem* p, Workspace* w, int64_t B, int renorm, hipStream_t s) {
+// RK4 control values: the workspace's own (t, h, steps, flags) or its
+// second set.
+struct RkCtl {
+    double* t;
+    double* h;
+    int64_t* steps;
+    int32_t* flags;
+};
+RkCtl rk_set(Workspace* w, int which) {
+    return which == 0 ? RkCtl{w->t, w->h, w->steps, w->flags} : RkCtl{w->t1, w->h1, w->steps1, w->flags1};
+}
+
+// One classical RK4 step whose stages read the control values `in`.  With
+// `out` the last stage also advances the control into `out` (no launch of
+// its own); else the control pass advances `in` in place.
+tm_status rk4_attempt(const Problem* p, Workspace* w, int64_t B, int renorm, const RkCtl& in, const RkCtl* out,
+                      hipStream_t s) {
     const float* kp[3] = {w->k[0], w->k[1], w->k[2]};
     const double half[1] = {0.5}, one[1] = {1.0};
+    auto with_ctl = [&](EpiArgs e) {
+        e.h = in.h;
+        e.t = in.t;
+        e.steps = in.steps;
+        e.flags = in.flags;
+        return e;
+    };
     tm_status r;
-    EpiArgs e1 = stage_args(w, w->k[0], nullptr, 0, half, w->ya);
+    EpiArgs e1 = with_ctl(stage_args(w, w->k[0], nullptr, 0, half, w->ya));
     if ((r = launch_field(p, Epi::STAGE, B, w->y, e1, s)) != TM_OK) return r;
-    EpiArgs e2 = stage_args(w, w->k[1], nullptr, 0, half, w->yb);
+    EpiArgs e2 = with_ctl(stage_args(w, w->k[1], nullptr, 0, half, w->yb));
     if ((r = launch_field(p, Epi::STAGE, B, w->ya, e2, s)) != TM_OK) return r;
-    EpiArgs e3 = stage_args(w, w->k[2], nullptr, 0, one, w->ya);
+    EpiArgs e3 = with_ctl(stage_args(w, w->k[2], nullptr, 0, one, w->ya));
     if ((r = launch_field(p, Epi::STAGE, B, w->yb, e3, s)) != TM_OK) return r;
     const double fin[4] = {1.0 / 6, 2.0 / 6, 2.0 / 6, 1.0 / 6};
-    EpiArgs e4 = stage_args(w, nullptr, kp, 3, fin, nullptr);
+    EpiArgs e4 = with_ctl(stage_args(w, nullptr, kp, 3, fin, nullptr));
     e4.y_mut = w->y;
     e4.renorm = renorm;
+    if (out) {
+        e4.rk_t_out = out->t;
+        e4.rk_h_out = out->h;
+        e4.rk_steps_out = out->steps;
+        e4.rk_flags_out = out->flags;
+    }
     if ((r = launch_field(p, Epi::RK4_FINAL, B, w->ya, e4, s)) != TM_OK) return r;
-    return launch_control(w, B, TM_RK4, s);
+    return out ? TM_OK : launch_control(w, B, TM_RK4, s);
 }
 
 }  // namespace
 
 tm_status enqueue_attempts(const Problem* p, Workspace* w, int integ, int64_t B, int renorm,
                            int count, hipStream_t s) {
+    if (integ == TM_RK4) {
+        // pairs of steps advance the control in their last stages, from the
+        // workspace's set into the second and back; an odd last step uses
+        // the control pass
+        const RkCtl c0 = rk_set(w, 0), c1 = rk_set(w, 1);
+        int i = 0;
+        for (; i + 1 < count; i += 2) {
+            tm_status r = rk4_attempt(p, w, B, renorm, c0, &c1, s);
+            if (r == TM_OK) r = rk4_attempt(p, w, B, renorm, c1, &c0, s);
+            if (r != TM_OK) return r;
+        }
+        return i < count ? rk4_attempt(p, w, B, renorm, c0, nullptr, s) : TM_OK;
+    }
     for (int i = 0; i < count; ++i) {
-        tm_status r = integ == TM_RK4 ? rk4_attempt(p, w, B, renorm, s) : dp_attempt(p, w, B, s);
+        tm_status r = dp_attempt(p, w, B, s);
         if (r != TM_OK) return r;
     }
     return TM_OK;

@@ -260,6 +260,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_psym_finish(DevProblem P, co
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int pos = t % kFinishPos, g = t / kFinishPos;
     const bool adds = g < G;
+    rk4_last_stage_control<MODE>(E);
     __shared__ f4 gs[G][kFinishPos];
     const f4* src = reinterpret_cast<const f4*>(part + (static_cast<int64_t>(s) * nt + K) * nt * (3 * TS)) + pos;
     f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};

@@ -165,6 +165,7 @@ __global__ __launch_bounds__(256) void k_field_bsr(DevProblem P, const int64_t* 
     const int s = blockIdx.y;
     const int a = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    rk4_last_stage_control<MODE>(E);
     bool frozen = false;
     if constexpr (STEPPING) frozen = E.h[s] == 0.0;
     if constexpr (MODE == Epi::STAGE || MODE == Epi::RK4_FINAL) {
