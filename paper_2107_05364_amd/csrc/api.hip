@@ -69,7 +69,7 @@ Workspace::~Workspace() {
     float* fl[] = {y, ya, yb, y5, k[0], k[1], k[2], k[3], k[4], k[5], k[6], Ha, hd, part};
     for (float* p : fl)
         if (p) (void)hipFree(p);
-    void* vp[] = {xh, xl, t, h, dt, t1, h1, steps1, flags1, errp, dmxp, snap, steps, rejected, flags, acc, params, esum, diag, stat, bar,
+    void* vp[] = {xh, xl, fxh[0], fxh[1], fxh[2], fxl[0], fxl[1], fxl[2], t, h, dt, t1, h1, steps1, flags1, errp, dmxp, snap, steps, rejected, flags, acc, params, esum, diag, stat, bar,
                   bar_fail};
     for (void* p : vp)
         if (p) (void)hipFree(p);
@@ -604,7 +604,8 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
     int64_t xbytes = 0, pbytes = 0, splits = 0;
     if (dense) {
         const int64_t esz = T->prec == TM_PREC_FP32 ? 4 : 2;
-        // the right operand in the product's fragment order (hi + lo for the split forms)
+        // the right operand in the product's fragment order (hi + lo for the
+        // split forms), once for k_prep and once per stage output ya, yb, y5
         xbytes = bcap * T->ld * esz * (T->prec == TM_PREC_FP32 ? 1 : 2);
         splits = gemm_splits(p);
         pbytes = splits * bcap * T->rows * 4;
@@ -613,7 +614,7 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
     if (psym) pbytes = psym_partial_floats(T, bcap) * 4;
     const int64_t dbytes = bcap * (nblk * 6 + 4) * 8;  // diagnostics partials + energies
     int64_t bytes = 12 * sb + bcap * 12 + bcap * (8 * 7 + 8 * 2 + 4 * 2 + 8 * kSnapStride + 24) + 16 * bcap * n + 576 +
-                    RP_COUNT * 8 + nblk * bcap * 32 + xbytes + pbytes + dbytes;
+                    RP_COUNT * 8 + nblk * bcap * 32 + 4 * xbytes + pbytes + dbytes;
     {
         std::lock_guard<std::mutex> lk(p->ctx->mu);
         const int64_t old = p->ws ? p->ws->bytes : 0;
@@ -670,6 +671,10 @@ tm_status ensure_workspace(Problem* p, int64_t B) {
         const int64_t half = T->prec == TM_PREC_FP32 ? xbytes : xbytes / 2;
         e = alloc(&w->xh, half);
         if (e == hipSuccess && T->prec != TM_PREC_FP32) e = alloc(&w->xl, half);
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+            e = alloc(&w->fxh[i], half);
+            if (e == hipSuccess && T->prec != TM_PREC_FP32) e = alloc(&w->fxl[i], half);
+        }
     }
     if ((dense || psym) && e == hipSuccess) {
         e = alloc(reinterpret_cast<void**>(&w->part), pbytes);

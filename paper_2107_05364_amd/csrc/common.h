@@ -224,6 +224,16 @@ struct Workspace {
     float* part = nullptr;    // split-K partials [S][bpad][rows]
     int64_t part_splits = 0;
     int64_t bpad = 0;         // states in the GEMM operand buffers (multiple of 16)
+    // the right operand of ya, yb and y5 in the same order, written by the
+    // stage whose output they are (zero in the padding: allocated zeroed,
+    // never written there).  frag_src: the buffer whose copy the last
+    // batched launch wrote (else null); frag_chain: set by a caller whose
+    // next launch reads the previous stage's output unchanged (the stages
+    // of one attempt), so that that launch may use the copy
+    void* fxh[3] = {};
+    void* fxl[3] = {};
+    const float* frag_src = nullptr;
+    bool frag_chain = false;
     // per-state control
     double* t = nullptr;
     double* h = nullptr;      // step used by the current attempt (0: frozen)

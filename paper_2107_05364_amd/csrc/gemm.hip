@@ -472,60 +472,135 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 //     kc KC + 16 sub + 4 g + e at ((sub nt + st) 64 + 16 g + j) 4 + e;
 //   split forms (32-state tiles, nt = ns / 32): state 32 st + i, column
 //     kc KC + 16 ks + 8 q + e at ((ks nt + st) 64 + 32 q + i) 8 + e;
-// states B .. ns - 1 are zero.  One thread per output element.
-// With the component-blocked operator, K is in component order as well:
-// column k holds component k / np of tile k % np.
+// states B .. ns - 1 and tiles n .. np - 1 are zero.  With the
+// component-blocked operator, K is in component order as well: column k
+// holds component k / np of tile k % np.
+// One workgroup per 64 tiles and 16 states: the 16 x 192 stage-input values
+// of its tiles (three components each) come in as coalesced 16-byte loads,
+// are scaled (Ms from LDS) into an LDS tile, and leave as the 16-byte
+// fragment pieces of the three chunks they make (dense form: columns 3 b0 ..
+// 3 b0 + 191; the component-blocked form: the chunk of each component), each
+// output piece one contiguous store.
+constexpr int kPrepTiles = 64;
+constexpr int kPrepStates = 16;
+constexpr int kPrepCols = 3 * kPrepTiles;
 template <int PREC>
 __global__ __launch_bounds__(256) void k_prep(int64_t B, int64_t ns, int64_t ld, int32_t n, bool cblk,
                                               const float* __restrict__ Y, const float* __restrict__ Ms,
                                               float inv_ref, void* __restrict__ xh, void* __restrict__ xl) {
-    constexpr int VEC = Elt<PREC>::kVec;
-    constexpr int TW = PREC == 0 ? 16 : 32;  // states per tile
-    const int64_t nt = ns / TW;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= ns * ld) return;
-    const int64_t kc = i / (ns * KC);
-    const int64_t w = i % (ns * KC);
-    const int64_t piece = w / VEC;
-    const int e = static_cast<int>(w % VEC);
-    const int ln = static_cast<int>(piece % 64);
-    const int64_t q = piece / 64;
-    const int64_t st = q % nt, sub = q / nt;
-    int64_t s, k;
-    if constexpr (PREC == 0) {
-        s = 16 * st + (ln & 15);
-        k = kc * KC + 16 * sub + 4 * (ln >> 4) + e;
-    } else {
-        s = 32 * st + (ln & 31);
-        k = kc * KC + 16 * sub + 8 * (ln >> 5) + e;
+    __shared__ float tile[kPrepStates][kPrepCols + 1];
+    __shared__ float msl[kPrepTiles];
+    const int t = threadIdx.x;
+    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kPrepTiles;
+    const int64_t s0 = static_cast<int64_t>(blockIdx.y) * kPrepStates;
+    constexpr int F4 = kPrepCols / 4;  // 16-byte pieces per state row
+    constexpr int LR = (kPrepStates * F4 + 255) / 256;
+    float4 v[LR];
+#pragma unroll
+    for (int r = 0; r < LR; ++r) {
+        const int f = t + 256 * r, i = f / F4, m = f % F4;
+        v[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (f < kPrepStates * F4 && s0 + i < B) v[r] = *reinterpret_cast<const float4*>(Y + (s0 + i) * ld + 3 * b0 + 4 * m);
     }
+    if (t < kPrepTiles && b0 + t < n) msl[t] = Ms[b0 + t] * inv_ref;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < LR; ++r) {
+        const int f = t + 256 * r, i = f / F4, m = f % F4;
+        if (f >= kPrepStates * F4) continue;
+        const float vv[4] = {v[r].x, v[r].y, v[r].z, v[r].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = 4 * m + e;
+            tile[i][c] = b0 + c / 3 < n ? vv[e] * msl[c / 3] : 0.0f;
+        }
+    }
+    __syncthreads();
     const int64_t np = ld / 3;
-    const int64_t b = cblk ? k % np : k / 3;
-    const int64_t y = cblk ? 3 * b + k / np : k;  // the element of the tile-order state
-    const float v = (s < B && b < n) ? Y[s * ld + y] * (Ms[b] * inv_ref) : 0.0f;
+    const int64_t cs = ns * KC;  // elements of one chunk
+    // K chunk and LDS column of chunk-local column kk of output chunk j
+    auto chunk = [&](int j) { return cblk ? (j * np + b0) / KC : 3 * b0 / KC + j; };
+    auto col = [&](int j, int kk) { return cblk ? 3 * kk + j : KC * j + kk; };
     if constexpr (PREC == 0) {
-        static_cast<float*>(xh)[i] = v;
-    } else if constexpr (PREC == 1) {
-        const __bf16 h = static_cast<__bf16>(v);
-        static_cast<__bf16*>(xh)[i] = h;
-        static_cast<__bf16*>(xl)[i] = static_cast<__bf16>(v - static_cast<float>(h));
+        // float32: the workgroup's states are 16-state tile st = blockIdx.y; 256 float4 pieces per chunk
+        const int64_t nt = ns / 16, st = blockIdx.y;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int pc = t + 256 * r, j = pc / 256, w = pc % 256;
+            const int sub = w / 64, g = (w % 64) / 16, jj = w % 16, kk = 16 * sub + 4 * g;
+            const float4 o = make_float4(tile[jj][col(j, kk)], tile[jj][col(j, kk + 1)], tile[jj][col(j, kk + 2)],
+                                         tile[jj][col(j, kk + 3)]);
+            *reinterpret_cast<float4*>(static_cast<float*>(xh) + chunk(j) * cs + ((sub * nt + st) * 64 + 16 * g + jj) * 4) = o;
+        }
     } else {
-        const _Float16 h = static_cast<_Float16>(v);
-        static_cast<_Float16*>(xh)[i] = h;
-        static_cast<_Float16*>(xl)[i] = static_cast<_Float16>(v - static_cast<float>(h));
+        // split forms: the workgroup's states are half h of 32-state tile st; 128 pieces per chunk
+        using T = typename Elt<PREC>::T;
+        using AV = typename Elt<PREC>::V;
+        const int64_t nt = ns / 32, st = blockIdx.y / 2;
+        const int h = blockIdx.y % 2;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int pc = t + 256 * r;
+            if (pc >= 3 * 128) break;
+            const int j = pc / 128, w = pc % 128;
+            const int ks = w / 32, q = (w % 32) / 16, il = w % 16, kk = 16 * ks + 8 * q;
+            AV hi, lo;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float x = tile[il][col(j, kk + e)];
+                const T hv = static_cast<T>(x);
+                hi[e] = hv;
+                lo[e] = static_cast<T>(x - static_cast<float>(hv));
+            }
+            const int64_t o = chunk(j) * cs + ((ks * nt + st) * 64 + 32 * q + 16 * h + il) * 8;
+            *reinterpret_cast<AV*>(static_cast<T*>(xh) + o) = hi;
+            *reinterpret_cast<AV*>(static_cast<T*>(xl) + o) = lo;
+        }
     }
 }
+
+// Right-operand element (state s, column k) of value v in the product's
+// fragment order (the k_prep layout; ns states padded).
+template <int PREC>
+__device__ inline void frag_store(void* xh, void* xl, int64_t ns, int64_t k, int64_t s, float v) {
+    const int64_t kc = k / KC;
+    const int kk = static_cast<int>(k % KC);
+    if constexpr (PREC == 0) {
+        const int64_t nt = ns / 16, st = s / 16;
+        const int j = static_cast<int>(s % 16), sub = kk / 16, g = (kk % 16) / 4, e = kk % 4;
+        static_cast<float*>(xh)[kc * ns * KC + ((sub * nt + st) * 64 + 16 * g + j) * 4 + e] = v;
+    } else {
+        using T = typename Elt<PREC>::T;
+        const int64_t nt = ns / 32, st = s / 32;
+        const int i = static_cast<int>(s % 32), ks = kk / 16, q = (kk % 16) / 8, e = kk % 8;
+        const int64_t o = kc * ns * KC + ((ks * nt + st) * 64 + 32 * q + i) * 8 + e;
+        const T h = static_cast<T>(v);
+        static_cast<T*>(xh)[o] = h;
+        static_cast<T*>(xl)[o] = static_cast<T>(v - static_cast<float>(h));
+    }
+}
+
+// Where a stage writes the right operand of its output (the next stage's
+// input) as well: the fragment arrays, the padded state count and 1 / Ms_ref.
+struct FragOut {
+    void* xh = nullptr;
+    void* xl = nullptr;
+    int64_t ns = 0;
+    float inv = 0.0f;
+};
 
 // Sum of the split-K partials in fixed order, then the per-tile finish.
 // Rows are in component order for the component-blocked operator (row
 // i np + a holds component i of tile a), else in tile order (3 a + i).
 // splits_z: the partials of the z rows of the component-blocked operator
-// (= splits in the dense form).
-template <Epi MODE>
+// (= splits in the dense form).  A stage launch with F.xh set also writes
+// its output's right operand, the values k_prep would make of it, so that
+// the next stage's product needs no k_prep.
+template <Epi MODE, int PREC>
 __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __restrict__ part,
                                                 int64_t splits, int64_t splits_z, int64_t bpad, int64_t rows,
                                                 bool cblk, float scale, const float* __restrict__ X, int64_t sx,
-                                                EpiArgs E) {
+                                                EpiArgs E, FragOut F) {
     const int s = blockIdx.y;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     rk4_last_stage_control<MODE>(E);
@@ -541,6 +616,18 @@ __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __res
             if (sp < splits_z) h2 += pp[2 * rs];
         }
         finish_tile<MODE>(P, X, sx, E, s, a, -scale * h0, -scale * h1, -scale * h2, &rmax, &dmax);
+        if constexpr (MODE == Epi::STAGE) {
+            if (F.xh) {
+                // this thread's own stores of the stage output, read back
+                const float* yn = E.ynext + static_cast<int64_t>(s) * sx + 3 * static_cast<int64_t>(a);
+                const float w = P.Ms[a] * F.inv;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int64_t k = cblk ? c * static_cast<int64_t>(P.np) + a : 3 * static_cast<int64_t>(a) + c;
+                    frag_store<PREC>(F.xh, F.xl, F.ns, k, s, yn[c] * w);
+                }
+            }
+        }
     }
     if constexpr (MODE == Epi::DP_LAST) {
         __shared__ double red[2][4];
@@ -645,10 +732,19 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
                "batched product: workspace has no right-operand buffer");
     const int prec = T->prec == TM_PREC_FP32 ? 0 : T->prec == TM_PREC_BF16X3 ? 1 : 2;
     const int64_t ld = T->ld;
-    // right operand, in fragment order
-    {
-        const int64_t cnt = ns * ld;
-        const unsigned grid = static_cast<unsigned>((cnt + 255) / 256);
+    // stage buffers with a right-operand copy of their own
+    auto frag_slot = [&](const float* y) { return y == w->ya ? 0 : y == w->yb ? 1 : y == w->y5 ? 2 : -1; };
+    const int fin = frag_slot(X);
+    const bool ready = w->frag_chain && fin >= 0 && w->frag_src == X && w->fxh[fin];
+    w->frag_chain = false;
+    const void* xin_h = ready ? w->fxh[fin] : w->xh;
+    const void* xin_l = ready ? w->fxl[fin] : w->xl;
+    // right operand, in fragment order, unless the stage that wrote X made it
+    if (!ready) {
+        TM_REQUIRE(ld % (3 * kPrepTiles) == 0, TM_EINVAL, "batched product: K extent %lld is not whole tile groups",
+                   static_cast<long long>(ld));
+        const dim3 grid(static_cast<unsigned>(ld / (3 * kPrepTiles)),
+                        static_cast<unsigned>((ns + kPrepStates - 1) / kPrepStates));
         const float inv = static_cast<float>(1.0 / p->ms_ref);
         const int32_t n32 = static_cast<int32_t>(p->n);
         if (prec == 0)
@@ -665,8 +761,8 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     G.Ahi = T->data;
     G.Alo = T->lo;
     G.rscale = T->rscale;
-    G.Xhi = w->xh;
-    G.Xlo = w->xl;
+    G.Xhi = xin_h;
+    G.Xlo = xin_l;
     G.part = w->part;
     G.rows = T->rows;
     G.np = ld / 3;
@@ -692,14 +788,30 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     const DevProblem P = p->dev();
     const dim3 grid(static_cast<unsigned>((p->n + 255) / 256), static_cast<unsigned>(B));
     const int64_t sx = 3 * p->np;
-    switch (mode) {
-        case Epi::HD: k_finish<Epi::HD><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
-        case Epi::HEFF: k_finish<Epi::HEFF><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
-        case Epi::DMDT: k_finish<Epi::DMDT><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
-        case Epi::STAGE: k_finish<Epi::STAGE><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
-        case Epi::RK4_FINAL: k_finish<Epi::RK4_FINAL><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
-        case Epi::DP_LAST: k_finish<Epi::DP_LAST><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e); break;
+    // a stage whose output is ya, yb or y5 writes that output's right operand too
+    FragOut F;
+    const int fout = mode == Epi::STAGE ? frag_slot(e.ynext) : -1;
+    if (fout >= 0 && w->fxh[fout]) {
+        F.xh = w->fxh[fout];
+        F.xl = w->fxl[fout];
+        F.ns = ns;
+        F.inv = static_cast<float>(1.0 / p->ms_ref);
     }
+    auto fin_p = [&](auto pc) {
+        constexpr int PC = decltype(pc)::value;
+        switch (mode) {
+            case Epi::HD: k_finish<Epi::HD, PC><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
+            case Epi::HEFF: k_finish<Epi::HEFF, PC><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
+            case Epi::DMDT: k_finish<Epi::DMDT, PC><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
+            case Epi::STAGE: k_finish<Epi::STAGE, PC><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
+            case Epi::RK4_FINAL: k_finish<Epi::RK4_FINAL, PC><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
+            case Epi::DP_LAST: k_finish<Epi::DP_LAST, PC><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
+        }
+    };
+    if (prec == 0) fin_p(std::integral_constant<int, 0>{});
+    else if (prec == 1) fin_p(std::integral_constant<int, 1>{});
+    else fin_p(std::integral_constant<int, 2>{});
+    w->frag_src = F.xh ? e.ynext : nullptr;
     TM_TRY_HIP(hipGetLastError());
     return TM_OK;
 }

@@ -136,11 +136,13 @@ tm_status dp_attempt(const Problem* p, Workspace* w, int64_t B, hipStream_t s) {
         double c[7];
         for (int j = 0; j <= st; ++j) c[j] = kDpA[st + 1][j];
         EpiArgs e = stage_args(w, w->k[st], kp, st, c, nxt[st]);
+        w->frag_chain = st >= 2;  // stage 2 reads the committed attempt's input
         tm_status r = launch_field(p, Epi::STAGE, B, in[st], e, s);
         if (r != TM_OK) return r;
     }
     const double none[7] = {0, 0, 0, 0, 0, 0, 0};
     EpiArgs e = stage_args(w, w->k[6], kp, 6, none, nullptr);
+    w->frag_chain = true;
     tm_status r = launch_field(p, Epi::DP_LAST, B, w->y5, e, s);
     if (r != TM_OK) return r;
     return launch_commit(p, w, B, s);  // step control fused into the commit pass
@@ -174,10 +176,13 @@ tm_status rk4_attempt(const Problem* p, Workspace* w, int64_t B, int renorm, con
     };
     tm_status r;
     EpiArgs e1 = with_ctl(stage_args(w, w->k[0], nullptr, 0, half, w->ya));
+    w->frag_chain = false;
     if ((r = launch_field(p, Epi::STAGE, B, w->y, e1, s)) != TM_OK) return r;
     EpiArgs e2 = with_ctl(stage_args(w, w->k[1], nullptr, 0, half, w->yb));
+    w->frag_chain = true;  // stages 2, 3 and 4 read the previous stage's output
     if ((r = launch_field(p, Epi::STAGE, B, w->ya, e2, s)) != TM_OK) return r;
     EpiArgs e3 = with_ctl(stage_args(w, w->k[2], nullptr, 0, one, w->ya));
+    w->frag_chain = true;
     if ((r = launch_field(p, Epi::STAGE, B, w->yb, e3, s)) != TM_OK) return r;
     const double fin[4] = {1.0 / 6, 2.0 / 6, 2.0 / 6, 1.0 / 6};
     EpiArgs e4 = with_ctl(stage_args(w, nullptr, kp, 3, fin, nullptr));
@@ -189,6 +194,7 @@ tm_status rk4_attempt(const Problem* p, Workspace* w, int64_t B, int renorm, con
         e4.rk_steps_out = out->steps;
         e4.rk_flags_out = out->flags;
     }
+    w->frag_chain = true;
     if ((r = launch_field(p, Epi::RK4_FINAL, B, w->ya, e4, s)) != TM_OK) return r;
     return out ? TM_OK : launch_control(w, B, TM_RK4, s);
 }
