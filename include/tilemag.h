@@ -389,9 +389,11 @@ tm_status tm_problem_set_shape(tm_problem* p, int32_t shape);
  * six-plane stage kernel (SYM6) the candidates are its launch shapes and
  * chosen is the shape kept.  For a DENSE9 operator in FP32 / BF16X3 / FP16X3
  * (the batched product) the candidates are the numbers of K splits (2, 3, 4,
- * 5, 6, 8) and chosen is the split count kept; the split count sets the
- * summation order, so results are bitwise reproducible for a fixed count and
- * independent of the batch.  For PSYM6 / PSYM4 it times the evaluation with
+ * 5, 6, 8) and, for a single layer of tiles (component-blocked operator),
+ * the aligned work plans 100 + nq (K in nq super-ranges, nq = 2 .. 8 where
+ * nq divides the z columns' chunk count and the z row blocks pair up), and
+ * chosen is the choice kept; it sets the summation order, so results are
+ * bitwise reproducible for a fixed choice and independent of the batch.  For PSYM6 / PSYM4 it times the evaluation with
  * cached (chosen = 0) and with nontemporal (chosen = 1) operator loads in the
  * tile pass and keeps the faster (the results are the same either way).  For
  * the other operators (one kernel shape each) it only times that kernel and
@@ -405,7 +407,7 @@ tm_status tm_problem_tune(tm_problem* p, int64_t B, int32_t iters, hipStream_t s
                           int32_t* chosen, double* best_ms);
 
 /* Applies a choice as tm_problem_tune reports it, without timing: a launch
- * shape for SYM6, a K-split count for the batched DENSE9 product, 0 / 1
+ * shape for SYM6, a K-split count or aligned plan for the batched DENSE9 product, 0 / 1
  * (cached / nontemporal operator loads) for PSYM6 / PSYM4.  For reproducing
  * a known configuration (a profiling run, another process) exactly.
  * TM_EINVAL if the choice is not a candidate for p (nothing changes then). */

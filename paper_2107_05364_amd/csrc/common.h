@@ -363,6 +363,11 @@ int gemm_state_tiles(int64_t B);
 // (float32: 16 x {1, 2, 4, 8}; the split forms: 32 x {1, 2, 4}).
 int64_t gemm_state_pad(const Tensor* T, int64_t B);
 int64_t gemm_splits(const Problem* p);
+// Batched product: choices from kGemmAligned on are the aligned work plan
+// with choice - kGemmAligned K super-ranges (component-blocked operators
+// whose parts fit it); the plan's super-range count, else 0.
+constexpr int kGemmAligned = 100;
+int gemm_aligned_nq(const Problem* p, int choice);
 tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const float* X,
                                const EpiArgs& e, hipStream_t s);
 constexpr int64_t kMaxGemmStates = 128;

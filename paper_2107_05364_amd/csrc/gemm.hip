@@ -32,6 +32,7 @@
 #include <hip/hip_fp16.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "common.h"
 #include "epilogue.h"
@@ -63,6 +64,11 @@ struct GemmArgs {
     // work items: the first rb2 row blocks take splits_xy K splits, the
     // others (the z rows of the component-blocked form) splits_z
     int64_t rowblocks, rb2, splits_xy, splits_z;
+    // aligned plan (component-blocked form, nq > 0): K cut into nq
+    // super-ranges, x/y rows in parts of px chunks, z rows in parts of pz =
+    // px / 2; an item is one x/y part or two z parts (of consecutive z row
+    // blocks) of one super-range, items numbered super-range by super-range
+    int64_t nq, px, pz;
 };
 
 // Work items in split-major order: the row blocks of split 0, then of split
@@ -115,6 +121,137 @@ __device__ inline void row_block_k(const GemmArgs& G, int64_t rb, int64_t* k0, i
     }
 }
 
+// What a workgroup multiplies: one or two segments of consecutive stored
+// blocks and K chunks; chunk c of the item is block blkA + c at K chunk
+// kcA + c for c < lenA, else block blkB + (c - lenA) at K chunk kcB +
+// (c - lenA).  Each segment is summed into partial-sum slot slotA / slotB of
+// its row block rbA / rbB.
+struct GemmWork {
+    int64_t blkA, kcA, blkB, kcB, rbA, rbB;
+    int32_t lenA, len, slotA, slotB;
+};
+
+// Work of workgroup bid (false past the last item; XCD order as gemm_item).
+__device__ inline bool gemm_work(const GemmArgs& G, int64_t bid, GemmWork* w) {
+    if (G.nq == 0) {
+        int64_t rb, sp;
+        if (!gemm_item(G, bid, &rb, &sp)) return false;
+        int64_t kfirst, klast, rbase;
+        row_block_k(G, rb, &kfirst, &klast, &rbase);
+        const int64_t kb = kfirst + sp * G.kper;
+        const int64_t ke = min(kb + G.kper, klast);
+        // a split past the row block's K range adds nothing: it writes zero partials
+        const int32_t nch = ke > kb ? static_cast<int32_t>((ke - kb) / KC) : 0;
+        w->blkA = rbase / kBlockElems + (nch > 0 ? (kb - kfirst) / KC : 0);
+        w->kcA = (nch > 0 ? kb : kfirst) / KC;
+        w->rbA = rb;
+        w->slotA = static_cast<int32_t>(sp);
+        w->lenA = w->len = nch;
+        w->blkB = w->blkA;
+        w->kcB = w->kcA;
+        w->rbB = rb;
+        w->slotB = w->slotA;
+        return true;
+    }
+    const int64_t zrb = G.rowblocks - G.rb2;
+    const int64_t per_q = G.rb2 + zrb / 2;  // items per super-range
+    const int64_t total = G.nq * per_q;
+    const int64_t per = (total + kXcds - 1) / kXcds;
+    const int64_t item = (bid % kXcds) * per + bid / kXcds;
+    if (item >= total) return false;
+    const int64_t q = item / per_q, r = item % per_q;
+    const int64_t kc2 = 2 * G.np / KC, kz = G.np / KC;
+    w->slotA = w->slotB = static_cast<int32_t>(q);
+    if (r < G.rb2) {
+        w->rbA = w->rbB = r;
+        w->kcA = w->kcB = q * G.px;
+        w->blkA = w->blkB = r * kc2 + q * G.px;
+        w->lenA = w->len = static_cast<int32_t>(G.px);
+    } else {
+        const int64_t z = G.rb2 + 2 * (r - G.rb2);  // first of the item's two z row blocks
+        w->rbA = z;
+        w->rbB = z + 1;
+        w->kcA = w->kcB = kc2 + q * G.pz;
+        w->blkA = G.rb2 * kc2 + (z - G.rb2) * kz + q * G.pz;
+        w->blkB = w->blkA + kz;
+        w->lenA = static_cast<int32_t>(G.pz);
+        w->len = static_cast<int32_t>(2 * G.pz);
+    }
+    return true;
+}
+
+// Calls f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>) in turn.
+template <typename F, int... I>
+__device__ inline void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ inline void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// The work loop of both products over the item's chunks c = 0 .. len - 1,
+// chunk c multiplied from register ring slot c mod R.  Per chunk: the X tile
+// of chunk c + 1 and the operator rows of chunk c + R - 1 are requested, the
+// products of chunk c run (operator rows from the ring, X from LDS buffer
+// c mod 2), the X tile goes to LDS buffer (c + 1) mod 2 (which no wave reads
+// any more: all passed the barrier after chunk c - 1), one barrier.  Near
+// the end the loads repeat the last chunk instead of branching, so that the
+// wait counts stay exact.  The addresses of a chunk come from gemm_work's
+// segments by a select, so that the requests run ahead across the segment
+// boundary; the loop itself is split there: flush(rb, slot) writes a
+// segment's partial sums and clears the accumulators between the two loops
+// (segment B enters its loop at ring slot lenA mod R), without a branch per
+// chunk and without draining the pipeline.
+template <int R, typename LX, typename LA, typename CP, typename SX, typename FL>
+__device__ inline void gemm_run(const GemmWork& W, LX&& load_x, LA&& load_a, CP&& compute, SX&& store_x,
+                                FL&& flush) {
+    const int last = W.len - 1;
+    auto step = [&](auto slot, int c) {
+        constexpr int S = decltype(slot)::value;
+        load_x(min(c + 1, last));
+        load_a(std::integral_constant<int, (S + R - 1) % R>{}, min(c + R - 1, last));
+        compute(slot, c & 1);
+        // the X tile goes to LDS after the products: a store moved up among
+        // them (the four-slot ring's schedule does that) waits for its load
+        // right away
+        __builtin_amdgcn_sched_barrier(0);
+        store_x((c + 1) & 1);
+        __syncthreads();
+    };
+    // chunks [c0, c1): a head up to the next multiple of R (branches once
+    // per segment), then whole rounds of the ring, then the tail
+    auto run = [&](int c0, int c1) {
+        int c = c0;
+        static_for<R - 1>([&](auto k) {
+            constexpr int S = decltype(k)::value + 1;
+            if (c < c1 && c % R == S) {
+                step(std::integral_constant<int, S>{}, c);
+                ++c;
+            }
+        });
+        for (; c + R <= c1; c += R) static_for<R>([&](auto k) { step(k, c + decltype(k)::value); });
+        static_for<R - 1>([&](auto k) {
+            if (c + decltype(k)::value < c1) step(k, c + decltype(k)::value);
+        });
+    };
+    if (W.len > 0) {
+        load_x(0);
+        static_for<R - 1>([&](auto k) { load_a(k, min(static_cast<int>(decltype(k)::value), last)); });
+        store_x(0);
+        __syncthreads();
+    }
+    if (W.lenA < W.len) {
+        run(0, W.lenA);
+        flush(W.rbA, W.slotA);
+        run(W.lenA, W.len);
+        flush(W.rbB, W.slotB);
+    } else {
+        run(0, W.len);
+        flush(W.rbA, W.slotA);
+    }
+}
+
 template <int PREC>
 struct Elt;
 template <>
@@ -136,116 +273,94 @@ __device__ inline v16f mfma_split(const AV& a, const AV& b, const v16f& c) {
     else return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
-// Software pipeline per K chunk c: the operator rows of chunk c+2 and the X
-// tile of chunk c+1 are loaded into registers while the MFMAs of chunk c run
-// (operator rows from ring slot c % 3, X from LDS buffer c & 1); the X tile
-// then goes to buffer (c+1) & 1, which no wave reads any more (all passed the
-// barrier after chunk c-1).  One barrier per chunk.  One wave per SIMD (the
-// register file holds three chunks of operator rows); the MFMAs sweep the
-// independent accumulators so that none waits for its predecessor.
-template <int PREC, int NST>
+// FP32 product on 16x16x4 MFMAs: a workgroup (4 waves) owns 128 operator
+// rows at a time, wave w two 16-row tiles, x all NST 16-state tiles, over
+// its work (gemm_work, gemm_run).  One wave per SIMD (the register file
+// holds R chunks of operator rows); the MFMAs sweep the independent
+// accumulators so that none waits for its predecessor.
+template <int PREC, int NST, int R>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_gemm(GemmArgs G) {
     static_assert(PREC == 0, "the split forms use k_gemm_split");
     using T = typename Elt<PREC>::T;
     using AV = typename Elt<PREC>::V;
-    constexpr bool SPLIT = PREC != 0;
     constexpr int VEC = Elt<PREC>::kVec;
     constexpr int NSUB = KC / (4 * VEC);                       // MFMA K steps per chunk
     constexpr int NS = NST * 16;
     constexpr int XB = NS * KC * static_cast<int>(sizeof(T));  // bytes of one X array per chunk
     constexpr int XPIECES = XB / 16;
-    constexpr int XPT = (XPIECES + 255) / 256;                 // 16-byte pieces per thread and array
-    constexpr int BUF = XB * (SPLIT ? 2 : 1);
-    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
+    constexpr int XPT = (XPIECES + 255) / 256;                 // 16-byte pieces per thread
+    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * XB];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, j = lane & 15;
-    int64_t rb, sp;
-    if (!gemm_item(G, blockIdx.x, &rb, &sp)) return;
-    const int64_t rowbase = rb * kGemmRows + wave * 32;
-    int64_t kfirst, klast, rbase;
-    row_block_k(G, rb, &kfirst, &klast, &rbase);
-    const int64_t kb = kfirst + sp * G.kper;
-    const int64_t ke = min(kb + G.kper, klast);
-    // a split past the row block's K range adds nothing: it writes zero partials
-    const int nch = ke > kb ? static_cast<int>((ke - kb) / KC) : 0;
-    const int64_t kc0 = (nch > 0 ? kb : kfirst) / KC;
-
-    // this workgroup's first operator block and this lane's place in a block
-    const int64_t ablk = rbase + (kc0 - kfirst / KC) * kBlockElems;
-    const T* Ah = static_cast<const T*>(G.Ahi) + ablk;
-    const T* Al = SPLIT ? static_cast<const T*>(G.Alo) + ablk : nullptr;
-    const unsigned char* Xh = static_cast<const unsigned char*>(G.Xhi) + kc0 * XB;
-    const unsigned char* Xl = SPLIT ? static_cast<const unsigned char*>(G.Xlo) + kc0 * XB : nullptr;
+    GemmWork W;
+    if (!gemm_work(G, blockIdx.x, &W)) return;
+    const T* Ah = static_cast<const T*>(G.Ahi);
+    const unsigned char* Xh = static_cast<const unsigned char*>(G.Xhi);
+    auto blk_of = [&](int c) { return c < W.lenA ? W.blkA + c : W.blkB + (c - W.lenA); };
+    auto kc_of = [&](int c) { return c < W.lenA ? W.kcA + c : W.kcB + (c - W.lenA); };
 
     v4f acc[2][NST];
+    auto zero = [&]() {
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+        for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int s = 0; s < NST; ++s) acc[r][s] = v4f{0.f, 0.f, 0.f, 0.f};
+            for (int s = 0; s < NST; ++s) acc[r][s] = v4f{0.f, 0.f, 0.f, 0.f};
+    };
+    zero();
 
-    v4u xh_r[XPT], xl_r[XPT];
-    // operator rows of three chunks: the one being multiplied and the next two in flight
-    AV ah[3][NSUB][2], al[3][NSUB][2];
+    v4u xh_r[XPT];
+    // operator rows of R chunks: the one being multiplied and the next in flight
+    AV ah[R][NSUB][2];
 
     auto load_x = [&](int c) {
+        const int64_t base = kc_of(c) * XB;
 #pragma unroll
         for (int q = 0; q < XPT; ++q) {
             const int idx = threadIdx.x + 256 * q;
-            if (XPIECES % 256 == 0 || idx < XPIECES) {
-                const int64_t off = static_cast<int64_t>(c) * XB + 16 * idx;
-                xh_r[q] = *reinterpret_cast<const v4u*>(Xh + off);
-                if constexpr (SPLIT) xl_r[q] = *reinterpret_cast<const v4u*>(Xl + off);
-            }
+            if (XPIECES % 256 == 0 || idx < XPIECES) xh_r[q] = *reinterpret_cast<const v4u*>(Xh + base + 16 * idx);
         }
     };
     auto store_x = [&](int buf) {
-        unsigned char* base = lds + buf * BUF;
+        unsigned char* base = lds + buf * XB;
 #pragma unroll
         for (int q = 0; q < XPT; ++q) {
             const int idx = threadIdx.x + 256 * q;
-            if (XPIECES % 256 == 0 || idx < XPIECES) {
-                *reinterpret_cast<v4u*>(base + 16 * idx) = xh_r[q];
-                if constexpr (SPLIT) *reinterpret_cast<v4u*>(base + XB + 16 * idx) = xl_r[q];
-            }
+            if (XPIECES % 256 == 0 || idx < XPIECES) *reinterpret_cast<v4u*>(base + 16 * idx) = xh_r[q];
         }
     };
     // chunk rows go to ring slot S (a compile-time index, so the ring stays in registers)
     auto load_a = [&](auto slot, int c) {
         constexpr int S = decltype(slot)::value;
-        const int64_t cb = static_cast<int64_t>(c) * kBlockElems;
+        const int64_t cb = blk_of(c) * kBlockElems;
 #pragma unroll
         for (int sub = 0; sub < NSUB; ++sub)
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt) {
                 const int64_t off = cb + static_cast<int64_t>(((wave * NSUB + sub) * 2 + rt) * 64 + lane) * VEC;
                 ah[S][sub][rt] = *reinterpret_cast<const AV*>(Ah + off);
-                if constexpr (SPLIT) al[S][sub][rt] = *reinterpret_cast<const AV*>(Al + off);
             }
     };
     auto compute = [&](auto slot, int buf) {
         constexpr int S = decltype(slot)::value;
         const auto& hi = ah[S];
-        const auto& lo = al[S];
-        const unsigned char* xs = lds + buf * BUF;
+        const unsigned char* xs = lds + buf * XB;
 #pragma unroll
         for (int sub = 0; sub < NSUB; ++sub) {
-            if constexpr (PREC == 0) {
-                float4 b[NST];
+            float4 b[NST];
+#pragma unroll
+            for (int st = 0; st < NST; ++st)
+                b[st] = *reinterpret_cast<const float4*>(xs + ((sub * NST + st) * 64 + lane) * 16);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int st = 0; st < NST; ++st)
-                    b[st] = *reinterpret_cast<const float4*>(xs + ((sub * NST + st) * 64 + lane) * 16);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int st = 0; st < NST; ++st)
-#pragma unroll
-                        for (int rt = 0; rt < 2; ++rt) {
-                            const float av = q == 0 ? hi[sub][rt].x : q == 1 ? hi[sub][rt].y : q == 2 ? hi[sub][rt].z : hi[sub][rt].w;
-                            const float bv = q == 0 ? b[st].x : q == 1 ? b[st].y : q == 2 ? b[st].z : b[st].w;
-                            acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[rt][st], 0, 0, 0);
-                        }
-            }
+                    for (int rt = 0; rt < 2; ++rt) {
+                        const float av = q == 0 ? hi[sub][rt].x : q == 1 ? hi[sub][rt].y : q == 2 ? hi[sub][rt].z : hi[sub][rt].w;
+                        const float bv = q == 0 ? b[st].x : q == 1 ? b[st].y : q == 2 ? b[st].z : b[st].w;
+                        acc[rt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[rt][st], 0, 0, 0);
+                    }
         }
         // the next chunks' global loads (issued above in program order) are
         // spread over the products so that they co-issue with the MFMAs
@@ -257,63 +372,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);          // VMEM read
         }
     };
-
-    // Near the end the loads repeat the last chunk instead of branching, so
-    // that the wait counts stay exact: each multiply waits for its own
-    // operator rows only.
-    using S0 = std::integral_constant<int, 0>;
-    using S1 = std::integral_constant<int, 1>;
-    using S2 = std::integral_constant<int, 2>;
-    const int last = nch - 1;
-    auto step = [&](auto slot, int c) {
-        constexpr int S = decltype(slot)::value;
-        load_x(min(c + 1, last));
-        load_a(std::integral_constant<int, (S + 2) % 3>{}, min(c + 2, last));
-        compute(slot, c & 1);
-        store_x((c + 1) & 1);
-        __syncthreads();
+    // D[4 g + r][j] of tile (rt, st) -> part[slot][state 16 st + j][row 128 rb + 32 wave + 16 rt + 4 g + r]
+    auto flush = [&](int64_t rb, int32_t slot) {
+        float* out = G.part + slot * G.bpad * G.rows;
+        const int64_t rowbase = rb * kGemmRows + wave * 32;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            const int64_t r0 = rowbase + 16 * rt + 4 * g;
+#pragma unroll
+            for (int st = 0; st < NST; ++st) {
+                const v4f v = acc[rt][st];
+                *reinterpret_cast<float4*>(out + (16 * st + j) * G.rows + r0) = make_float4(v.x, v.y, v.z, v.w);
+            }
+        }
+        zero();
     };
-    if (nch > 0) {
-        load_x(0);
-        load_a(S0{}, 0);
-        load_a(S1{}, min(1, last));
-        store_x(0);
-        __syncthreads();
-        int c = 0;
-        for (; c + 3 <= nch; c += 3) {
-            step(S0{}, c);
-            step(S1{}, c + 1);
-            step(S2{}, c + 2);
-        }
-        if (c < nch) step(S0{}, c);
-        if (c + 1 < nch) step(S1{}, c + 1);
-    }
-    // D[4 g + r][j] of tile (rt, st) -> part[split][state 16 st + j][row rowbase + 16 rt + 4 g + r]
-    float* out = G.part + sp * G.bpad * G.rows;
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-        const int64_t r0 = rowbase + 16 * rt + 4 * g;
-        float4 sc = make_float4(1.f, 1.f, 1.f, 1.f);
-        if constexpr (PREC == 2) sc = *reinterpret_cast<const float4*>(G.rscale + r0);
-#pragma unroll
-        for (int st = 0; st < NST; ++st) {
-            const v4f v = acc[rt][st];
-            *reinterpret_cast<float4*>(out + (16 * st + j) * G.rows + r0) =
-                make_float4(v.x * sc.x, v.y * sc.y, v.z * sc.z, v.w * sc.w);
-        }
-    }
+    gemm_run<R>(W, load_x, load_a, compute, store_x, flush);
 }
 
 // The split forms (BF16X3, FP16X3) on 32x32x16 MFMAs: a workgroup (4 waves)
-// owns 128 operator rows, wave w one 32-row tile, x all NSB 32-state tiles,
-// over one K range.  Per K chunk of 64 (four K steps of 16) a lane loads its
-// operator row's hi and lo halves for each step (16 bytes each, the blocked
-// order: 1 KB per wave load) and the B fragments from the LDS copy of the X
-// chunk.  Same pipeline as k_gemm: operator rows two chunks ahead in a
-// three-slot register ring, the X tile one chunk ahead through a
-// double-buffered LDS tile, one barrier per chunk; per K step three sweeps
+// owns 128 operator rows at a time, wave w one 32-row tile, x all NSB
+// 32-state tiles, over its work (gemm_work, gemm_run).  Per K chunk of 64
+// (four K steps of 16) a lane loads its operator row's hi and lo halves for
+// each step (16 bytes each, the blocked order: 1 KB per wave load) and the B
+// fragments from the LDS copy of the X chunk; per K step three sweeps
 // (hi hi, hi lo, lo hi) over the NSB independent accumulators.
-template <int PREC, int NSB>
+template <int PREC, int NSB, int R>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_gemm_split(GemmArgs G) {
     static_assert(PREC == 1 || PREC == 2, "split forms only");
     using T = typename Elt<PREC>::T;
@@ -327,38 +411,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int64_t rb, sp;
-    if (!gemm_item(G, blockIdx.x, &rb, &sp)) return;
-    const int64_t rowbase = rb * kGemmRows + wave * 32;
-    int64_t kfirst, klast, rbase;
-    row_block_k(G, rb, &kfirst, &klast, &rbase);
-    const int64_t kb = kfirst + sp * G.kper;
-    const int64_t ke = min(kb + G.kper, klast);
-    // a split past the row block's K range adds nothing: it writes zero partials
-    const int nch = ke > kb ? static_cast<int>((ke - kb) / KC) : 0;
-    const int64_t kc0 = (nch > 0 ? kb : kfirst) / KC;
-
-    const int64_t ablk = rbase + (kc0 - kfirst / KC) * kBlockElems;
-    const T* Ah = static_cast<const T*>(G.Ahi) + ablk;
-    const T* Al = static_cast<const T*>(G.Alo) + ablk;
-    const unsigned char* Xh = static_cast<const unsigned char*>(G.Xhi) + kc0 * XB;
-    const unsigned char* Xl = static_cast<const unsigned char*>(G.Xlo) + kc0 * XB;
+    GemmWork W;
+    if (!gemm_work(G, blockIdx.x, &W)) return;
+    const T* Ah = static_cast<const T*>(G.Ahi);
+    const T* Al = static_cast<const T*>(G.Alo);
+    const unsigned char* Xh = static_cast<const unsigned char*>(G.Xhi);
+    const unsigned char* Xl = static_cast<const unsigned char*>(G.Xlo);
+    auto blk_of = [&](int c) { return c < W.lenA ? W.blkA + c : W.blkB + (c - W.lenA); };
+    auto kc_of = [&](int c) { return c < W.lenA ? W.kcA + c : W.kcB + (c - W.lenA); };
 
     v16f acc[NSB];
+    auto zero = [&]() {
 #pragma unroll
-    for (int s = 0; s < NSB; ++s)
+        for (int s = 0; s < NSB; ++s)
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[s][e] = 0.0f;
+            for (int e = 0; e < 16; ++e) acc[s][e] = 0.0f;
+    };
+    zero();
 
     v4u xh_r[XPT], xl_r[XPT];
-    AV ah[3][KS], al[3][KS];
+    AV ah[R][KS], al[R][KS];
 
     auto load_x = [&](int c) {
+        const int64_t base = kc_of(c) * XB;
 #pragma unroll
         for (int q = 0; q < XPT; ++q) {
             const int idx = threadIdx.x + 256 * q;
             if (XPIECES % 256 == 0 || idx < XPIECES) {
-                const int64_t off = static_cast<int64_t>(c) * XB + 16 * idx;
+                const int64_t off = base + 16 * idx;
                 xh_r[q] = *reinterpret_cast<const v4u*>(Xh + off);
                 xl_r[q] = *reinterpret_cast<const v4u*>(Xl + off);
             }
@@ -377,7 +457,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     };
     auto load_a = [&](auto slot, int c) {
         constexpr int S = decltype(slot)::value;
-        const int64_t cb = static_cast<int64_t>(c) * kBlockElems;
+        const int64_t cb = blk_of(c) * kBlockElems;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int64_t off = cb + static_cast<int64_t>((wave * KS + ks) * 64 + lane) * 8;
@@ -421,48 +501,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);                            // VMEM read
         }
     };
-
-    using S0 = std::integral_constant<int, 0>;
-    using S1 = std::integral_constant<int, 1>;
-    using S2 = std::integral_constant<int, 2>;
-    const int last = nch - 1;
-    auto step = [&](auto slot, int c) {
-        constexpr int S = decltype(slot)::value;
-        load_x(min(c + 1, last));
-        load_a(std::integral_constant<int, (S + 2) % 3>{}, min(c + 2, last));
-        compute(slot, c & 1);
-        store_x((c + 1) & 1);
-        __syncthreads();
-    };
-    if (nch > 0) {
-        load_x(0);
-        load_a(S0{}, 0);
-        load_a(S1{}, min(1, last));
-        store_x(0);
-        __syncthreads();
-        int c = 0;
-        for (; c + 3 <= nch; c += 3) {
-            step(S0{}, c);
-            step(S1{}, c + 1);
-            step(S2{}, c + 2);
-        }
-        if (c < nch) step(S0{}, c);
-        if (c + 1 < nch) step(S1{}, c + 1);
-    }
-    // element 4 i + j of tile st -> part[split][state 32 st + l % 32][row rowbase + 8 i + 4 (l / 32) + j]
-    float* out = G.part + sp * G.bpad * G.rows;
+    // element 4 i + j of tile st -> part[slot][state 32 st + l % 32][row 128 rb + 32 wave + 8 i + 4 (l / 32) + j]
     const int col = lane & 31, h = lane >> 5;
+    auto flush = [&](int64_t rb, int32_t slot) {
+        float* out = G.part + slot * G.bpad * G.rows;
+        const int64_t rowbase = rb * kGemmRows + wave * 32;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int64_t r0 = rowbase + 8 * i + 4 * h;
-        float4 sc = make_float4(1.f, 1.f, 1.f, 1.f);
-        if constexpr (PREC == 2) sc = *reinterpret_cast<const float4*>(G.rscale + r0);
+        for (int i = 0; i < 4; ++i) {
+            const int64_t r0 = rowbase + 8 * i + 4 * h;
+            float4 sc = make_float4(1.f, 1.f, 1.f, 1.f);
+            if constexpr (PREC == 2) sc = *reinterpret_cast<const float4*>(G.rscale + r0);
 #pragma unroll
-        for (int st = 0; st < NSB; ++st)
-            *reinterpret_cast<float4*>(out + (32 * st + col) * G.rows + r0) =
-                make_float4(acc[st][4 * i] * sc.x, acc[st][4 * i + 1] * sc.y, acc[st][4 * i + 2] * sc.z,
-                            acc[st][4 * i + 3] * sc.w);
-    }
+            for (int st = 0; st < NSB; ++st)
+                *reinterpret_cast<float4*>(out + (32 * st + col) * G.rows + r0) =
+                    make_float4(acc[st][4 * i] * sc.x, acc[st][4 * i + 1] * sc.y, acc[st][4 * i + 2] * sc.z,
+                                acc[st][4 * i + 3] * sc.w);
+        }
+        zero();
+    };
+    gemm_run<R>(W, load_x, load_a, compute, store_x, flush);
 }
 
 // Right operand from the (padded) stage input Y [B][ld]: (Ms_b / Ms_ref) m,
@@ -649,31 +706,26 @@ __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __res
     }
 }
 
-// workgroups of the 1-D product grid (gemm_item): the items rounded up to a
+// workgroups of the 1-D product grid (gemm_work): the items rounded up to a
 // whole number per XCD
 inline unsigned gemm_items(const GemmArgs& G) {
-    const int64_t total = G.rb2 * G.splits_xy + (G.rowblocks - G.rb2) * G.splits_z;
+    const int64_t total = G.nq > 0 ? G.nq * (G.rb2 + (G.rowblocks - G.rb2) / 2)
+                                   : G.rb2 * G.splits_xy + (G.rowblocks - G.rb2) * G.splits_z;
     return static_cast<unsigned>((total + kXcds - 1) / kXcds * kXcds);
 }
 
-template <int PREC, int NST>
-tm_status launch_gemm_t(const GemmArgs& G, int64_t rowblocks, int64_t splits, hipStream_t s) {
-    (void)rowblocks;
-    (void)splits;
-    launch_op(k_gemm<PREC, NST>, dim3(gemm_items(G)), dim3(256), s, G);
-    TM_TRY_HIP(hipGetLastError());
-    return TM_OK;
+template <int PREC, int NST, int R>
+void launch_gemm_fp32(const GemmArgs& G, hipStream_t s) {
+    launch_op(k_gemm<PREC, NST, R>, dim3(gemm_items(G)), dim3(256), s, G);
 }
 
-template <int PREC>
-tm_status launch_gemm_split(int nsb, const GemmArgs& G, int64_t rowblocks, int64_t splits, hipStream_t s) {
-    (void)rowblocks;
-    (void)splits;
+template <int PREC, int R>
+tm_status launch_gemm_split(int nsb, const GemmArgs& G, hipStream_t s) {
     const dim3 grid(gemm_items(G));
     switch (nsb) {
-        case 1: launch_op(k_gemm_split<PREC, 1>, grid, dim3(256), s, G); break;
-        case 2: launch_op(k_gemm_split<PREC, 2>, grid, dim3(256), s, G); break;
-        case 4: launch_op(k_gemm_split<PREC, 4>, grid, dim3(256), s, G); break;
+        case 1: launch_op(k_gemm_split<PREC, 1, R>, grid, dim3(256), s, G); break;
+        case 2: launch_op(k_gemm_split<PREC, 2, R>, grid, dim3(256), s, G); break;
+        case 4: launch_op(k_gemm_split<PREC, 4, R>, grid, dim3(256), s, G); break;
         default:
             set_error("batched product: unsupported 32-state tile count %d", nsb);
             return TM_EINVAL;
@@ -682,17 +734,19 @@ tm_status launch_gemm_split(int nsb, const GemmArgs& G, int64_t rowblocks, int64
     return TM_OK;
 }
 
-template <int PREC>
-tm_status launch_gemm_p(int nst, const GemmArgs& G, int64_t rowblocks, int64_t splits, hipStream_t s) {
+template <int R>
+tm_status launch_gemm_p(int nst, const GemmArgs& G, hipStream_t s) {
     switch (nst) {
-        case 1: return launch_gemm_t<PREC, 1>(G, rowblocks, splits, s);
-        case 2: return launch_gemm_t<PREC, 2>(G, rowblocks, splits, s);
-        case 4: return launch_gemm_t<PREC, 4>(G, rowblocks, splits, s);
-        case 8: return launch_gemm_t<PREC, 8>(G, rowblocks, splits, s);
-        default: break;
+        case 1: launch_gemm_fp32<0, 1, R>(G, s); break;
+        case 2: launch_gemm_fp32<0, 2, R>(G, s); break;
+        case 4: launch_gemm_fp32<0, 4, R>(G, s); break;
+        case 8: launch_gemm_fp32<0, 8, R>(G, s); break;
+        default:
+            set_error("batched product: unsupported state-tile count %d", nst);
+            return TM_EINVAL;
     }
-    set_error("batched product: unsupported state-tile count %d", nst);
-    return TM_EINVAL;
+    TM_TRY_HIP(hipGetLastError());
+    return TM_OK;
 }
 
 }  // namespace
@@ -708,7 +762,19 @@ int64_t gemm_state_pad(const Tensor* T, int64_t B) {
     return 32 * (t <= 1 ? 1 : t <= 2 ? 2 : 4);
 }
 
+int gemm_aligned_nq(const Problem* p, int choice) {
+    const Tensor* T = p->T;
+    if (choice < kGemmAligned || !T->cblk) return 0;
+    const int64_t nq = choice - kGemmAligned, np = T->ld / 3;
+    const int64_t kz = np / KC, zrb = T->rows / kGemmRows - 2 * np / kGemmRows;
+    // whole parts in every super-range, z row blocks in pairs
+    const bool ok = nq >= 2 && nq <= 16 && kz % nq == 0 && zrb % 2 == 0;
+    return ok ? static_cast<int>(nq) : 0;
+}
+
 int64_t gemm_splits(const Problem* p) {
+    // the aligned plan sums one slot per super-range
+    if (const int nq = gemm_aligned_nq(p, p->gemm_splits)) return nq;
     const int64_t rowblocks = p->T->rows / kGemmRows;
     const int64_t kchunks = p->T->ld / KC;
     // about one workgroup per CU (one wave per SIMD), unless tuned
@@ -767,6 +833,9 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     G.rows = T->rows;
     G.np = ld / 3;
     G.cblk = T->cblk ? 1 : 0;
+    G.nq = gemm_aligned_nq(p, p->gemm_splits);
+    G.px = G.nq ? 2 * G.np / KC / G.nq : 0;
+    G.pz = G.px / 2;
     const int64_t splits = gemm_splits(p);
     TM_REQUIRE(splits <= w->part_splits, TM_EINVAL, "batched product: workspace holds %lld K splits, %lld asked",
                static_cast<long long>(w->part_splits), static_cast<long long>(splits));
@@ -779,9 +848,11 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     G.rb2 = T->cblk ? 2 * G.np / kGemmRows : rowblocks;
     G.splits_xy = used_splits;
     G.splits_z = T->cblk ? (G.np + G.kper - 1) / G.kper : used_splits;
-    tm_status st = prec == 0   ? launch_gemm_p<0>(static_cast<int>(ns / 16), G, rowblocks, used_splits, s)
-                   : prec == 1 ? launch_gemm_split<1>(static_cast<int>(ns / 32), G, rowblocks, used_splits, s)
-                               : launch_gemm_split<2>(static_cast<int>(ns / 32), G, rowblocks, used_splits, s);
+    // the finish adds the slots of the plan: nq per row for the aligned one
+    const int64_t fin_xy = G.nq ? G.nq : G.splits_xy, fin_z = G.nq ? G.nq : G.splits_z;
+    const int nst = static_cast<int>(ns / 16), nsb = static_cast<int>(ns / 32);
+    tm_status st = prec == 0 ? launch_gemm_p<3>(nst, G, s) : prec == 1 ? launch_gemm_split<1, 3>(nsb, G, s)
+                                                             : launch_gemm_split<2, 3>(nsb, G, s);
     if (st != TM_OK) return st;
     // X holds (Ms_b / Ms_ref) m (or m itself when Ms is uniform): H_d = -Ms_ref C
     const float scale = static_cast<float>(p->ms_ref);
@@ -800,12 +871,12 @@ tm_status launch_field_batched(const Problem* p, Epi mode, int64_t B, const floa
     auto fin_p = [&](auto pc) {
         constexpr int PC = decltype(pc)::value;
         switch (mode) {
-            case Epi::HD: k_finish<Epi::HD, PC><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
-            case Epi::HEFF: k_finish<Epi::HEFF, PC><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
-            case Epi::DMDT: k_finish<Epi::DMDT, PC><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
-            case Epi::STAGE: k_finish<Epi::STAGE, PC><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
-            case Epi::RK4_FINAL: k_finish<Epi::RK4_FINAL, PC><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
-            case Epi::DP_LAST: k_finish<Epi::DP_LAST, PC><<<grid, 256, 0, s>>>(P, w->part, used_splits, G.splits_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
+            case Epi::HD: k_finish<Epi::HD, PC><<<grid, 256, 0, s>>>(P, w->part, fin_xy, fin_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
+            case Epi::HEFF: k_finish<Epi::HEFF, PC><<<grid, 256, 0, s>>>(P, w->part, fin_xy, fin_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
+            case Epi::DMDT: k_finish<Epi::DMDT, PC><<<grid, 256, 0, s>>>(P, w->part, fin_xy, fin_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
+            case Epi::STAGE: k_finish<Epi::STAGE, PC><<<grid, 256, 0, s>>>(P, w->part, fin_xy, fin_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
+            case Epi::RK4_FINAL: k_finish<Epi::RK4_FINAL, PC><<<grid, 256, 0, s>>>(P, w->part, fin_xy, fin_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
+            case Epi::DP_LAST: k_finish<Epi::DP_LAST, PC><<<grid, 256, 0, s>>>(P, w->part, fin_xy, fin_z, w->bpad, T->rows, T->cblk, scale, X, sx, e, F); break;
         }
     };
     if (prec == 0) fin_p(std::integral_constant<int, 0>{});

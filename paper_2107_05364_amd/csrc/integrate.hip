@@ -667,7 +667,7 @@ bool apply_choice(Problem* p, TuneKind k, int c) {
     static const int kCand[] = {2, 3, 4, 5, 6, 8};
     switch (k) {
         case TuneKind::SPLITS: {
-            bool ok = false;
+            bool ok = gemm_aligned_nq(p, c) > 0;
             for (int q : kCand) ok = ok || (q == c && c <= p->T->ld / kGemmKC);
             if (!ok) return false;
             if (p->gemm_splits != c) drop_graphs(p);
@@ -728,6 +728,8 @@ extern "C" tm_status tm_problem_tune(tm_problem* pp, int64_t B, int32_t iters, h
     if (kind == TuneKind::SPLITS) {
         for (int c : {2, 3, 4, 5, 6, 8})
             if (c <= p->T->ld / kGemmKC) cand.push_back(c);
+        for (int q = 2; q <= 8; ++q)
+            if (gemm_aligned_nq(p, kGemmAligned + q)) cand.push_back(kGemmAligned + q);
     } else if (kind == TuneKind::LOADS) {
         cand = {0, 1};
     } else if (kind == TuneKind::SHAPES) {

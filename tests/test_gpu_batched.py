@@ -128,12 +128,14 @@ def test_tuned_split_count(tmg, ctx, orc, prec):
 @pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("mesh", ["film", "slab"])
 def test_every_split_count(tmg, ctx, orc, prec, mesh):
-    """Every K-split count the autotuner can pick (applied with
-    tm_problem_apply), on a single layer (component-blocked operator: the z
+    """Every work plan the autotuner can pick (applied with tm_problem_apply):
+    the K-split counts, on a single layer (component-blocked operator: the z
     rows take fewer splits, and some counts leave work items short of a whole
-    number per XCD) and on a three-layer mesh with per-tile Ms (dense form):
-    H_d against the oracle within the precision's tolerance, a repeat bitwise
-    identical."""
+    number per XCD) and on a three-layer mesh with per-tile Ms (dense form),
+    and on the single layer the aligned plans (choice 100 + super-ranges,
+    where the operator's parts fit them; items of two z parts whose
+    operator rows switch row block mid-item): H_d against the oracle within
+    the precision's tolerance, a repeat bitwise identical."""
     if mesh == "film":
         wl = W.thin_film(nx=40, ny=10)
         centers, sizes = wl.centers, wl.sizes
@@ -146,14 +148,23 @@ def test_every_split_count(tmg, ctx, orc, prec, mesh):
     m = np.stack([W.random_unit_vectors(60 + k, n) for k in range(37)]).astype(np.float32)
     Tref = orc.assemble(centers, sizes)
     want = [orc.demag(Tref, Ms, m[k].astype(np.float64)) for k in (0, 18, 36)]
-    for splits in (2, 3, 4, 5, 6, 8):
-        tmg.tm_problem_apply(p.handle, splits)
+    aligned = 0
+    for splits in (2, 3, 4, 5, 6, 8) + tuple(100 + q for q in range(2, 9)):
+        try:
+            tmg.tm_problem_apply(p.handle, splits)
+        except tmg.TilemagError:
+            assert splits >= 100, splits  # only aligned plans can be refused here
+            continue
+        aligned += splits >= 100
         H = p.demag(device_state(m)).cpu().numpy()
         for k, w in zip((0, 18, 36), want):
             e2, emax = rel_errors(H[k], w)
             assert e2 <= TOL[prec] and emax <= TOL[prec], (splits, k, e2, emax)
         assert np.array_equal(H, p.demag(device_state(m)).cpu().numpy()), splits
         _say("  %s %s, %d K splits ok" % (mesh, NAMES[prec], splits))
+    # the film (np = 512: 8 z chunks, 4 z row blocks) admits 2, 4 and 8
+    # super-ranges; the three-layer mesh keeps the dense form, which has none
+    assert aligned == (3 if mesh == "film" else 0), aligned
     close(g, T, p)
 
 
