@@ -216,6 +216,9 @@ def batched_section(tmg, W, torch, attempts=60, profile_iters=20):
         m = torch.as_tensor(m32, device="cuda")
         hds[name] = p.demag(m).cpu().numpy()
         rhs_ms, _ = tmg.tm_profile_field(p.handle, B, profile_iters)
+        # inside an attempt every stage but the first reads the right operand
+        # its previous stage wrote (no conversion pass)
+        rhs_chain_ms, _ = tmg.tm_profile_field_mode(p.handle, B, 4, profile_iters)
         # a single layer: the operator is stored without its two zero blocks
         # (5 of the 9 components per block pair; bytes and products alike)
         comps = 5 if np.all(wl.centers[:, 2] == wl.centers[0, 2]) else 9
@@ -231,6 +234,7 @@ def batched_section(tmg, W, torch, attempts=60, profile_iters=20):
         out[name] = {"state_steps_per_s": round(B * attempts / el, 1),
                      "ms_per_step": round(el * 1e3 / attempts, 4),
                      "rhs_us": round(rhs_ms * 1e3, 2),
+                     "rhs_in_attempt_us": round(rhs_chain_ms * 1e3, 2),
                      "mfma_tflops": round(flops / (rhs_ms * 1e-3) / 1e12, 2),
                      "mfma_frac": round(flops / (rhs_ms * 1e-3) / 1e12 / peaks[name], 4),
                      "operator_gbs": round(op_bytes / (rhs_ms * 1e-3) / 1e9, 1),

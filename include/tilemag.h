@@ -344,7 +344,10 @@ tm_status tm_profile_field(tm_problem* p, int64_t B, int32_t iters, hipStream_t 
 /* Same timing for one epilogue variant: mode 0 the stage update (as
  * tm_profile_field), 1 the demag field only, 2 the last Dormand-Prince stage
  * with its float64 error estimate, 3 the operator pass alone (for PSYM6 the
- * tile kernel without the reduction + epilogue launch; otherwise as 0). */
+ * tile kernel without the reduction + epilogue launch; otherwise as 0), 4 the
+ * stage update as inside an attempt, each launch reading the previous one's
+ * output (for the batched DENSE9 product: the right operand the previous
+ * stage wrote, no conversion pass; otherwise as 0). */
 tm_status tm_profile_field_mode(tm_problem* p, int64_t B, int32_t mode, int32_t iters,
                                 hipStream_t stream, double* avg_ms, int64_t* bytes_out);
 

@@ -81,7 +81,8 @@ __device__ inline void epi_load(const float* __restrict__ X, int64_t sx, const E
 // the stepping modes complete their Runge-Kutta stage.
 template <Epi MODE>
 __device__ void epi_compute(const DevProblem& P, int64_t sx, const EpiArgs& E, int s, int a,
-                            const EpiIn& in, float H0, float H1, float H2, double* rmax, double* dmax) {
+                            const EpiIn& in, float H0, float H1, float H2, double* rmax, double* dmax,
+                            float* yn_out = nullptr) {
     const int64_t o = s * sx + 3 * static_cast<int64_t>(a);
     if constexpr (MODE == Epi::HD || MODE == Epi::HEFF) {
         float* out = E.out + s * E.out_stride + 3 * static_cast<int64_t>(a);
@@ -112,6 +113,9 @@ __device__ void epi_compute(const DevProblem& P, int64_t sx, const EpiArgs& E, i
             }
             float* yn = E.ynext + o;
             yn[0] = in.y[0] + h * c0; yn[1] = in.y[1] + h * c1; yn[2] = in.y[2] + h * c2;
+            if (yn_out) {  // the stored values, for a caller that converts them further
+                yn_out[0] = yn[0]; yn_out[1] = yn[1]; yn_out[2] = yn[2];
+            }
             return;
         } else if constexpr (MODE == Epi::RK4_FINAL) {
             const double hd = E.h[s];
@@ -164,13 +168,13 @@ __device__ void epi_compute(const DevProblem& P, int64_t sx, const EpiArgs& E, i
 template <Epi MODE, bool LOCAL = true>
 __device__ void finish_tile(const DevProblem& P, const float* __restrict__ X, int64_t sx,
                             const EpiArgs& E, int s, int a, float hd0, float hd1, float hd2,
-                            double* rmax, double* dmax) {
+                            double* rmax, double* dmax, float* yn_out = nullptr) {
     EpiIn in;
     epi_load<MODE>(X, sx, E, s, a, in);
     float H0 = hd0, H1 = hd1, H2 = hd2;
     if constexpr (LOCAL && MODE != Epi::HD)
         add_local_field(P, X + s * sx, E.Ha, s, a, in.m[0], in.m[1], in.m[2], H0, H1, H2);
-    epi_compute<MODE>(P, sx, E, s, a, in, H0, H1, H2, rmax, dmax);
+    epi_compute<MODE>(P, sx, E, s, a, in, H0, H1, H2, rmax, dmax, yn_out);
 }
 
 

@@ -203,7 +203,7 @@ __device__ inline void static_for(F&& f) {
 // segment's partial sums and clears the accumulators between the two loops
 // (segment B enters its loop at ring slot lenA mod R), without a branch per
 // chunk and without draining the pipeline.
-template <int R, typename LX, typename LA, typename CP, typename SX, typename FL>
+template <int R, bool SEG2, typename LX, typename LA, typename CP, typename SX, typename FL>
 __device__ inline void gemm_run(const GemmWork& W, LX&& load_x, LA&& load_a, CP&& compute, SX&& store_x,
                                 FL&& flush) {
     const int last = W.len - 1;
@@ -212,10 +212,6 @@ __device__ inline void gemm_run(const GemmWork& W, LX&& load_x, LA&& load_a, CP&
         load_x(min(c + 1, last));
         load_a(std::integral_constant<int, (S + R - 1) % R>{}, min(c + R - 1, last));
         compute(slot, c & 1);
-        // the X tile goes to LDS after the products: a store moved up among
-        // them (the four-slot ring's schedule does that) waits for its load
-        // right away
-        __builtin_amdgcn_sched_barrier(0);
         store_x((c + 1) & 1);
         __syncthreads();
     };
@@ -223,13 +219,15 @@ __device__ inline void gemm_run(const GemmWork& W, LX&& load_x, LA&& load_a, CP&
     // per segment), then whole rounds of the ring, then the tail
     auto run = [&](int c0, int c1) {
         int c = c0;
-        static_for<R - 1>([&](auto k) {
-            constexpr int S = decltype(k)::value + 1;
-            if (c < c1 && c % R == S) {
-                step(std::integral_constant<int, S>{}, c);
-                ++c;
-            }
-        });
+        if constexpr (SEG2) {
+            static_for<R - 1>([&](auto k) {
+                constexpr int S = decltype(k)::value + 1;
+                if (c < c1 && c % R == S) {
+                    step(std::integral_constant<int, S>{}, c);
+                    ++c;
+                }
+            });
+        }
         for (; c + R <= c1; c += R) static_for<R>([&](auto k) { step(k, c + decltype(k)::value); });
         static_for<R - 1>([&](auto k) {
             if (c + decltype(k)::value < c1) step(k, c + decltype(k)::value);
@@ -241,7 +239,7 @@ __device__ inline void gemm_run(const GemmWork& W, LX&& load_x, LA&& load_a, CP&
         store_x(0);
         __syncthreads();
     }
-    if (W.lenA < W.len) {
+    if (SEG2 && W.lenA < W.len) {
         run(0, W.lenA);
         flush(W.rbA, W.slotA);
         run(W.lenA, W.len);
@@ -278,7 +276,7 @@ __device__ inline v16f mfma_split(const AV& a, const AV& b, const v16f& c) {
 // its work (gemm_work, gemm_run).  One wave per SIMD (the register file
 // holds R chunks of operator rows); the MFMAs sweep the independent
 // accumulators so that none waits for its predecessor.
-template <int PREC, int NST, int R>
+template <int PREC, int NST, int R, bool SEG2>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_gemm(GemmArgs G) {
     static_assert(PREC == 0, "the split forms use k_gemm_split");
     using T = typename Elt<PREC>::T;
@@ -297,8 +295,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     if (!gemm_work(G, blockIdx.x, &W)) return;
     const T* Ah = static_cast<const T*>(G.Ahi);
     const unsigned char* Xh = static_cast<const unsigned char*>(G.Xhi);
-    auto blk_of = [&](int c) { return c < W.lenA ? W.blkA + c : W.blkB + (c - W.lenA); };
-    auto kc_of = [&](int c) { return c < W.lenA ? W.kcA + c : W.kcB + (c - W.lenA); };
+    // a plan with one segment per item (SEG2 false) addresses without a select
+    auto blk_of = [&](int c) { return !SEG2 || c < W.lenA ? W.blkA + c : W.blkB + (c - W.lenA); };
+    auto kc_of = [&](int c) { return !SEG2 || c < W.lenA ? W.kcA + c : W.kcB + (c - W.lenA); };
 
     v4f acc[2][NST];
     auto zero = [&]() {
@@ -387,7 +386,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         }
         zero();
     };
-    gemm_run<R>(W, load_x, load_a, compute, store_x, flush);
+    gemm_run<R, SEG2>(W, load_x, load_a, compute, store_x, flush);
 }
 
 // The split forms (BF16X3, FP16X3) on 32x32x16 MFMAs: a workgroup (4 waves)
@@ -397,7 +396,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 // each step (16 bytes each, the blocked order: 1 KB per wave load) and the B
 // fragments from the LDS copy of the X chunk; per K step three sweeps
 // (hi hi, hi lo, lo hi) over the NSB independent accumulators.
-template <int PREC, int NSB, int R>
+template <int PREC, int NSB, int R, bool SEG2>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_gemm_split(GemmArgs G) {
     static_assert(PREC == 1 || PREC == 2, "split forms only");
     using T = typename Elt<PREC>::T;
@@ -417,8 +416,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const T* Al = static_cast<const T*>(G.Alo);
     const unsigned char* Xh = static_cast<const unsigned char*>(G.Xhi);
     const unsigned char* Xl = static_cast<const unsigned char*>(G.Xlo);
-    auto blk_of = [&](int c) { return c < W.lenA ? W.blkA + c : W.blkB + (c - W.lenA); };
-    auto kc_of = [&](int c) { return c < W.lenA ? W.kcA + c : W.kcB + (c - W.lenA); };
+    // a plan with one segment per item (SEG2 false) addresses without a select
+    auto blk_of = [&](int c) { return !SEG2 || c < W.lenA ? W.blkA + c : W.blkB + (c - W.lenA); };
+    auto kc_of = [&](int c) { return !SEG2 || c < W.lenA ? W.kcA + c : W.kcB + (c - W.lenA); };
 
     v16f acc[NSB];
     auto zero = [&]() {
@@ -519,7 +519,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         }
         zero();
     };
-    gemm_run<R>(W, load_x, load_a, compute, store_x, flush);
+    gemm_run<R, SEG2>(W, load_x, load_a, compute, store_x, flush);
 }
 
 // Right operand from the (padded) stage input Y [B][ld]: (Ms_b / Ms_ref) m,
@@ -616,27 +616,6 @@ __global__ __launch_bounds__(256) void k_prep(int64_t B, int64_t ns, int64_t ld,
     }
 }
 
-// Right-operand element (state s, column k) of value v in the product's
-// fragment order (the k_prep layout; ns states padded).
-template <int PREC>
-__device__ inline void frag_store(void* xh, void* xl, int64_t ns, int64_t k, int64_t s, float v) {
-    const int64_t kc = k / KC;
-    const int kk = static_cast<int>(k % KC);
-    if constexpr (PREC == 0) {
-        const int64_t nt = ns / 16, st = s / 16;
-        const int j = static_cast<int>(s % 16), sub = kk / 16, g = (kk % 16) / 4, e = kk % 4;
-        static_cast<float*>(xh)[kc * ns * KC + ((sub * nt + st) * 64 + 16 * g + j) * 4 + e] = v;
-    } else {
-        using T = typename Elt<PREC>::T;
-        const int64_t nt = ns / 32, st = s / 32;
-        const int i = static_cast<int>(s % 32), ks = kk / 16, q = (kk % 16) / 8, e = kk % 8;
-        const int64_t o = kc * ns * KC + ((ks * nt + st) * 64 + 32 * q + i) * 8 + e;
-        const T h = static_cast<T>(v);
-        static_cast<T*>(xh)[o] = h;
-        static_cast<T*>(xl)[o] = static_cast<T>(v - static_cast<float>(h));
-    }
-}
-
 // Where a stage writes the right operand of its output (the next stage's
 // input) as well: the fragment arrays, the padded state count and 1 / Ms_ref.
 struct FragOut {
@@ -662,6 +641,7 @@ __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __res
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     rk4_last_stage_control<MODE>(E);
     double rmax = 0.0, dmax = 0.0;
+    float yv[3] = {0.0f, 0.0f, 0.0f};  // the stage output of tile a (STAGE)
     if (a < P.n) {
         const int64_t r0 = cblk ? a : 3 * static_cast<int64_t>(a);
         const int64_t rs = cblk ? P.np : 1;  // row stride between the components
@@ -672,16 +652,57 @@ __global__ __launch_bounds__(256) void k_finish(DevProblem P, const float* __res
             h1 += pp[rs];
             if (sp < splits_z) h2 += pp[2 * rs];
         }
-        finish_tile<MODE>(P, X, sx, E, s, a, -scale * h0, -scale * h1, -scale * h2, &rmax, &dmax);
-        if constexpr (MODE == Epi::STAGE) {
-            if (F.xh) {
-                // this thread's own stores of the stage output, read back
-                const float* yn = E.ynext + static_cast<int64_t>(s) * sx + 3 * static_cast<int64_t>(a);
+        finish_tile<MODE>(P, X, sx, E, s, a, -scale * h0, -scale * h1, -scale * h2, &rmax, &dmax, yv);
+    }
+    if constexpr (MODE == Epi::STAGE) {
+        if (F.xh) {
+            // the workgroup's 256 tiles x 3 components of the stage output
+            // (the values this thread stored, from registers), scaled, through LDS in
+            // column order: component-blocked c 256 + t (column c np + a),
+            // dense 3 t + c (column 3 a + c); then whole fragment pieces (8
+            // consecutive columns of the split forms, 4 of FP32) leave as
+            // 16-byte stores.  Tiles n .. np - 1 are zero, as k_prep makes them.
+            __shared__ float fv[3 * 256];
+            const int tl = threadIdx.x;
+            float v[3] = {0.0f, 0.0f, 0.0f};
+            if (a < P.n) {
                 const float w = P.Ms[a] * F.inv;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const int64_t k = cblk ? c * static_cast<int64_t>(P.np) + a : 3 * static_cast<int64_t>(a) + c;
-                    frag_store<PREC>(F.xh, F.xl, F.ns, k, s, yn[c] * w);
+                for (int c = 0; c < 3; ++c) v[c] = yv[c] * w;
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) fv[cblk ? c * 256 + tl : 3 * tl + c] = v[c];
+            __syncthreads();
+            constexpr int VEC = PREC == 0 ? 4 : 8;
+            const int64_t a0 = static_cast<int64_t>(blockIdx.x) * 256, np = P.np;
+            for (int pc = tl; pc < 3 * 256 / VEC; pc += 256) {
+                const int i0 = VEC * pc;
+                const int64_t k0 = cblk ? (i0 / 256) * np + a0 + i0 % 256 : 3 * a0 + i0;
+                if (cblk ? a0 + i0 % 256 >= np : k0 >= 3 * np) continue;
+                const int64_t kc = k0 / KC;
+                const int kk = static_cast<int>(k0 % KC);
+                if constexpr (PREC == 0) {
+                    const int64_t nt = F.ns / 16, st = s / 16;
+                    const int j = s % 16, sub = kk / 16, g = (kk % 16) / 4;
+                    *reinterpret_cast<float4*>(static_cast<float*>(F.xh) + kc * F.ns * KC +
+                                               ((sub * nt + st) * 64 + 16 * g + j) * 4) =
+                        make_float4(fv[i0], fv[i0 + 1], fv[i0 + 2], fv[i0 + 3]);
+                } else {
+                    using T = typename Elt<PREC>::T;
+                    using AV = typename Elt<PREC>::V;
+                    const int64_t nt = F.ns / 32, st = s / 32;
+                    const int i = s % 32, ks = kk / 16, q = (kk % 16) / 8;
+                    AV hi, lo;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const float x = fv[i0 + e];
+                        const T hv = static_cast<T>(x);
+                        hi[e] = hv;
+                        lo[e] = static_cast<T>(x - static_cast<float>(hv));
+                    }
+                    const int64_t o = kc * F.ns * KC + ((ks * nt + st) * 64 + 32 * q + i) * 8;
+                    *reinterpret_cast<AV*>(static_cast<T*>(F.xh) + o) = hi;
+                    *reinterpret_cast<AV*>(static_cast<T*>(F.xl) + o) = lo;
                 }
             }
         }
@@ -714,18 +735,26 @@ inline unsigned gemm_items(const GemmArgs& G) {
     return static_cast<unsigned>((total + kXcds - 1) / kXcds * kXcds);
 }
 
+// the aligned plan's items have two segments (SEG2), the split plan's one
 template <int PREC, int NST, int R>
 void launch_gemm_fp32(const GemmArgs& G, hipStream_t s) {
-    launch_op(k_gemm<PREC, NST, R>, dim3(gemm_items(G)), dim3(256), s, G);
+    if (G.nq) launch_op(k_gemm<PREC, NST, R, true>, dim3(gemm_items(G)), dim3(256), s, G);
+    else launch_op(k_gemm<PREC, NST, R, false>, dim3(gemm_items(G)), dim3(256), s, G);
+}
+
+template <int PREC, int NSB, int R>
+void launch_split_t(const GemmArgs& G, dim3 grid, hipStream_t s) {
+    if (G.nq) launch_op(k_gemm_split<PREC, NSB, R, true>, grid, dim3(256), s, G);
+    else launch_op(k_gemm_split<PREC, NSB, R, false>, grid, dim3(256), s, G);
 }
 
 template <int PREC, int R>
 tm_status launch_gemm_split(int nsb, const GemmArgs& G, hipStream_t s) {
     const dim3 grid(gemm_items(G));
     switch (nsb) {
-        case 1: launch_op(k_gemm_split<PREC, 1, R>, grid, dim3(256), s, G); break;
-        case 2: launch_op(k_gemm_split<PREC, 2, R>, grid, dim3(256), s, G); break;
-        case 4: launch_op(k_gemm_split<PREC, 4, R>, grid, dim3(256), s, G); break;
+        case 1: launch_split_t<PREC, 1, R>(G, grid, s); break;
+        case 2: launch_split_t<PREC, 2, R>(G, grid, s); break;
+        case 4: launch_split_t<PREC, 4, R>(G, grid, s); break;
         default:
             set_error("batched product: unsupported 32-state tile count %d", nsb);
             return TM_EINVAL;

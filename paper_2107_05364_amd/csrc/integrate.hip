@@ -549,6 +549,11 @@ tm_status time_field(Problem* p, int64_t B, int mode, int32_t iters, hipStream_t
         ep = Epi::STAGE;
         X = w->ya;
     }
+    // mode 4: stage launches as inside an attempt, each reading the previous
+    // one's output (ya -> yb -> ya ...), so that the batched product takes
+    // the right operand its previous stage wrote
+    const EpiArgs e_back = mode == 4 ? stage_args(w, w->k[2], kp, 1, c, w->ya) : e;
+    int parity = 0;
     // stages of a state with h = 0 are skipped: give every state a step
     k_fill<<<static_cast<unsigned>((B + 255) / 256), 256, 0, s>>>(w->h, B, 1e-15);
     TM_TRY_HIP(hipGetLastError());
@@ -559,7 +564,12 @@ tm_status time_field(Problem* p, int64_t B, int mode, int32_t iters, hipStream_t
     // launch (the pair-symmetric tile pass); otherwise the whole evaluation
     const bool tiles_only = mode == 3 && is_psym(p->T->layout);
     auto one = [&]() {
-        return tiles_only ? launch_psym_tiles(p, B, X, w->h, w->Ha, s) : launch_field(p, ep, B, X, e, s);
+        if (tiles_only) return launch_psym_tiles(p, B, X, w->h, w->Ha, s);
+        if (mode != 4) return launch_field(p, ep, B, X, e, s);
+        // the first launch converts its input; every later one reads the copy
+        w->frag_chain = parity > 0;
+        const bool fwd = parity++ % 2 == 0;
+        return launch_field(p, ep, B, fwd ? w->ya : w->yb, fwd ? e : e_back, s);
     };
     tm_status st = one();  // untimed first launch
     if (st == TM_OK && hipEventRecord(e0, s) != hipSuccess) st = TM_EDEVICE;
@@ -582,7 +592,7 @@ tm_status time_field(Problem* p, int64_t B, int mode, int32_t iters, hipStream_t
 extern "C" tm_status tm_profile_field_mode(tm_problem* pp, int64_t B, int32_t mode, int32_t iters,
                                            hipStream_t s, double* avg_ms, int64_t* bytes_out) {
     Problem* p = reinterpret_cast<Problem*>(pp);
-    TM_REQUIRE(p && avg_ms && B >= 1 && iters >= 1 && mode >= 0 && mode <= 3, TM_EINVAL,
+    TM_REQUIRE(p && avg_ms && B >= 1 && iters >= 1 && mode >= 0 && mode <= 4, TM_EINVAL,
                "tm_profile_field: bad arguments");
     TM_TRY_HIP(hipSetDevice(p->ctx->device));
     tm_status st = ensure_workspace(p, B);

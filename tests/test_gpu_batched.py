@@ -207,3 +207,17 @@ def test_split_precision_hysteresis_run(tmg, ctx, prec):
     _say("split vs fp32 hysteresis run, 10 ps: max|dm| %.2e" % d)
     assert d <= 1e-3
     close(g1, T1, p1, g2, T2, p2)
+
+
+def test_profile_modes_run(tmg, ctx):
+    """The field-timing modes on a batched problem: the stand-alone stage
+    update (0) and the stage updates as inside an attempt (4, reading the
+    right operand the previous stage wrote) both time; 5 is refused."""
+    wl = W.hysteresis_batch(B=8, nx=40, ny=10)
+    g, T, p = build(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha, store=1, layout=tmg.TM_LAYOUT_DENSE9)
+    for mode in (0, 4):
+        ms, nbytes = tmg.tm_profile_field_mode(p.handle, 8, mode, 3)
+        assert ms > 0 and nbytes > 0, (mode, ms, nbytes)
+    with pytest.raises(tmg.TilemagError):
+        tmg.tm_profile_field_mode(p.handle, 8, 5, 3)
+    close(g, T, p)
