@@ -16,18 +16,20 @@
 //            the scale is removed in the GEMM epilogue.
 //
 // Work split: a workgroup (4 waves) owns 128 operator rows x all states and
-// one K range (split-K); each wave owns 32 rows (two 16-row MFMA tiles in
-// FP32, one 32-row tile in the split forms).  K advances in chunks of 64.
-// The operator is stored blocked (dense9_index): one workgroup's rows of one
-// chunk are a contiguous 16 KB (16-bit halves, each) or 32 KB (float32)
-// span, read straight into registers, 1 KB per wave load.  The right
-// operand is written by k_prep in the same fragment order, one contiguous
-// span per chunk, staged once per workgroup in LDS (a plain copy: every LDS
+// one K range (split-K), or, in the aligned plan of a single layer, one or
+// two such segments (gemm_work); each wave owns 32 rows (two 16-row MFMA
+// tiles in FP32, one 32-row tile in the split forms).  K advances in chunks
+// of 64.  The operator is stored blocked (dense9_index): one workgroup's rows
+// of one chunk are a contiguous 16 KB (16-bit halves, each) or 32 KB
+// (float32) span, read straight into registers, 1 KB per wave load.  The
+// right operand is in the same fragment order, one contiguous span per
+// chunk, written by k_prep or, inside an attempt, by the previous stage's
+// k_finish; it is staged once per workgroup in LDS (a plain copy: every LDS
 // access is a contiguous 1 KB per wave, free of bank conflicts) and reused
-// by the four waves.  Partial sums go to part[split][state][row]
-// and a fixed-order elementwise pass adds the splits, finishes the effective
-// field and the Runge-Kutta stage per tile.  The summation order depends only
-// on the problem size, never on the batch.
+// by the four waves.  Partial sums go to part[slot][state][row] and a
+// fixed-order elementwise pass adds the slots, finishes the effective field
+// and the Runge-Kutta stage per tile.  The summation order depends only on
+// the problem size and the work plan, never on the batch.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
