@@ -168,15 +168,21 @@ def test_every_split_count(tmg, ctx, orc, prec, mesh):
     close(g, T, p)
 
 
-def test_batched_dp45_matches_matvec_path(tmg, ctx):
+@pytest.mark.parametrize("plan", [0, 102])
+def test_batched_dp45_matches_matvec_path(tmg, ctx, plan):
     """DP45 on 8 states to a common end time: the FP32 GEMM path and the FP32
     matvec path (different summation orders) agree within the float32
-    resolution of the tolerance-1e-6 integration."""
+    resolution of the tolerance-1e-6 integration.  The stages inside an
+    attempt read the right operand their previous stage wrote; plan 102 (the
+    aligned plan with two K super-ranges: items of two z row blocks) runs it
+    through the two-segment product."""
     import torch
 
     wl = W.hysteresis_batch(B=8, nx=40, ny=10)
     Ha = torch.as_tensor(wl.Ha.astype(np.float32), device="cuda")
     ga, Ta, pa = build(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha, layout=tmg.TM_LAYOUT_DENSE9)
+    if plan:
+        tmg.tm_problem_apply(pa.handle, plan)
     gb, Tb, pb = build(tmg, ctx, wl.centers, wl.sizes, alpha=wl.alpha)
     ma, mb = device_state(wl.m0), device_state(wl.m0)
     ta, _, sa, _ = pa.run(ma, Ha, tmg.TM_DP45, dt=1e-14, max_steps=1 << 20, t_end=20e-12)
