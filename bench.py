@@ -646,9 +646,9 @@ def sp3_section(tmg, W, torch, ns=(4, 6, 8, 10, 12, 16, 20)):
 
 
 def peaks_section(torch, tmg):
-    """Achievable rates on this device for context: the library's own stream
-    read (2 GiB) and register-only MFMA loops, a 4 GiB device copy (read +
-    write bytes) and library GEMMs (torch.mm) in bf16 and fp32."""
+    """Probe rates on this device for context (not ceilings): the library's
+    own stream read (2 GiB) and register-only MFMA loops, a 4 GiB device copy
+    (read + write bytes) and library GEMMs (torch.mm) in bf16 and fp32."""
     out = {}
     rd, mb, mf = tmg.tm_measure_peaks(0, 2 << 30)
     out["stream_read_gbs"] = round(rd, 1)
@@ -932,8 +932,10 @@ def main():
         rec["serving"] = serving_section(tmg, W, torch, count=args.serving_count, n_max=args.serving_nmax,
                                          max_active=args.serving_max_active)
     if not args.no_peaks:
-        progress("achievable peaks")
-        rec["achievable_peaks"] = peaks_section(torch, tmg)
+        progress("probe rates")
+        # context: what plain probes reach on this machine (not ceilings: the
+        # slab's stage kernel streams at or above the read probe)
+        rec["probe_rates"] = peaks_section(torch, tmg)
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle)")
         base, errs = cpu_baseline(wl, args.cpu_steps, m_final, hd_final, batched_data)

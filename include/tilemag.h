@@ -93,8 +93,9 @@ const char* tm_last_error(void);
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t tm_version(void);
 
-/* Achievable rates of device `device`, measured with the library's own
- * kernels (context for the roofline fractions, which use published peaks):
+/* Probe rates of device `device`, measured with the library's own kernels
+ * (context for the roofline fractions, which use published peaks; not
+ * ceilings: a well-shaped kernel can stream faster than the read probe):
  * a streaming read of a zero-filled read_bytes buffer (1 MiB .. 16 GiB,
  * rounded down to whole 64 KiB chunks; allocated and freed by the call) in
  * GB/s, the fastest of: one workgroup per chunk as the pair-symmetric tile
